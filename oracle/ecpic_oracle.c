@@ -1,0 +1,1217 @@
+/*
+ * ecpic_oracle.c -- plain serial FP64 CPU oracle.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load this file.  The product path (the HIP library) never calls
+ * it, includes it, or shares any code, table or constant with it.
+ *
+ * What it computes is the time step of the energy-conserving, unstaggered,
+ * Lorenz-gauge potential PIC method of Christlieb, Chacon and Gong,
+ * "An Energy-Conserving Unstaggered Electromagnetic-Potential Particle-in-Cell
+ * Method, Part I":
+ *
+ *   shapes      B-spline particle shapes S_g on a collocated periodic mesh
+ *               (Sec. 2.3, eq. Ah-mesh)
+ *   orbit       straight unwrapped orbit and knot-crossing breakpoints
+ *               (Sec. 4.2 eq. particle-orbit; Sec. 4.7 eq. breakpoint-set)
+ *   weights     split orbit integrals S-bar and D (eqs. split-Sbar, split-DA):
+ *               closed forms of App. A / App. B for degree 1, Gauss-Legendre
+ *               per segment otherwise (Sec. 4.7, 2 n_q - 1 >= 3 r)
+ *   deposit     orbit current (eq. orbit-current)
+ *   fields      continuity update (eq. cn-continuity) and Crank-Nicolson
+ *               potential update (eq. cn-field-update) with Fourier symbols
+ *               (Sec. 3.3), evaluated with a plain separable DFT
+ *   push        orbit-discrete-gradient canonical-momentum push (eq. orbit-push)
+ *   step        Picard iteration of Algorithm 1
+ *   diagnostics K, W (eqs. particle-energy, field-energy), R_field, R_particle,
+ *               R_total (Sec. 5.3), gauge/Gauss residuals (Sec. 5.1),
+ *               chain-rule residual R_A (Sec. 5.2)
+ *
+ * Everything is double precision, no blocking or fusion: one particle at a
+ * time, one segment at a time, one stencil node at a time.
+ *
+ * Readings where the paper leaves a choice open (each listed in the design
+ * notes of the repository):
+ *   - every field and both spline degrees live on nodes x_g = g H; degree 1
+ *     uses the cell floor(x/H), degree 2 the nearest node floor(x/H + 1/2);
+ *   - the first-derivative Fourier symbol is zero on the Nyquist index and the
+ *     Laplacian symbol is -|k~|^2 with that same k~ (keeps curl curl =
+ *     grad div - Laplacian exact);
+ *   - the stencil of a split segment is the one of its midpoint;
+ *   - the initial charge is also zeroed on every mode where k~ = 0;
+ *   - v^{n-1} := v^0 at the first step;
+ *   - Picard errors: e_v = max|v^{p+1}-v^p| / max|v^{p+1}|,
+ *     e_J = max|J^p - J^{p-1}| / J_s with J_s = sum_i |q_i| max_a|vbar_ia| / |Omega|;
+ *     at most p_max + 1 iterations, stop only for p >= 1;
+ *   - diagnostics of a step use the accepted iterate's orbit, current and fields.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------------- */
+/* configuration and state                                                   */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t n[3];      /* mesh points per axis */
+  double L[3];       /* periodic box lengths */
+  double kappa;      /* nondimensional speed of light */
+  double sigma1;     /* source coefficient of the phi equation */
+  double sigma2;     /* source coefficient of the A equation */
+  double dt;
+  int32_t r;         /* spline degree: 1 or 2 */
+  int32_t split;     /* 1: split every orbit integral at crossed knots; 0: one rule over [0,1] */
+  int32_t nq;        /* Gauss points per segment, 0: smallest exact rule (2 nq - 1 >= 3 r) */
+  int32_t analytic;  /* degree 1 with splitting: 1 = App. A/B closed forms, 0 = Gauss */
+  double tol;        /* Picard tolerance */
+  int32_t pmax;      /* Picard iterations p = 0..pmax */
+} orc_cfg;
+
+typedef struct {
+  int32_t iters;
+  int32_t converged;
+  double err_v, err_J;
+} orc_step_info;
+
+typedef struct {
+  double K, W, E_total;
+  double R_field, R_particle, R_total;
+  double gauge_max, gauge_l2, gauss_max, gauss_l2;
+  double RA_rms, RA_max, pou_max;
+  double JE_mesh;       /* sum_g J.E^{n+1/2} dV of the accepted iterate */
+  double work_particle; /* sum_i q vbar.Ebar of the accepted iterate */
+  int64_t step;
+} orc_energy;
+
+typedef struct {
+  int n[3];
+  double L[3], H[3], dV, vol;
+  int64_t ncell;
+} grid;
+
+typedef struct {
+  orc_cfg c;
+  grid G;
+  int nq;
+  double gx[64], gw[64];     /* Gauss-Legendre nodes/weights on [-1, 1] */
+  int64_t np;
+  double q, m;
+  double *x, *v, *vprev, *P; /* 3*np each, component-major: x[a*np + i] */
+  cplx *phi, *psi, *A, *U, *rho; /* Fourier state, A and U hold 3 components */
+  double *J;                 /* real-space current of the accepted iterate (3*ncell) */
+  orc_energy en;
+  double K0, W0;
+  int have_energy;
+} orc_sim;
+
+/* ------------------------------------------------------------------------- */
+/* small helpers                                                             */
+/* ------------------------------------------------------------------------- */
+
+static void make_grid(const orc_cfg* c, grid* G) {
+  G->ncell = 1;
+  for (int a = 0; a < 3; ++a) {
+    G->n[a] = c->n[a];
+    G->L[a] = c->L[a];
+    G->H[a] = c->L[a] / c->n[a];
+    G->ncell *= c->n[a];
+  }
+  G->dV = G->H[0] * G->H[1] * G->H[2];
+  G->vol = G->L[0] * G->L[1] * G->L[2];
+}
+
+static long wrap_index(long i, int n) {
+  long r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+static int64_t node_id(const grid* G, long ix, long iy, long iz) {
+  return ((int64_t)wrap_index(ix, G->n[0]) * G->n[1] + wrap_index(iy, G->n[1])) * G->n[2] +
+         wrap_index(iz, G->n[2]);
+}
+
+/* position wrapped into the periodic box (used only where a point shape is
+   evaluated at the end of an orbit, and when a step is accepted) */
+static double wrap_pos(double x, double L) {
+  double w = x - L * floor(x / L);
+  if (w < 0) w += L;
+  if (w >= L) w -= L;
+  return w;
+}
+
+/* Gauss-Legendre rule on [-1,1]: Newton iteration on the Legendre polynomial
+   P_n, evaluated by the three-term recurrence (k+1)P_{k+1} = (2k+1) x P_k - k P_{k-1}. */
+static void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-17) break;
+    }
+    /* recompute the derivative at the converged node */
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+    }
+    x[i] = -z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* B-spline shapes (Sec. 2.3; degree r centred B-spline per axis)            */
+/* ------------------------------------------------------------------------- */
+
+/* index of the node the local polynomial pieces are written against:
+   degree 1 -> the cell's left node floor(u); degree 2 -> nearest node */
+static long spline_base(int r, double u) { return r == 1 ? (long)floor(u) : (long)floor(u + 0.5); }
+
+/* first stencil node relative to the base */
+static long spline_first(int r, long base) { return r == 1 ? base : base - 1; }
+
+/* weights w[o] and derivatives dw[o] (per unit of u) of the stencil nodes
+   first+o, for local coordinate t = u - base.  Degree 1: M1(xi) = 1 - |xi|.
+   Degree 2: M2(xi) = 3/4 - xi^2 (|xi| <= 1/2), (3/2 - |xi|)^2 / 2 (1/2 <= |xi| <= 3/2). */
+static void spline_pieces(int r, double t, double* w, double* dw) {
+  if (r == 1) {
+    w[0] = 1.0 - t;  /* node base,   xi = t     */
+    w[1] = t;        /* node base+1, xi = t - 1 */
+    dw[0] = -1.0;
+    dw[1] = 1.0;
+  } else {
+    w[0] = 0.5 * (0.5 - t) * (0.5 - t); /* node base-1, xi = t + 1 */
+    w[1] = 0.75 - t * t;                /* node base,   xi = t     */
+    w[2] = 0.5 * (0.5 + t) * (0.5 + t); /* node base+1, xi = t - 1 */
+    dw[0] = -(0.5 - t);
+    dw[1] = -2.0 * t;
+    dw[2] = 0.5 + t;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* orbit segments (Sec. 4.7, eq. breakpoint-set)                             */
+/* ------------------------------------------------------------------------- */
+
+static int cmp_double(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+#define MAX_BREAKS 512
+
+/* sorted, de-duplicated breakpoints 0 = s_0 < ... < s_M = 1 of the orbit
+   x(s) = x0 + s d.  Knots sit at k H (degree 1) and (k + 1/2) H (degree 2).
+   Returns the number of breakpoints, or -1 if the orbit is absurdly long. */
+static int orbit_breakpoints(const grid* G, int r, const double x0[3], const double d[3],
+                             double* s) {
+  int ns = 0;
+  s[ns++] = 0.0;
+  s[ns++] = 1.0;
+  double off = (r == 1) ? 0.0 : 0.5;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] == 0.0) continue; /* no breakpoints from a coordinate that does not move */
+    double H = G->H[a];
+    double u0 = x0[a] / H, u1 = (x0[a] + d[a]) / H;
+    long klo = (long)floor(fmin(u0, u1) - off) - 1;
+    long khi = (long)floor(fmax(u0, u1) - off) + 1;
+    for (long k = klo; k <= khi; ++k) {
+      double xi = ((double)k + off) * H;
+      double sk = (xi - x0[a]) / d[a];
+      if (sk > 0.0 && sk < 1.0) {
+        if (ns >= MAX_BREAKS) return -1;
+        s[ns++] = sk;
+      }
+    }
+  }
+  qsort(s, ns, sizeof(double), cmp_double);
+  int m = 1;
+  for (int i = 1; i < ns; ++i)
+    if (s[i] != s[m - 1]) s[m++] = s[i];
+  return m;
+}
+
+/* Integrals of one orbit piece against its stencil (at most 3x3x3 nodes):
+     Iw[nu]   = int S_nu(x(s)) ds
+     X[j][nu] = int d_j S_nu(x(s)) ds
+     Y[j][nu] = int (s - s0) d_j S_nu(x(s)) ds
+   so that, with A_g(s) = A^(m) + C (s - s0) (App. B),
+     int A_g(s) d_j S_g ds = A^(m) X + C Y. */
+typedef struct {
+  long first[3];
+  int w; /* stencil width r + 1 */
+  double s0;
+  double Iw[27];
+  double X[3][27];
+  double Y[3][27];
+} piece;
+
+static int pidx(int w, int i, int j, int k) { return (i * w + j) * w + k; }
+
+/* App. A and App. B closed forms for degree 1 on the segment [s0, s1] */
+static void piece_r1_analytic(const grid* G, const double x0[3], const double d[3], double s0,
+                              double s1, piece* o) {
+  double h = s1 - s0;
+  double smid = 0.5 * (s0 + s1);
+  double lam[3][2], mu[3][2];
+  o->w = 2;
+  o->s0 = s0;
+  for (int a = 0; a < 3; ++a) {
+    double H = G->H[a];
+    long base = spline_base(1, (x0[a] + smid * d[a]) / H);
+    o->first[a] = spline_first(1, base);
+    double rm = (x0[a] + s0 * d[a]) / H - (double)base; /* r_{alpha,m} */
+    double beta = d[a] / H;                             /* beta_alpha  */
+    lam[a][0] = 1.0 - rm;
+    mu[a][0] = -beta;
+    lam[a][1] = rm;
+    mu[a][1] = beta;
+  }
+  double h2 = h * h, h3 = h2 * h, h4 = h3 * h;
+  for (int nx = 0; nx < 2; ++nx)
+    for (int ny = 0; ny < 2; ++ny)
+      for (int nz = 0; nz < 2; ++nz) {
+        int nu[3] = {nx, ny, nz};
+        double Lc[3], Mc[3];
+        for (int a = 0; a < 3; ++a) {
+          Lc[a] = lam[a][nu[a]];
+          Mc[a] = mu[a][nu[a]];
+        }
+        int id = pidx(2, nx, ny, nz);
+        double c0 = Lc[0] * Lc[1] * Lc[2];
+        double c1 = Mc[0] * Lc[1] * Lc[2] + Lc[0] * Mc[1] * Lc[2] + Lc[0] * Lc[1] * Mc[2];
+        double c2 = Mc[0] * Mc[1] * Lc[2] + Mc[0] * Lc[1] * Mc[2] + Lc[0] * Mc[1] * Mc[2];
+        double c3 = Mc[0] * Mc[1] * Mc[2];
+        o->Iw[id] = c0 * h + c1 / 2.0 * h2 + c2 / 3.0 * h3 + c3 / 4.0 * h4;
+        for (int j = 0; j < 3; ++j) {
+          int p = (j + 1) % 3, q = (j + 2) % 3;
+          double sig = nu[j] ? 1.0 : -1.0;
+          double d0 = Lc[p] * Lc[q];
+          double d1 = Mc[p] * Lc[q] + Lc[p] * Mc[q];
+          double d2 = Mc[p] * Mc[q];
+          o->X[j][id] = sig / G->H[j] * (d0 * h + d1 / 2.0 * h2 + d2 / 3.0 * h3);
+          o->Y[j][id] = sig / G->H[j] * (d0 / 2.0 * h2 + d1 / 3.0 * h3 + d2 / 4.0 * h4);
+        }
+      }
+}
+
+/* Empty piece against the polynomial pieces of the given base nodes,
+   with A_g(s) written relative to s0. */
+static void piece_init(int r, const long base[3], double s0, piece* o) {
+  o->w = r + 1;
+  o->s0 = s0;
+  for (int a = 0; a < 3; ++a) o->first[a] = spline_first(r, base[a]);
+  memset(o->Iw, 0, sizeof(o->Iw));
+  memset(o->X, 0, sizeof(o->X));
+  memset(o->Y, 0, sizeof(o->Y));
+}
+
+/* add one quadrature point s with weight wt to a piece */
+static void piece_add_point(const grid* G, int r, const double x0[3], const double d[3], double s,
+                            double wt, const long base[3], piece* o) {
+  int w = r + 1;
+  double eta = s - o->s0;
+  double wv[3][3], dwv[3][3];
+  for (int a = 0; a < 3; ++a) {
+    double u = (x0[a] + s * d[a]) / G->H[a];
+    spline_pieces(r, u - (double)base[a], wv[a], dwv[a]);
+    for (int o2 = 0; o2 < w; ++o2) dwv[a][o2] /= G->H[a];
+  }
+  for (int i = 0; i < w; ++i)
+    for (int j = 0; j < w; ++j)
+      for (int k = 0; k < w; ++k) {
+        int id = pidx(w, i, j, k);
+        double S = wv[0][i] * wv[1][j] * wv[2][k];
+        double dS[3] = {dwv[0][i] * wv[1][j] * wv[2][k], wv[0][i] * dwv[1][j] * wv[2][k],
+                        wv[0][i] * wv[1][j] * dwv[2][k]};
+        o->Iw[id] += wt * S;
+        for (int jj = 0; jj < 3; ++jj) {
+          o->X[jj][id] += wt * dS[jj];
+          o->Y[jj][id] += wt * eta * dS[jj];
+        }
+      }
+}
+
+/* Gauss-Legendre rule (nodes gx, weights gw on [-1,1]) mapped to [s0, s1]
+   and evaluated against the polynomial pieces of the given base nodes. */
+static void piece_gauss(const grid* G, int r, const double x0[3], const double d[3], double s0,
+                        double s1, const long base[3], int nq, const double* gx,
+                        const double* gw, piece* o) {
+  double h = s1 - s0;
+  piece_init(r, base, s0, o);
+  for (int iq = 0; iq < nq; ++iq)
+    piece_add_point(G, r, x0, d, s0 + 0.5 * h * (1.0 + gx[iq]), 0.5 * h * gw[iq], base, o);
+}
+
+/* All pieces of one orbit.  With splitting: one piece per segment, its stencil
+   taken at the segment midpoint.  Without splitting: the n_q-point rule over
+   [0,1], each quadrature point with the stencil of its own cell (one piece per
+   point, written relative to s = 0).  Returns the number of pieces (or -1). */
+static int orbit_pieces(const orc_sim* S, const double x0[3], const double d[3], piece* out,
+                        int cap) {
+  const grid* G = &S->G;
+  int r = S->c.r;
+  if (!S->c.split) {
+    if (S->nq > cap) return -1;
+    for (int iq = 0; iq < S->nq; ++iq) {
+      double sq = 0.5 * (1.0 + S->gx[iq]);
+      long base[3];
+      for (int a = 0; a < 3; ++a) base[a] = spline_base(r, (x0[a] + sq * d[a]) / G->H[a]);
+      piece_init(r, base, 0.0, &out[iq]);
+      piece_add_point(G, r, x0, d, sq, 0.5 * S->gw[iq], base, &out[iq]);
+    }
+    return S->nq;
+  }
+  double s[MAX_BREAKS];
+  int nb = orbit_breakpoints(G, r, x0, d, s);
+  if (nb < 0) return -1;
+  int n = 0;
+  for (int m = 0; m + 1 < nb; ++m) {
+    double s0 = s[m], s1 = s[m + 1];
+    if (!(s1 > s0)) continue; /* zero-length pieces contribute nothing */
+    if (n >= cap) return -1;
+    if (r == 1 && S->c.analytic) {
+      piece_r1_analytic(G, x0, d, s0, s1, &out[n]);
+    } else {
+      double smid = 0.5 * (s0 + s1);
+      long base[3];
+      for (int a = 0; a < 3; ++a) base[a] = spline_base(r, (x0[a] + smid * d[a]) / G->H[a]);
+      piece_gauss(G, r, x0, d, s0, s1, base, S->nq, S->gx, S->gw, &out[n]);
+    }
+    ++n;
+  }
+  return n;
+}
+
+/* ------------------------------------------------------------------------- */
+/* particle <-> mesh maps                                                    */
+/* ------------------------------------------------------------------------- */
+
+/* point interpolant F_h(x) = sum_g F_g S_g(x) (eq. Ah-mesh), x wrapped first */
+static void interp_point(const grid* G, int r, const double xin[3], const double* F, int ncomp,
+                         double* out) {
+  int w = r + 1;
+  double wv[3][3], dwv[3][3];
+  long first[3];
+  for (int a = 0; a < 3; ++a) {
+    double x = wrap_pos(xin[a], G->L[a]);
+    double u = x / G->H[a];
+    long base = spline_base(r, u);
+    first[a] = spline_first(r, base);
+    spline_pieces(r, u - (double)base, wv[a], dwv[a]);
+  }
+  for (int l = 0; l < ncomp; ++l) out[l] = 0.0;
+  for (int i = 0; i < w; ++i)
+    for (int j = 0; j < w; ++j)
+      for (int k = 0; k < w; ++k) {
+        int64_t g = node_id(G, first[0] + i, first[1] + j, first[2] + k);
+        double Sv = wv[0][i] * wv[1][j] * wv[2][k];
+        for (int l = 0; l < ncomp; ++l) out[l] += F[(int64_t)l * G->ncell + g] * Sv;
+      }
+}
+
+#define MAX_PIECES 600
+
+/* orbit current of one particle: J_g += q vbar Sbar_g / dV (eq. orbit-current) */
+static int deposit_one(const orc_sim* S, const double x0[3], const double d[3], const double qv[3],
+                       double* J, piece* buf) {
+  const grid* G = &S->G;
+  int np = orbit_pieces(S, x0, d, buf, MAX_PIECES);
+  if (np < 0) return -1;
+  for (int m = 0; m < np; ++m) {
+    const piece* o = &buf[m];
+    int w = o->w;
+    for (int i = 0; i < w; ++i)
+      for (int j = 0; j < w; ++j)
+        for (int k = 0; k < w; ++k) {
+          int64_t g = node_id(G, o->first[0] + i, o->first[1] + j, o->first[2] + k);
+          double Ig = o->Iw[pidx(w, i, j, k)];
+          for (int l = 0; l < 3; ++l) J[(int64_t)l * G->ncell + g] += qv[l] * Ig / G->dV;
+        }
+  }
+  return 0;
+}
+
+/* orbit gather of one particle (eqs. orbit-gather-general, Ubar-def, DA-def):
+   gphibar_l = sum_g (grad_h phi)_lg Sbar_g, Ubar_l = sum_g U_lg Sbar_g,
+   D_lj = sum_g int A_lg(s) d_j S_g(x(s)) ds with A_g(s) = (1-s) A^n + s A^{n+1},
+   pou = sum_g Sbar_g. */
+static int gather_one(const orc_sim* S, const double x0[3], const double d[3], const double* gphi,
+                      const double* Uh, const double* A0, const double* A1, double gphibar[3],
+                      double Ubar[3], double D[3][3], double* pou, piece* buf) {
+  const grid* G = &S->G;
+  int np = orbit_pieces(S, x0, d, buf, MAX_PIECES);
+  if (np < 0) return -1;
+  for (int l = 0; l < 3; ++l) {
+    gphibar[l] = 0.0;
+    Ubar[l] = 0.0;
+    for (int j = 0; j < 3; ++j) D[l][j] = 0.0;
+  }
+  *pou = 0.0;
+  for (int m = 0; m < np; ++m) {
+    const piece* o = &buf[m];
+    int w = o->w;
+    double sm = o->s0;
+    for (int i = 0; i < w; ++i)
+      for (int j = 0; j < w; ++j)
+        for (int k = 0; k < w; ++k) {
+          int64_t g = node_id(G, o->first[0] + i, o->first[1] + j, o->first[2] + k);
+          int id = pidx(w, i, j, k);
+          double Ig = o->Iw[id];
+          *pou += Ig;
+          for (int l = 0; l < 3; ++l) {
+            int64_t lg = (int64_t)l * G->ncell + g;
+            gphibar[l] += gphi[lg] * Ig;
+            Ubar[l] += Uh[lg] * Ig;
+            double Am = (1.0 - sm) * A0[lg] + sm * A1[lg]; /* A^(m): global s_m (App. B) */
+            double C = A1[lg] - A0[lg];
+            for (int jj = 0; jj < 3; ++jj) D[l][jj] += Am * o->X[jj][id] + C * o->Y[jj][id];
+          }
+        }
+  }
+  return 0;
+}
+
+/* point-shape charge deposit rho_g = sum_i q S_g(x_i) / dV (eq. source-moments) */
+static void deposit_point_charge(const grid* G, int r, int64_t np, const double* x, double q,
+                                 double* rho) {
+  int w = r + 1;
+  for (int64_t i = 0; i < np; ++i) {
+    double wv[3][3], dwv[3][3];
+    long first[3];
+    for (int a = 0; a < 3; ++a) {
+      double xa = wrap_pos(x[(int64_t)a * np + i], G->L[a]);
+      double u = xa / G->H[a];
+      long base = spline_base(r, u);
+      first[a] = spline_first(r, base);
+      spline_pieces(r, u - (double)base, wv[a], dwv[a]);
+    }
+    for (int ii = 0; ii < w; ++ii)
+      for (int jj = 0; jj < w; ++jj)
+        for (int kk = 0; kk < w; ++kk) {
+          int64_t g = node_id(G, first[0] + ii, first[1] + jj, first[2] + kk);
+          rho[g] += q * wv[0][ii] * wv[1][jj] * wv[2][kk] / G->dV;
+        }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Fourier operators (Sec. 3.3): plain separable DFT                         */
+/* ------------------------------------------------------------------------- */
+
+/* f^_k = sum_j f_j exp(sign 2 pi i j k / N) along one axis of the 3D array */
+static void dft_axis(const grid* G, cplx* f, int axis, int sign) {
+  int N = G->n[axis];
+  int64_t stride = 1;
+  for (int a = axis + 1; a < 3; ++a) stride *= G->n[a];
+  int64_t outer = 1;
+  for (int a = 0; a < axis; ++a) outer *= G->n[a];
+  cplx* tw = (cplx*)malloc(sizeof(cplx) * N);
+  cplx* tmp = (cplx*)malloc(sizeof(cplx) * N);
+  for (int t = 0; t < N; ++t) {
+    double ang = 2.0 * M_PI * (double)t / (double)N;
+    tw[t] = cos(ang) + (double)sign * sin(ang) * I;
+  }
+  for (int64_t o = 0; o < outer; ++o)
+    for (int64_t in = 0; in < stride; ++in) {
+      int64_t b = o * N * stride + in;
+      for (int k = 0; k < N; ++k) {
+        cplx acc = 0.0;
+        for (int j = 0; j < N; ++j) acc += f[b + (int64_t)j * stride] * tw[((int64_t)j * k) % N];
+        tmp[k] = acc;
+      }
+      for (int k = 0; k < N; ++k) f[b + (int64_t)k * stride] = tmp[k];
+    }
+  free(tw);
+  free(tmp);
+}
+
+/* sign = -1: forward (unnormalised); sign = +1: inverse (scaled by 1/ncell) */
+static void dft3(const grid* G, cplx* f, int sign) {
+  for (int a = 0; a < 3; ++a) dft_axis(G, f, a, sign);
+  if (sign > 0)
+    for (int64_t g = 0; g < G->ncell; ++g) f[g] /= (double)G->ncell;
+}
+
+/* Fourier symbol k~ of the first derivative along one axis, mode index m:
+   2 pi m_signed / L, and zero on the Nyquist index of an even axis */
+static double ktilde(const grid* G, int a, long m) {
+  int N = G->n[a];
+  if (2 * m == N) return 0.0;
+  long ms = (2 * m < N) ? m : m - N;
+  return 2.0 * M_PI * (double)ms / G->L[a];
+}
+
+static void mode_k(const grid* G, int64_t g, double k[3]) {
+  long iz = g % G->n[2];
+  long iy = (g / G->n[2]) % G->n[1];
+  long ix = g / ((int64_t)G->n[2] * G->n[1]);
+  k[0] = ktilde(G, 0, ix);
+  k[1] = ktilde(G, 1, iy);
+  k[2] = ktilde(G, 2, iz);
+}
+
+static void to_real(const grid* G, const cplx* fh, double* out) {
+  cplx* t = (cplx*)malloc(sizeof(cplx) * G->ncell);
+  memcpy(t, fh, sizeof(cplx) * G->ncell);
+  dft3(G, t, +1);
+  for (int64_t g = 0; g < G->ncell; ++g) out[g] = creal(t[g]);
+  free(t);
+}
+
+static void to_fourier(const grid* G, const double* f, cplx* out) {
+  for (int64_t g = 0; g < G->ncell; ++g) out[g] = f[g];
+  dft3(G, out, -1);
+}
+
+/* continuity (eq. cn-continuity) and Crank-Nicolson update (eq. cn-field-update)
+   of one step, mode by mode.  Inputs are the level-n spectra and J^{n+1/2};
+   outputs the level-(n+1) spectra.  The CN pair (phi, psi) solves the 2x2 system
+     phi1 - a psi1                 = phi0 + a psi0
+     a w2 phi1 + psi1              = psi0 - a w2 phi0 + dt kappa^2 sigma1 rho^{n+1/2}
+   with a = dt/2, w2 = kappa^2 |k~|^2 (Delta_h -> -|k~|^2); (A_l, U_l) likewise with
+   sigma2 J_l. */
+static void field_update(const orc_sim* S, const cplx* Jh, const cplx* phi0, const cplx* psi0,
+                         const cplx* A0, const cplx* U0, const cplx* rho0, cplx* phi1, cplx* psi1,
+                         cplx* A1, cplx* U1, cplx* rho1) {
+  const grid* G = &S->G;
+  double dt = S->c.dt, kap2 = S->c.kappa * S->c.kappa;
+  double a = 0.5 * dt;
+  int64_t nc = G->ncell;
+  for (int64_t g = 0; g < nc; ++g) {
+    double k[3];
+    mode_k(G, g, k);
+    double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    double w2 = kap2 * k2;
+    cplx divJ = I * (k[0] * Jh[g] + k[1] * Jh[nc + g] + k[2] * Jh[2 * nc + g]);
+    rho1[g] = rho0[g] - dt * divJ;
+    cplx rhoh = 0.5 * (rho1[g] + rho0[g]);
+    double det = 1.0 + a * a * w2;
+    {
+      cplx b1 = phi0[g] + a * psi0[g];
+      cplx b2 = psi0[g] - a * w2 * phi0[g] + dt * kap2 * S->c.sigma1 * rhoh;
+      phi1[g] = (b1 + a * b2) / det;
+      psi1[g] = (b2 - a * w2 * b1) / det;
+    }
+    for (int l = 0; l < 3; ++l) {
+      int64_t lg = (int64_t)l * nc + g;
+      cplx b1 = A0[lg] + a * U0[lg];
+      cplx b2 = U0[lg] - a * w2 * A0[lg] + dt * kap2 * S->c.sigma2 * Jh[lg];
+      A1[lg] = (b1 + a * b2) / det;
+      U1[lg] = (b2 - a * w2 * b1) / det;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* energies and constraint residuals                                         */
+/* ------------------------------------------------------------------------- */
+
+/* W = sum_g (|E_g|^2 / (2 sigma1) + |B_g|^2 / (2 sigma2)) dV with
+   E = -grad_h phi - U, B = curl_h A (eqs. field-energy, fields-from-potentials-discrete) */
+static double field_energy(const orc_sim* S, const cplx* phi, const cplx* A, const cplx* U) {
+  const grid* G = &S->G;
+  int64_t nc = G->ncell;
+  cplx* Eh = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  cplx* Bh = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  for (int64_t g = 0; g < nc; ++g) {
+    double k[3];
+    mode_k(G, g, k);
+    for (int l = 0; l < 3; ++l) Eh[l * nc + g] = -I * k[l] * phi[g] - U[l * nc + g];
+    Bh[0 * nc + g] = I * (k[1] * A[2 * nc + g] - k[2] * A[1 * nc + g]);
+    Bh[1 * nc + g] = I * (k[2] * A[0 * nc + g] - k[0] * A[2 * nc + g]);
+    Bh[2 * nc + g] = I * (k[0] * A[1 * nc + g] - k[1] * A[0 * nc + g]);
+  }
+  double* f = (double*)malloc(sizeof(double) * nc);
+  double W = 0.0;
+  for (int l = 0; l < 3; ++l) {
+    to_real(G, Eh + l * nc, f);
+    for (int64_t g = 0; g < nc; ++g) W += f[g] * f[g] / (2.0 * S->c.sigma1) * G->dV;
+    to_real(G, Bh + l * nc, f);
+    for (int64_t g = 0; g < nc; ++g) W += f[g] * f[g] / (2.0 * S->c.sigma2) * G->dV;
+  }
+  free(Eh);
+  free(Bh);
+  free(f);
+  return W;
+}
+
+static double kinetic_energy(const orc_sim* S) {
+  double K = 0.0;
+  for (int64_t i = 0; i < S->np; ++i)
+    for (int a = 0; a < 3; ++a) {
+      double va = S->v[(int64_t)a * S->np + i];
+      K += 0.5 * S->m * va * va;
+    }
+  return K;
+}
+
+/* G_h = psi / kappa^2 + div_h A (eq. gauge-diagnostic),
+   R_h = div_h E - sigma1 rho (eq. gauss-diagnostic), max and rms over nodes */
+static void constraints(const orc_sim* S, double* gmax, double* gl2, double* rmax, double* rl2) {
+  const grid* G = &S->G;
+  int64_t nc = G->ncell;
+  double kap2 = S->c.kappa * S->c.kappa;
+  cplx* gh = (cplx*)malloc(sizeof(cplx) * nc);
+  cplx* rh = (cplx*)malloc(sizeof(cplx) * nc);
+  for (int64_t g = 0; g < nc; ++g) {
+    double k[3];
+    mode_k(G, g, k);
+    cplx divA = I * (k[0] * S->A[g] + k[1] * S->A[nc + g] + k[2] * S->A[2 * nc + g]);
+    gh[g] = S->psi[g] / kap2 + divA;
+    cplx divE = 0.0;
+    for (int l = 0; l < 3; ++l) {
+      cplx El = -I * k[l] * S->phi[g] - S->U[l * nc + g];
+      divE += I * k[l] * El;
+    }
+    rh[g] = divE - S->c.sigma1 * S->rho[g];
+  }
+  double* f = (double*)malloc(sizeof(double) * nc);
+  to_real(G, gh, f);
+  *gmax = 0.0;
+  *gl2 = 0.0;
+  for (int64_t g = 0; g < nc; ++g) {
+    *gmax = fmax(*gmax, fabs(f[g]));
+    *gl2 += f[g] * f[g];
+  }
+  *gl2 = sqrt(*gl2 / nc);
+  to_real(G, rh, f);
+  *rmax = 0.0;
+  *rl2 = 0.0;
+  for (int64_t g = 0; g < nc; ++g) {
+    *rmax = fmax(*rmax, fabs(f[g]));
+    *rl2 += f[g] * f[g];
+  }
+  *rl2 = sqrt(*rl2 / nc);
+  free(gh);
+  free(rh);
+  free(f);
+}
+
+/* ------------------------------------------------------------------------- */
+/* public API                                                                */
+/* ------------------------------------------------------------------------- */
+
+int orc_check_config(const orc_cfg* c) {
+  for (int a = 0; a < 3; ++a)
+    if (c->n[a] < 2 || !(c->L[a] > 0.0)) return -1;
+  if (c->r != 1 && c->r != 2) return -1;
+  if (!(c->dt > 0.0) || !(c->kappa > 0.0) || !(c->sigma1 > 0.0) || !(c->sigma2 > 0.0)) return -1;
+  /* Maxwell scaling sigma1 = kappa^2 sigma2 (eq. Maxwell_scaling), to roundoff */
+  double lhs = c->sigma1, rhs = c->kappa * c->kappa * c->sigma2;
+  if (fabs(lhs - rhs) > 1e-13 * fmax(fabs(lhs), fabs(rhs))) return -1;
+  if (c->nq < 0 || c->nq > 64 || c->pmax < 0) return -1;
+  return 0;
+}
+
+orc_sim* orc_create(const orc_cfg* c, int64_t np) {
+  if (orc_check_config(c) != 0 || np < 0) return NULL;
+  orc_sim* S = (orc_sim*)calloc(1, sizeof(orc_sim));
+  S->c = *c;
+  make_grid(c, &S->G);
+  int nq = c->nq;
+  if (nq == 0) nq = (3 * c->r + 2) / 2; /* smallest n with 2n - 1 >= 3r */
+  S->nq = nq;
+  gauss_legendre(nq, S->gx, S->gw);
+  S->np = np;
+  int64_t n3 = 3 * (np > 0 ? np : 1);
+  S->x = (double*)calloc(n3, sizeof(double));
+  S->v = (double*)calloc(n3, sizeof(double));
+  S->vprev = (double*)calloc(n3, sizeof(double));
+  S->P = (double*)calloc(n3, sizeof(double));
+  int64_t nc = S->G.ncell;
+  S->phi = (cplx*)calloc(nc, sizeof(cplx));
+  S->psi = (cplx*)calloc(nc, sizeof(cplx));
+  S->rho = (cplx*)calloc(nc, sizeof(cplx));
+  S->A = (cplx*)calloc(3 * nc, sizeof(cplx));
+  S->U = (cplx*)calloc(3 * nc, sizeof(cplx));
+  S->J = (double*)calloc(3 * nc, sizeof(double));
+  S->q = -1.0;
+  S->m = 1.0;
+  return S;
+}
+
+void orc_destroy(orc_sim* S) {
+  if (!S) return;
+  free(S->x);
+  free(S->v);
+  free(S->vprev);
+  free(S->P);
+  free(S->phi);
+  free(S->psi);
+  free(S->rho);
+  free(S->A);
+  free(S->U);
+  free(S->J);
+  free(S);
+}
+
+/* Gauss rule in use (for tests) */
+int orc_gauss_rule(const orc_sim* S, double* x, double* w) {
+  for (int i = 0; i < S->nq; ++i) {
+    x[i] = S->gx[i];
+    w[i] = S->gw[i];
+  }
+  return S->nq;
+}
+
+int orc_gauss_legendre(int n, double* x, double* w) {
+  if (n < 1 || n > 64) return -1;
+  gauss_legendre(n, x, w);
+  return 0;
+}
+
+static void update_energy_start(orc_sim* S) {
+  S->en.K = kinetic_energy(S);
+  S->en.W = field_energy(S, S->phi, S->A, S->U);
+  S->en.E_total = S->en.K + S->en.W;
+  constraints(S, &S->en.gauge_max, &S->en.gauge_l2, &S->en.gauss_max, &S->en.gauss_l2);
+}
+
+/* Initial state of the two-stream setup (Sec. 5.4): point-shape charge deposit
+   plus uniform background n0, mean removed (and zeroed on every k~ = 0 mode),
+   phi^0 from -Delta_h phi = sigma1 rho, psi = A = U = 0, P = m v, v^{-1} = v^0. */
+int orc_init_particles(orc_sim* S, const double* x, const double* v, double q, double m,
+                       double n0) {
+  const grid* G = &S->G;
+  int64_t np = S->np, nc = G->ncell;
+  S->q = q;
+  S->m = m;
+  for (int64_t i = 0; i < 3 * np; ++i) {
+    S->v[i] = v[i];
+    S->vprev[i] = v[i];
+    S->P[i] = m * v[i];
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int64_t i = 0; i < np; ++i) S->x[a * np + i] = wrap_pos(x[a * np + i], G->L[a]);
+  double* rho = (double*)calloc(nc, sizeof(double));
+  deposit_point_charge(G, S->c.r, np, S->x, q, rho);
+  double mean = 0.0;
+  for (int64_t g = 0; g < nc; ++g) {
+    rho[g] += n0;
+    mean += rho[g];
+  }
+  mean /= (double)nc;
+  for (int64_t g = 0; g < nc; ++g) rho[g] -= mean;
+  to_fourier(G, rho, S->rho);
+  free(rho);
+  for (int64_t g = 0; g < nc; ++g) {
+    double k[3];
+    mode_k(G, g, k);
+    double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    if (k2 == 0.0) {
+      S->rho[g] = 0.0;
+      S->phi[g] = 0.0;
+    } else {
+      S->phi[g] = S->c.sigma1 * S->rho[g] / k2;
+    }
+    S->psi[g] = 0.0;
+    for (int l = 0; l < 3; ++l) {
+      S->A[l * nc + g] = 0.0;
+      S->U[l * nc + g] = 0.0;
+    }
+  }
+  memset(S->J, 0, sizeof(double) * 3 * nc);
+  memset(&S->en, 0, sizeof(S->en));
+  update_energy_start(S);
+  S->K0 = S->en.K;
+  S->W0 = S->en.W;
+  S->have_energy = 1;
+  return 0;
+}
+
+/* One time step: Algorithm 1 (Picard iteration of the coupled orbit /
+   continuity / CN / push system).  Returns 0 when converged, 1 when the
+   iteration reached p_max (the last iterate is accepted), -1 on error. */
+int orc_picard_step(orc_sim* S, orc_step_info* info) {
+  const grid* G = &S->G;
+  int64_t np = S->np, nc = G->ncell;
+  double dt = S->c.dt, q = S->q, m = S->m;
+
+  double K_n = kinetic_energy(S);
+  double W_n = field_energy(S, S->phi, S->A, S->U);
+
+  /* level-n mesh quantities in real space */
+  double* A0r = (double*)malloc(sizeof(double) * 3 * nc);
+  for (int l = 0; l < 3; ++l) to_real(G, S->A + l * nc, A0r + l * nc);
+
+  double* vit = (double*)malloc(sizeof(double) * 3 * np + 8);
+  double* vnew = (double*)malloc(sizeof(double) * 3 * np + 8);
+  double* Pnew = (double*)malloc(sizeof(double) * 3 * np + 8);
+  double* J = (double*)malloc(sizeof(double) * 3 * nc);
+  double* Jprev = (double*)malloc(sizeof(double) * 3 * nc);
+  cplx* Jh = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  cplx *phi1 = (cplx*)malloc(sizeof(cplx) * nc), *psi1 = (cplx*)malloc(sizeof(cplx) * nc);
+  cplx* rho1 = (cplx*)malloc(sizeof(cplx) * nc);
+  cplx *A1 = (cplx*)malloc(sizeof(cplx) * 3 * nc), *U1 = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  cplx* tmp = (cplx*)malloc(sizeof(cplx) * nc);
+  double* gphi = (double*)malloc(sizeof(double) * 3 * nc);
+  double* Uhalf = (double*)malloc(sizeof(double) * 3 * nc);
+  double* A1r = (double*)malloc(sizeof(double) * 3 * nc);
+  piece* buf = (piece*)malloc(sizeof(piece) * MAX_PIECES);
+  int status = 1;
+  double err_v = 0.0, err_J = 0.0;
+  int p = 0;
+  double work = 0.0, JE = 0.0, RA2 = 0.0, RAmax = 0.0, poumax = 0.0;
+
+  /* extrapolated initial guess v^{n+1,0} = 2 v^n - v^{n-1} */
+  for (int64_t i = 0; i < 3 * np; ++i) vit[i] = 2.0 * S->v[i] - S->vprev[i];
+
+  for (p = 0; p <= S->c.pmax; ++p) {
+    /* orbit of the current iterate and its current J^{n+1/2,p} */
+    memset(J, 0, sizeof(double) * 3 * nc);
+    double Js = 0.0;
+    for (int64_t i = 0; i < np; ++i) {
+      double x0[3], vb[3], d[3], qv[3];
+      double vmax = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        x0[a] = S->x[a * np + i];
+        vb[a] = 0.5 * (vit[a * np + i] + S->v[a * np + i]);
+        d[a] = dt * vb[a];
+        qv[a] = q * vb[a];
+        vmax = fmax(vmax, fabs(vb[a]));
+      }
+      Js += fabs(q) * vmax;
+      if (deposit_one(S, x0, d, qv, J, buf) != 0) { status = -1; goto done; }
+    }
+    Js /= G->vol;
+
+    /* continuity + CN */
+    for (int l = 0; l < 3; ++l) to_fourier(G, J + l * nc, Jh + l * nc);
+    field_update(S, Jh, S->phi, S->psi, S->A, S->U, S->rho, phi1, psi1, A1, U1, rho1);
+
+    /* midpoint and end-of-step mesh fields in real space */
+    for (int l = 0; l < 3; ++l) {
+      for (int64_t g = 0; g < nc; ++g) {
+        double k[3];
+        mode_k(G, g, k);
+        tmp[g] = I * k[l] * 0.5 * (phi1[g] + S->phi[g]);
+      }
+      to_real(G, tmp, gphi + l * nc);
+      for (int64_t g = 0; g < nc; ++g) tmp[g] = 0.5 * (U1[l * nc + g] + S->U[l * nc + g]);
+      to_real(G, tmp, Uhalf + l * nc);
+      to_real(G, A1 + l * nc, A1r + l * nc);
+    }
+
+    /* gather + orbit-discrete-gradient push + velocity closure */
+    double dvmax = 0.0, vmaxall = 0.0;
+    work = 0.0;
+    RA2 = 0.0;
+    RAmax = 0.0;
+    poumax = 0.0;
+    for (int64_t i = 0; i < np; ++i) {
+      double x0[3], vb[3], d[3], x1[3];
+      for (int a = 0; a < 3; ++a) {
+        x0[a] = S->x[a * np + i];
+        vb[a] = 0.5 * (vit[a * np + i] + S->v[a * np + i]);
+        d[a] = dt * vb[a];
+        x1[a] = x0[a] + d[a];
+      }
+      double gpb[3], Ub[3], D[3][3], pou;
+      if (gather_one(S, x0, d, gphi, Uhalf, A0r, A1r, gpb, Ub, D, &pou, buf) != 0) {
+        status = -1;
+        goto done;
+      }
+      double Aend[3], Astart[3];
+      interp_point(G, S->c.r, x1, A1r, 3, Aend);
+      interp_point(G, S->c.r, x0, A0r, 3, Astart);
+      for (int j = 0; j < 3; ++j) {
+        double DTv = 0.0; /* ((D A)^T vbar)_j = sum_l D_lj vbar_l */
+        for (int l = 0; l < 3; ++l) DTv += D[l][j] * vb[l];
+        double Pj = S->P[j * np + i] + dt * (-q * gpb[j] + q * DTv);
+        Pnew[j * np + i] = Pj;
+        double vj = (Pj - q * Aend[j]) / m;
+        vnew[j * np + i] = vj;
+        dvmax = fmax(dvmax, fabs(vj - vit[j * np + i]));
+        vmaxall = fmax(vmaxall, fabs(vj));
+      }
+      for (int l = 0; l < 3; ++l) {
+        double Dv = 0.0;
+        for (int j = 0; j < 3; ++j) Dv += D[l][j] * vb[j];
+        double RA = Aend[l] - Astart[l] - dt * (Ub[l] + Dv);
+        RA2 += RA * RA;
+        RAmax = fmax(RAmax, fabs(RA));
+        work += q * vb[l] * (-gpb[l] - Ub[l]);
+      }
+      poumax = fmax(poumax, fabs(pou - 1.0));
+    }
+
+    /* mesh work sum_g J.E^{n+1/2} dV of this iterate */
+    JE = 0.0;
+    for (int l = 0; l < 3; ++l)
+      for (int64_t g = 0; g < nc; ++g)
+        JE += J[l * nc + g] * (-gphi[l * nc + g] - Uhalf[l * nc + g]) * G->dV;
+
+    /* fixed-point errors */
+    err_v = vmaxall > 0.0 ? dvmax / vmaxall : dvmax;
+    if (p >= 1) {
+      double dJ = 0.0;
+      for (int64_t g = 0; g < 3 * nc; ++g) dJ = fmax(dJ, fabs(J[g] - Jprev[g]));
+      err_J = Js > 0.0 ? dJ / Js : dJ;
+    } else {
+      err_J = INFINITY;
+    }
+    memcpy(Jprev, J, sizeof(double) * 3 * nc);
+
+    if (p >= 1 && err_v < S->c.tol && err_J < S->c.tol) {
+      status = 0;
+      break;
+    }
+    if (p == S->c.pmax) break;
+    memcpy(vit, vnew, sizeof(double) * 3 * np);
+  }
+  if (p > S->c.pmax) p = S->c.pmax;
+
+  /* accept iterate p: x^{n+1} = x^n + dt vbar^p (wrapped), v^{n+1} = v^{n+1,p+1},
+     P^{n+1} = P^{n+1,p}, mesh fields of iterate p */
+  for (int a = 0; a < 3; ++a)
+    for (int64_t i = 0; i < np; ++i) {
+      int64_t id = a * np + i;
+      double vb = 0.5 * (vit[id] + S->v[id]);
+      S->x[id] = wrap_pos(S->x[id] + dt * vb, G->L[a]);
+      S->vprev[id] = S->v[id];
+      S->v[id] = vnew[id];
+      S->P[id] = Pnew[id];
+    }
+  memcpy(S->phi, phi1, sizeof(cplx) * nc);
+  memcpy(S->psi, psi1, sizeof(cplx) * nc);
+  memcpy(S->rho, rho1, sizeof(cplx) * nc);
+  memcpy(S->A, A1, sizeof(cplx) * 3 * nc);
+  memcpy(S->U, U1, sizeof(cplx) * 3 * nc);
+  memcpy(S->J, J, sizeof(double) * 3 * nc);
+
+  /* diagnostics of the accepted iterate (its orbit, current and fields) */
+  update_energy_start(S);
+  S->en.R_field = S->en.W - W_n + dt * JE;
+  S->en.R_particle = S->en.K - K_n - dt * work;
+  S->en.R_total = (S->en.K + S->en.W) - (K_n + W_n);
+  S->en.JE_mesh = JE;
+  S->en.work_particle = work;
+  S->en.RA_rms = np > 0 ? sqrt(RA2 / (3.0 * np)) : 0.0;
+  S->en.RA_max = RAmax;
+  S->en.pou_max = poumax;
+  S->en.step += 1;
+
+done:
+  if (info) {
+    info->iters = p + 1;
+    info->converged = status == 0;
+    info->err_v = err_v;
+    info->err_J = err_J;
+  }
+  free(A0r);
+  free(vit);
+  free(vnew);
+  free(Pnew);
+  free(J);
+  free(Jprev);
+  free(Jh);
+  free(phi1);
+  free(psi1);
+  free(rho1);
+  free(A1);
+  free(U1);
+  free(tmp);
+  free(gphi);
+  free(Uhalf);
+  free(A1r);
+  free(buf);
+  return status;
+}
+
+int orc_energy_diagnostics(const orc_sim* S, orc_energy* out) {
+  *out = S->en;
+  return 0;
+}
+
+/* fields layout: [phi, psi, Ax, Ay, Az, Ux, Uy, Uz, rho] real-space, ncell each */
+int orc_get_state(const orc_sim* S, double* x, double* v, double* vprev, double* P,
+                  double* fields) {
+  int64_t n3 = 3 * S->np, nc = S->G.ncell;
+  if (x) memcpy(x, S->x, sizeof(double) * n3);
+  if (v) memcpy(v, S->v, sizeof(double) * n3);
+  if (vprev) memcpy(vprev, S->vprev, sizeof(double) * n3);
+  if (P) memcpy(P, S->P, sizeof(double) * n3);
+  if (fields) {
+    to_real(&S->G, S->phi, fields + 0 * nc);
+    to_real(&S->G, S->psi, fields + 1 * nc);
+    for (int l = 0; l < 3; ++l) to_real(&S->G, S->A + l * nc, fields + (2 + l) * nc);
+    for (int l = 0; l < 3; ++l) to_real(&S->G, S->U + l * nc, fields + (5 + l) * nc);
+    to_real(&S->G, S->rho, fields + 8 * nc);
+  }
+  return 0;
+}
+
+int orc_set_state(orc_sim* S, const double* x, const double* v, const double* vprev,
+                  const double* P, const double* fields, double q, double m) {
+  int64_t n3 = 3 * S->np, nc = S->G.ncell;
+  S->q = q;
+  S->m = m;
+  if (x) memcpy(S->x, x, sizeof(double) * n3);
+  if (v) memcpy(S->v, v, sizeof(double) * n3);
+  if (vprev) memcpy(S->vprev, vprev, sizeof(double) * n3);
+  if (P) memcpy(S->P, P, sizeof(double) * n3);
+  if (fields) {
+    to_fourier(&S->G, fields + 0 * nc, S->phi);
+    to_fourier(&S->G, fields + 1 * nc, S->psi);
+    for (int l = 0; l < 3; ++l) to_fourier(&S->G, fields + (2 + l) * nc, S->A + l * nc);
+    for (int l = 0; l < 3; ++l) to_fourier(&S->G, fields + (5 + l) * nc, S->U + l * nc);
+    to_fourier(&S->G, fields + 8 * nc, S->rho);
+  }
+  update_energy_start(S);
+  return 0;
+}
+
+/* real-space orbit current of the accepted iterate of the last step */
+int orc_get_current(const orc_sim* S, double* J) {
+  memcpy(J, S->J, sizeof(double) * 3 * S->G.ncell);
+  return 0;
+}
+
+/* Field update alone (continuity + CN) for a given real-space J^{n+1/2}, from the
+   current state; the state advances to level n+1 (particles untouched). */
+int orc_field_solve(orc_sim* S, const double* J) {
+  const grid* G = &S->G;
+  int64_t nc = G->ncell;
+  cplx* Jh = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  cplx *phi1 = (cplx*)malloc(sizeof(cplx) * nc), *psi1 = (cplx*)malloc(sizeof(cplx) * nc);
+  cplx* rho1 = (cplx*)malloc(sizeof(cplx) * nc);
+  cplx *A1 = (cplx*)malloc(sizeof(cplx) * 3 * nc), *U1 = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  for (int l = 0; l < 3; ++l) to_fourier(G, J + l * nc, Jh + l * nc);
+  field_update(S, Jh, S->phi, S->psi, S->A, S->U, S->rho, phi1, psi1, A1, U1, rho1);
+  memcpy(S->phi, phi1, sizeof(cplx) * nc);
+  memcpy(S->psi, psi1, sizeof(cplx) * nc);
+  memcpy(S->rho, rho1, sizeof(cplx) * nc);
+  memcpy(S->A, A1, sizeof(cplx) * 3 * nc);
+  memcpy(S->U, U1, sizeof(cplx) * 3 * nc);
+  memcpy(S->J, J, sizeof(double) * 3 * nc);
+  update_energy_start(S);
+  free(Jh);
+  free(phi1);
+  free(psi1);
+  free(rho1);
+  free(A1);
+  free(U1);
+  return 0;
+}
+
+/* W of arbitrary real-space potentials (phi, A[3], U[3]) -- used by tests */
+double orc_field_energy_of(const orc_sim* S, const double* phi, const double* A, const double* U) {
+  int64_t nc = S->G.ncell;
+  cplx* ph = (cplx*)malloc(sizeof(cplx) * nc);
+  cplx* Ah = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  cplx* Uh = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  to_fourier(&S->G, phi, ph);
+  for (int l = 0; l < 3; ++l) {
+    to_fourier(&S->G, A + l * nc, Ah + l * nc);
+    to_fourier(&S->G, U + l * nc, Uh + l * nc);
+  }
+  double W = field_energy(S, ph, Ah, Uh);
+  free(ph);
+  free(Ah);
+  free(Uh);
+  return W;
+}
+
+/* ---- single-particle and kernel-level entry points for tests ------------ */
+
+/* Orbit integrals of n particles against given real-space mesh fields
+   gphi (3 x ncell), Uh (3 x ncell), A0, A1 (3 x ncell).
+   out per particle (stride 24):
+     [0:3] gphibar, [3:6] Ubar, [6:15] D (row l, column j), [15:18] A1_h(x1),
+     [18:21] A0_h(x0), [21] sum_g Sbar_g, [22] number of pieces, [23] unused */
+int orc_orbit_gather(const orc_sim* S, int64_t n, const double* x0, const double* d,
+                     const double* gphi, const double* Uh, const double* A0, const double* A1,
+                     double* out) {
+  piece* buf = (piece*)malloc(sizeof(piece) * MAX_PIECES);
+  for (int64_t i = 0; i < n; ++i) {
+    double xa[3], da[3], x1[3];
+    for (int a = 0; a < 3; ++a) {
+      xa[a] = x0[3 * i + a];
+      da[a] = d[3 * i + a];
+      x1[a] = xa[a] + da[a];
+    }
+    double gpb[3], Ub[3], D[3][3], pou;
+    if (gather_one(S, xa, da, gphi, Uh, A0, A1, gpb, Ub, D, &pou, buf) != 0) {
+      free(buf);
+      return -1;
+    }
+    double* o = out + 24 * i;
+    for (int l = 0; l < 3; ++l) {
+      o[l] = gpb[l];
+      o[3 + l] = Ub[l];
+      for (int j = 0; j < 3; ++j) o[6 + 3 * l + j] = D[l][j];
+    }
+    interp_point(&S->G, S->c.r, x1, A1, 3, o + 15);
+    interp_point(&S->G, S->c.r, xa, A0, 3, o + 18);
+    o[21] = pou;
+    o[22] = (double)orbit_pieces(S, xa, da, buf, MAX_PIECES);
+    o[23] = 0.0;
+  }
+  free(buf);
+  return 0;
+}
+
+/* Orbit current of n particles (positions x0, displacements d, per-particle
+   q vbar in qv), all 3*n row-major per particle; J is 3 x ncell, accumulated. */
+int orc_orbit_deposit(const orc_sim* S, int64_t n, const double* x0, const double* d,
+                      const double* qv, double* J) {
+  piece* buf = (piece*)malloc(sizeof(piece) * MAX_PIECES);
+  for (int64_t i = 0; i < n; ++i) {
+    if (deposit_one(S, x0 + 3 * i, d + 3 * i, qv + 3 * i, J, buf) != 0) {
+      free(buf);
+      return -1;
+    }
+  }
+  free(buf);
+  return 0;
+}
+
+/* point interpolation of ncomp real-space fields at n points (3*n row-major) */
+int orc_interp(const orc_sim* S, int64_t n, const double* x, const double* F, int ncomp,
+               double* out) {
+  for (int64_t i = 0; i < n; ++i) interp_point(&S->G, S->c.r, x + 3 * i, F, ncomp, out + ncomp * i);
+  return 0;
+}
+
+/* breakpoints of one orbit (returns count) */
+int orc_breakpoints(const orc_sim* S, const double* x0, const double* d, double* s) {
+  return orbit_breakpoints(&S->G, S->c.r, x0, d, s);
+}
+
+/* 3D DFT of interleaved complex data (sign -1 forward, +1 inverse scaled) */
+int orc_dft3(const orc_sim* S, double* data, int sign) {
+  dft3(&S->G, (cplx*)data, sign);
+  return 0;
+}
+
+/* Fourier symbols k~ of the three axes at every mode (3 x ncell) */
+int orc_ktilde(const orc_sim* S, double* k) {
+  int64_t nc = S->G.ncell;
+  for (int64_t g = 0; g < nc; ++g) {
+    double kk[3];
+    mode_k(&S->G, g, kk);
+    for (int a = 0; a < 3; ++a) k[a * nc + g] = kk[a];
+  }
+  return 0;
+}
