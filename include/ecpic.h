@@ -1,0 +1,185 @@
+/*
+ * ecpic.h -- C ABI of the MI355X (gfx950) implementation of the
+ * energy-conserving, unstaggered, Lorenz-gauge potential particle-in-cell step
+ * of Christlieb, Chacon and Gong, "An Energy-Conserving Unstaggered
+ * Electromagnetic-Potential Particle-in-Cell Method, Part I: Non-relativistic
+ * Generalized-Momentum Formulation".
+ *
+ * Model (Sec. 2-3): periodic box, collocated nodes x_g = g H, potentials
+ * (phi, psi = d_t phi, A, U = d_t A) advanced by Crank-Nicolson
+ * (eq. cn-field-update) with Fourier derivatives (Sec. 3.3), charge advanced
+ * from the orbit current by continuity (eq. cn-continuity), particles pushed in
+ * canonical momentum with the orbit-discrete gradient (eq. orbit-push) inside
+ * the Picard iteration of Algorithm 1.
+ *
+ * General rules of the ABI
+ *   - Every function returns an ecpic_status.  Nothing aborts, nothing throws.
+ *     ecpic_last_error() gives a thread-local message for the last non-OK status.
+ *   - Device memory belongs to the caller.  ecpic_state_bytes() tells how much
+ *     "state" (persistent between steps) and "workspace" (scratch) memory a
+ *     simulation needs; the caller allocates both on the device (256-byte
+ *     aligned) and hands them to ecpic_create().  The library never allocates or
+ *     frees device memory.  It allocates a small pinned host buffer for the
+ *     per-iteration convergence read-back.
+ *   - All device work is enqueued on the HIP stream given to ecpic_create()
+ *     (NULL = default stream).  Calls that return host data synchronise that
+ *     stream; ecpic_picard_step() synchronises it once per Picard iteration to
+ *     read the two fixed-point errors.
+ *   - Host arrays passed in are copied before the call returns; the library
+ *     keeps no host pointer.
+ *   - Array layouts.  Particle arrays are component-major (SoA): x[a*np + i].
+ *     Mesh arrays are node arrays with node (ix, iy, iz) at flat index
+ *     (ix*Ny + iy)*Nz + iz; vector fields store their 3 components one after
+ *     the other (component-major).
+ *   - Units are the nondimensional ones of Sec. 2; q and m are per macro-particle.
+ */
+#ifndef ECPIC_H
+#define ECPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ECPIC_OK = 0,
+  ECPIC_ENOCONV = 1,     /* warning: the step completed but Picard reached picard_max;
+                            the last iterate is accepted (end of Algorithm 1) */
+  ECPIC_EINVAL = -1,     /* invalid argument or configuration */
+  ECPIC_ENOMEM = -2,     /* state/workspace too small, or pinned host allocation failed */
+  ECPIC_EDEVICE = -3,    /* a HIP call failed */
+  ECPIC_ENONFINITE = -4, /* a non-finite particle velocity or field appeared */
+  ECPIC_ESTATE = -5      /* call out of order (e.g. a step before init) */
+} ecpic_status;
+
+typedef enum { ECPIC_FP64 = 0, ECPIC_MIXED = 1 } ecpic_precision;
+
+typedef struct {
+  int32_t n[3];                 /* mesh points per axis: powers of two, 4 <= n <= 256 */
+  int32_t spline_degree;        /* r = 1 (linear B-spline, App. A/B) or 2 (quadratic) */
+  double L[3];                  /* periodic box lengths; H_a = L_a / n_a */
+  double kappa;                 /* nondimensional speed of light (Sec. 2.1) */
+  double sigma1, sigma2;        /* source coefficients; must satisfy sigma1 = kappa^2 sigma2
+                                   (eq. Maxwell_scaling), checked to 1e-13 relative */
+  double dt;                    /* time step */
+  double picard_tol;            /* tau: stop when both fixed-point errors are below it (p >= 1) */
+  int32_t picard_max;           /* p_max: iterations p = 0..p_max (at most p_max+1 passes) */
+  int32_t split_orbit_at_knots; /* 1: split orbit integrals at every crossed knot (Sec. 4.7);
+                                   0: one Gauss rule over the whole orbit (comparison runs) */
+  int32_t quad_points;          /* Gauss points per piece; 0 = smallest exact rule
+                                   (2 n_q - 1 >= 3 r): 2 for r = 1, 4 for r = 2 */
+  int32_t precision;            /* ecpic_precision */
+  double fixed_point_scale;     /* mixed precision: current quantum is 1/fixed_point_scale of
+                                   the per-particle charge unit (0 = 2^40) */
+  int32_t diagnostics;          /* 1: after each accepted step run the consistency sweep
+                                   (R_particle, R_A, partition of unity) */
+  int32_t reserved;
+} ecpic_config;
+
+typedef struct {
+  int32_t iters;     /* Picard passes executed (p + 1) */
+  int32_t converged; /* 1 if both errors fell below picard_tol */
+  double err_v;      /* max_i |v^{p+1} - v^p|_inf / max_i |v^{p+1}|_inf */
+  double err_J;      /* max_g |J^p - J^{p-1}|_inf / J_s, J_s = sum_i |q| |vbar_i|_inf / |Omega| */
+} ecpic_step_info;
+
+typedef struct {
+  double K, W, E_total;              /* eqs. particle-energy, field-energy, total-discrete-energy */
+  double R_field, R_particle, R_total; /* eqs. R-field, R-particle, R-total of the last step */
+  double gauge_max, gauge_l2;        /* G_h = psi/kappa^2 + div_h A (eq. gauge-diagnostic) */
+  double gauss_max, gauss_l2;        /* R_h = div_h E - sigma1 rho (eq. gauss-diagnostic) */
+  double RA_rms, RA_max;             /* chain-rule residual R_A (eq. RA-test), last step */
+  double pou_max;                    /* max_i |sum_g Sbar_ig - 1| (App. A), last step */
+  double JE_mesh;                    /* sum_g J^{n+1/2} . E^{n+1/2} dV of the last step */
+  double work_particle;              /* sum_i q vbar_i . Ebar_i of the last step */
+  int64_t step;                      /* number of accepted steps */
+} ecpic_energy;
+
+typedef struct ecpic_sim ecpic_sim;
+
+/* Bytes of device state and workspace for this configuration and particle
+   count.  Returns ECPIC_EINVAL for an invalid configuration. */
+ecpic_status ecpic_state_bytes(const ecpic_config* cfg, int64_t n_particles, size_t* state_bytes,
+                               size_t* workspace_bytes);
+
+/* Create a simulation over caller-owned device buffers (sizes from
+   ecpic_state_bytes, 256-byte aligned).  hip_stream is a hipStream_t or NULL.
+   The buffers must stay valid until ecpic_destroy(). */
+ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* state_dev,
+                          size_t state_bytes, void* workspace_dev, size_t workspace_bytes,
+                          void* hip_stream, ecpic_sim** out);
+
+void ecpic_destroy(ecpic_sim* sim);
+
+/* Initial state of Sec. 5.4: host positions x and velocities v (3*np each,
+   component-major); positions are wrapped into the box.  rho^0 is the
+   point-shape charge deposit (eq. source-moments) plus a uniform background
+   n0, mean removed and zeroed on every mode whose Fourier symbol vanishes;
+   phi^0 solves -Delta_h phi = sigma1 rho; psi = A = U = 0; P = m v;
+   v^{-1} = v^0. */
+ecpic_status ecpic_init_particles(ecpic_sim* sim, const double* x, const double* v, double q,
+                                  double m, double n0);
+
+/* One time step by Algorithm 1: extrapolated guess, then per Picard pass the
+   orbit current (eq. orbit-current), continuity and CN solve, orbit gather and
+   orbit-discrete-gradient push (eq. orbit-push); stop when both fixed-point
+   errors are below tau (p >= 1) or at p_max.  Returns ECPIC_OK, or
+   ECPIC_ENOCONV when p_max was reached (the step is still taken). */
+ecpic_status ecpic_picard_step(ecpic_sim* sim, ecpic_step_info* info);
+
+/* Continuity + CN field update alone (eqs. cn-continuity, cn-field-update)
+   with a caller current J^{n+1/2} (device, 3*ncell, component-major), or the
+   current of the last accepted step when J_dev is NULL.  Advances the mesh
+   state one level; particles are not touched. */
+ecpic_status ecpic_field_solve(ecpic_sim* sim, const double* J_dev);
+
+/* Energies and constraint residuals of the current state, and the balance
+   terms of the last step (Sec. 5.1-5.3).  R_particle, RA_* and pou_max need
+   diagnostics = 1 in the configuration (they are zero otherwise). */
+ecpic_status ecpic_energy_diagnostics(ecpic_sim* sim, ecpic_energy* out);
+
+/* Copy state to host buffers (any may be NULL): x, v, v^{n-1} (3*np each) and
+   real-space mesh fields (9*ncell: phi, psi, Ax, Ay, Az, Ux, Uy, Uz, rho). */
+ecpic_status ecpic_get_state(ecpic_sim* sim, double* x, double* v, double* vprev,
+                             double* fields);
+
+/* Replace the state from host buffers (same layout as ecpic_get_state; any may
+   be NULL to keep the current value).  q and m set the particle species. */
+ecpic_status ecpic_set_state(ecpic_sim* sim, const double* x, const double* v,
+                             const double* vprev, const double* fields, double q, double m);
+
+/* Orbit current J^{n+1/2} (3*ncell) of the last accepted step, to host. */
+ecpic_status ecpic_get_current(ecpic_sim* sim, double* J);
+
+/* Kernel-level entry points (device pointers, no simulation object): the
+   orbit integrals of n independent particles against given mesh fields, for
+   checking the particle kernels in isolation.
+     x0, d      3*n component-major: start positions (inside the box) and
+                unwrapped displacements of straight orbits x(s) = x0 + s d
+     gphi, U, A0, A1   3*ncell each (real-space node fields)
+     out        24*n, particle-major: [0:3] sum_g gphi_g Sbar_g, [3:6] sum_g U_g Sbar_g,
+                [6:15] D (row l = component of A, column j = derivative) per
+                eq. DA-def with A_g(s) = (1-s) A0 + s A1, [15:18] A1_h(x0+d),
+                [18:21] A0_h(x0), [21] sum_g Sbar_g, [22] number of orbit pieces
+   and the orbit current of n particles, accumulated into J (3*ncell):
+     J_g += qv_i Sbar_ig / dV   (qv: 3*n component-major, q_i vbar_i)   */
+ecpic_status ecpic_orbit_gather(const ecpic_config* cfg, int64_t n, const double* x0,
+                                const double* d, const double* gphi, const double* U,
+                                const double* A0, const double* A1, double* out,
+                                void* hip_stream);
+ecpic_status ecpic_orbit_deposit(const ecpic_config* cfg, int64_t n, const double* x0,
+                                 const double* d, const double* qv, double* J, void* hip_stream);
+
+/* Message for the last non-OK status of this thread ("" if none). */
+const char* ecpic_last_error(void);
+
+/* Library version string. */
+const char* ecpic_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECPIC_H */

@@ -1,0 +1,566 @@
+// C ABI of the library (declared in include/ecpic.h): configuration checks,
+// carving of the caller's device buffers, and the host side of Algorithm 1
+// (one Picard pass = scatter, forward FFT, continuity + CN, inverse FFT,
+// gather + push, then a read-back of the two fixed-point errors).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ecpic.h"
+#include "internal.hpp"
+#include "reduce.hpp"
+
+using namespace ecpic;
+
+namespace {
+
+thread_local std::string g_err;
+
+ecpic_status fail(ecpic_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+ecpic_status fail(ecpic_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ECPIC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));         \
+  } while (0)
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+ecpic_status check_config(const ecpic_config* c, int64_t np) {
+  if (!c) return fail(ECPIC_EINVAL, "null configuration");
+  if (np < 0) return fail(ECPIC_EINVAL, "negative particle count");
+  for (int a = 0; a < 3; ++a) {
+    if (!is_pow2(c->n[a]) || c->n[a] < 4 || c->n[a] > 256)
+      return fail(ECPIC_EINVAL, "n[%d] = %d must be a power of two in [4, 256]", a, c->n[a]);
+    if (!(c->L[a] > 0.0) || !std::isfinite(c->L[a]))
+      return fail(ECPIC_EINVAL, "L[%d] must be positive", a);
+  }
+  if (c->spline_degree != 1 && c->spline_degree != 2)
+    return fail(ECPIC_EINVAL, "spline_degree must be 1 or 2");
+  if (!(c->dt > 0.0) || !(c->kappa > 0.0) || !(c->sigma1 > 0.0) || !(c->sigma2 > 0.0))
+    return fail(ECPIC_EINVAL, "dt, kappa, sigma1, sigma2 must be positive");
+  const double lhs = c->sigma1, rhs = c->kappa * c->kappa * c->sigma2;
+  if (std::fabs(lhs - rhs) > 1e-13 * std::fmax(std::fabs(lhs), std::fabs(rhs)))
+    return fail(ECPIC_EINVAL, "Maxwell scaling sigma1 = kappa^2 sigma2 violated (%g vs %g)", lhs,
+                rhs);
+  if (c->picard_max < 0 || c->picard_max > 1000) return fail(ECPIC_EINVAL, "picard_max out of range");
+  if (!(c->picard_tol >= 0.0)) return fail(ECPIC_EINVAL, "picard_tol must be >= 0");
+  const int nq_min = c->spline_degree == 1 ? 2 : 4;
+  if (c->quad_points != 0 && c->quad_points != nq_min)
+    return fail(ECPIC_EINVAL, "quad_points: only the minimal exact rule (%d) is built", nq_min);
+  if (c->split_orbit_at_knots != 1)
+    return fail(ECPIC_EINVAL, "only split orbit integrals (split_orbit_at_knots = 1) are built");
+  if (c->precision != ECPIC_FP64) return fail(ECPIC_EINVAL, "precision: only FP64 is built");
+  return ECPIC_OK;
+}
+
+Grid make_grid(const ecpic_config* c) {
+  Grid G;
+  G.ncell = 1;
+  for (int a = 0; a < 3; ++a) {
+    G.n[a] = c->n[a];
+    G.L[a] = c->L[a];
+    G.H[a] = c->L[a] / c->n[a];
+    G.invH[a] = 1.0 / G.H[a];
+    G.ncell *= c->n[a];
+  }
+  G.dV = G.H[0] * G.H[1] * G.H[2];
+  G.vol = G.L[0] * G.L[1] * G.L[2];
+  return G;
+}
+
+// Bump allocator over a caller buffer (base may be null when only sizing).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+constexpr int kMaxSumValues = 4;
+
+}  // namespace
+
+struct ecpic_sim {
+  ecpic_config cfg;
+  Grid G;
+  int64_t np;
+  hipStream_t stream;
+  double q = -1.0, m = 1.0;
+  bool initialized = false;
+  // particles (state)
+  double *x, *v, *vprev, *vit, *vnew;
+  // mesh (state)
+  double2* spec[2];  // spectral levels (9 fields each); spec[cur] is level n
+  int cur = 0;
+  double* gbuf;      // interleaved gather fields
+  double* Jb[2];     // orbit current, double-buffered across Picard passes
+  int jlast = 0;     // index of the current of the last accepted pass
+  // workspace
+  double2* Jh;
+  double2* batch;
+  double* realbuf;
+  double* Uhalf;
+  double2* tw[3];
+  Scratch sc;
+  double* host = nullptr;  // pinned read-back
+  // energy bookkeeping
+  double K = 0.0, W = 0.0;
+  ecpic_energy en{};
+  FieldParams fp() const { return FieldParams{G, cfg.dt, cfg.kappa, cfg.sigma1, cfg.sigma2}; }
+  StepParams pp() const { return StepParams{G, cfg.dt, q, m, np}; }
+};
+
+namespace {
+
+void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_bytes) {
+  const int64_t np = S->np, nc = S->G.ncell;
+  const size_t n3 = (size_t)3 * (np > 0 ? np : 1);
+  Carver st{state};
+  S->x = st.take<double>(n3);
+  S->v = st.take<double>(n3);
+  S->vprev = st.take<double>(n3);
+  S->vit = st.take<double>(n3);
+  S->vnew = st.take<double>(n3);
+  S->spec[0] = st.take<double2>(9 * nc);
+  S->spec[1] = st.take<double2>(9 * nc);
+  S->gbuf = st.take<double>(kGbufStride * nc);
+  S->Jb[0] = st.take<double>(3 * nc);
+  S->Jb[1] = st.take<double>(3 * nc);
+  Carver w{ws};
+  S->Jh = w.take<double2>(3 * nc);
+  S->batch = w.take<double2>(9 * nc);
+  S->realbuf = w.take<double>(9 * nc);
+  S->Uhalf = w.take<double>(3 * nc);
+  for (int a = 0; a < 3; ++a) S->tw[a] = w.take<double2>(S->G.n[a] / 2);
+  S->sc.red = w.take<double>(S_NSLOTS);
+  S->sc.ticket = w.take<unsigned>(kNumTickets);
+  const int64_t maxblk = std::max<int64_t>((np + kBlock - 1) / kBlock, (nc + kBlock - 1) / kBlock);
+  S->sc.partials = w.take<double>((size_t)kMaxSumValues * (maxblk > 0 ? maxblk : 1));
+  if (state_bytes) *state_bytes = st.off + 256;
+  if (ws_bytes) *ws_bytes = w.off + 256;
+}
+
+// Real output descriptors for the inverse transform of the step.
+RealIO gather_fields_out(ecpic_sim* S) {
+  RealIO io{};
+  for (int l = 0; l < 3; ++l) {
+    io.p[l] = S->gbuf + l;          // grad_h phi^{n+1/2}
+    io.stride[l] = kGbufStride;
+    io.p[3 + l] = S->gbuf + 6 + l;  // A^{n+1}
+    io.stride[3 + l] = kGbufStride;
+  }
+  return io;
+}
+
+RealIO soa_io(double* base, int64_t nc, int nb) {
+  RealIO io{};
+  for (int b = 0; b < nb; ++b) {
+    io.p[b] = base + b * nc;
+    io.stride[b] = 1;
+  }
+  return io;
+}
+
+const double2* const* twp(ecpic_sim* S) { return S->tw; }
+
+ecpic_status sync_read(ecpic_sim* S, int first, int count) {
+  HIPCHK(hipMemcpyAsync(S->host, S->sc.red + first, sizeof(double) * count, hipMemcpyDeviceToHost,
+                        S->stream));
+  HIPCHK(hipStreamSynchronize(S->stream));
+  return ECPIC_OK;
+}
+
+// forward transform of the 9 real fields in realbuf into spec[cur]; A^n into gbuf
+ecpic_status load_fields_from_realbuf(ecpic_sim* S) {
+  const int64_t nc = S->G.ncell;
+  RealIO in = soa_io(S->realbuf, nc, 9);
+  fft3_forward(S->stream, S->G, 9, S->spec[S->cur], &in, nullptr, twp(S), S->sc);
+  launch_set_A0(S->stream, nc, S->realbuf + 2 * nc, S->gbuf);
+  HIPCHK(hipGetLastError());
+  return ECPIC_OK;
+}
+
+ecpic_status update_level_energies(ecpic_sim* S) {
+  launch_kinetic(S->stream, S->pp(), S->v, S->sc);
+  launch_field_energy(S->stream, S->fp(), S->spec[S->cur], S->sc);
+  HIPCHK(hipGetLastError());
+  if (S->np <= 0) launch_fill(S->stream, 1, S->sc.red + S_K, 0.0);
+  ecpic_status st = sync_read(S, 0, S_NSLOTS);
+  if (st != ECPIC_OK) return st;
+  S->K = S->host[S_K];
+  S->W = S->host[S_WCUR];
+  return ECPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ecpic_status ecpic_state_bytes(const ecpic_config* cfg, int64_t n_particles, size_t* state_bytes,
+                               size_t* workspace_bytes) {
+  ecpic_status st = check_config(cfg, n_particles);
+  if (st != ECPIC_OK) return st;
+  ecpic_sim S;
+  S.cfg = *cfg;
+  S.G = make_grid(cfg);
+  S.np = n_particles;
+  carve(&S, nullptr, nullptr, state_bytes, workspace_bytes);
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* state_dev,
+                          size_t state_bytes, void* workspace_dev, size_t workspace_bytes,
+                          void* hip_stream, ecpic_sim** out) {
+  if (!out) return fail(ECPIC_EINVAL, "null output pointer");
+  *out = nullptr;
+  ecpic_status st = check_config(cfg, n_particles);
+  if (st != ECPIC_OK) return st;
+  size_t need_s = 0, need_w = 0;
+  ecpic_state_bytes(cfg, n_particles, &need_s, &need_w);
+  if (!state_dev || !workspace_dev) return fail(ECPIC_EINVAL, "null device buffer");
+  if (state_bytes < need_s || workspace_bytes < need_w)
+    return fail(ECPIC_ENOMEM, "buffers too small: need state %zu, workspace %zu", need_s, need_w);
+  if ((reinterpret_cast<uintptr_t>(state_dev) & 255) || (reinterpret_cast<uintptr_t>(workspace_dev) & 255))
+    return fail(ECPIC_EINVAL, "device buffers must be 256-byte aligned");
+  ecpic_sim* S = new ecpic_sim();
+  S->cfg = *cfg;
+  S->G = make_grid(cfg);
+  S->np = n_particles;
+  S->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  carve(S, static_cast<char*>(state_dev), static_cast<char*>(workspace_dev), nullptr, nullptr);
+  if (hipHostMalloc(reinterpret_cast<void**>(&S->host), sizeof(double) * S_NSLOTS,
+                    hipHostMallocDefault) != hipSuccess) {
+    delete S;
+    return fail(ECPIC_ENOMEM, "pinned host allocation failed");
+  }
+  // twiddles exp(-2 pi i t / N), t < N/2, computed on the host in double
+  for (int a = 0; a < 3; ++a) {
+    const int N = S->G.n[a];
+    std::vector<double2> t(N / 2);
+    for (int k = 0; k < N / 2; ++k) {
+      const double ang = 2.0 * M_PI * (double)k / (double)N;
+      t[k] = make_double2(std::cos(ang), -std::sin(ang));
+    }
+    if (hipMemcpyAsync(S->tw[a], t.data(), sizeof(double2) * t.size(), hipMemcpyHostToDevice,
+                       S->stream) != hipSuccess ||
+        hipStreamSynchronize(S->stream) != hipSuccess) {
+      (void)hipHostFree(S->host);
+      delete S;
+      return fail(ECPIC_EDEVICE, "twiddle upload failed");
+    }
+  }
+  if (hipMemsetAsync(S->sc.ticket, 0, sizeof(unsigned) * kNumTickets, S->stream) != hipSuccess ||
+      hipMemsetAsync(S->sc.red, 0, sizeof(double) * S_NSLOTS, S->stream) != hipSuccess ||
+      hipStreamSynchronize(S->stream) != hipSuccess) {
+    (void)hipHostFree(S->host);
+    delete S;
+    return fail(ECPIC_EDEVICE, "scratch initialisation failed");
+  }
+  *out = S;
+  return ECPIC_OK;
+}
+
+void ecpic_destroy(ecpic_sim* S) {
+  if (!S) return;
+  if (S->host) (void)hipHostFree(S->host);
+  delete S;
+}
+
+ecpic_status ecpic_init_particles(ecpic_sim* S, const double* x, const double* v, double q,
+                                  double m, double n0) {
+  (void)n0;  // a uniform background only changes the k = 0 mode, which is zeroed
+  if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  if (S->np > 0 && (!x || !v)) return fail(ECPIC_EINVAL, "null particle arrays");
+  if (!(m > 0.0) || !std::isfinite(q)) return fail(ECPIC_EINVAL, "invalid q or m");
+  const int64_t np = S->np, nc = S->G.ncell;
+  S->q = q;
+  S->m = m;
+  if (np > 0) {
+    HIPCHK(hipMemcpyAsync(S->x, x, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipMemcpyAsync(S->v, v, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipMemcpyAsync(S->vprev, v, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
+  }
+  launch_wrap_positions(S->stream, S->pp(), S->x);
+  // rho^0: point-shape deposit, transformed; then the Poisson solve
+  launch_fill(S->stream, nc, S->realbuf, 0.0);
+  launch_deposit_rho(S->stream, S->cfg.spline_degree, S->pp(), S->x, S->realbuf);
+  RealIO in{};
+  in.p[0] = S->realbuf;
+  in.stride[0] = 1;
+  S->cur = 0;
+  fft3_forward(S->stream, S->G, 1, S->spec[0] + 8 * nc, &in, nullptr, twp(S), S->sc);
+  launch_poisson_init(S->stream, S->fp(), S->spec[0]);
+  launch_fill(S->stream, kGbufStride * nc, S->gbuf, 0.0);
+  launch_fill(S->stream, 3 * nc, S->Jb[0], 0.0);
+  launch_fill(S->stream, 3 * nc, S->Jb[1], 0.0);
+  HIPCHK(hipGetLastError());
+  ecpic_status st = update_level_energies(S);
+  if (st != ECPIC_OK) return st;
+  S->en = ecpic_energy{};
+  S->initialized = true;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
+  if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  if (!S->initialized) return fail(ECPIC_ESTATE, "step before init_particles/set_state");
+  const int r = S->cfg.spline_degree;
+  const int64_t nc = S->G.ncell;
+  const StepParams P = S->pp();
+  const FieldParams F = S->fp();
+  hipStream_t s = S->stream;
+  RealIO gout = gather_fields_out(S);
+  double2* cur = S->spec[S->cur];
+  double2* nxt = S->spec[1 - S->cur];
+
+  launch_extrapolate(s, S->np, S->v, S->vprev, S->vit);  // v^{n+1,0} = 2 v^n - v^{n-1}
+  int p = 0, jcur = 1 - S->jlast;
+  bool converged = false;
+  double err_v = 0.0, err_J = INFINITY;
+  for (p = 0; p <= S->cfg.picard_max; ++p) {
+    double* J = S->Jb[jcur];
+    double* Jprev = S->Jb[1 - jcur];
+    launch_reset_slots(s, S->sc.red, S_DVMAX, 5);  // DVMAX, VMAX, DJMAX, JS, BAD
+    launch_fill(s, 3 * nc, J, 0.0);
+    launch_scatter(s, r, P, S->x, S->v, S->vit, J, S->sc);  // J^{n+1/2,p}
+    RealIO jin = soa_io(J, nc, 3);
+    fft3_forward(s, S->G, 3, S->Jh, &jin, p >= 1 ? Jprev : nullptr, twp(S), S->sc);
+    launch_cn_update(s, F, cur, S->Jh, nxt, S->batch, S->sc);  // continuity + CN
+    fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));         // grad phi^{n+1/2}, A^{n+1}
+    launch_gather_push(s, r, P, S->x, S->v, S->vit, S->vnew, S->gbuf, S->sc);  // v^{n+1,p+1}
+    HIPCHK(hipGetLastError());
+    ecpic_status st = sync_read(S, S_DVMAX, 5);
+    if (st != ECPIC_OK) return st;
+    const double dv = S->host[0], vm = S->host[1], dj = S->host[2], js = S->host[3];
+    if (S->host[4] >= 2.0 || S->host[4] != S->host[4])
+      return fail(ECPIC_ENONFINITE, "non-finite velocity in Picard pass %d", p);
+    if (S->host[4] != 0.0)
+      return fail(ECPIC_EINVAL, "an orbit crossed more than %d knots in one step", kMaxPieces - 1);
+    if (!std::isfinite(dv) || !std::isfinite(vm) || !std::isfinite(dj) || !std::isfinite(js))
+      return fail(ECPIC_ENONFINITE, "non-finite velocity or current in Picard pass %d", p);
+    err_v = vm > 0.0 ? dv / vm : dv;
+    err_J = p >= 1 ? (js > 0.0 ? dj / js : dj) : INFINITY;
+    S->jlast = jcur;
+    jcur = 1 - jcur;
+    if (p >= 1 && err_v < S->cfg.picard_tol && err_J < S->cfg.picard_tol) {
+      converged = true;
+      break;
+    }
+    if (p == S->cfg.picard_max) break;
+    std::swap(S->vit, S->vnew);  // next iterate
+  }
+  if (p > S->cfg.picard_max) p = S->cfg.picard_max;
+
+  // consistency sweep of the accepted iterate (its orbit, current and fields)
+  if (S->cfg.diagnostics) {
+    launch_reset_slots(s, S->sc.red, S_RAMAX, 2);
+    launch_half_U(s, S->G, cur, nxt, S->batch);
+    RealIO uo = soa_io(S->Uhalf, nc, 3);
+    fft3_inverse(s, S->G, 3, S->batch, &uo, twp(S));
+    launch_sweep(s, r, P, S->x, S->v, S->vit, S->vnew, S->gbuf, S->Uhalf, S->sc);
+  }
+  // accept: x^{n+1} = x^n + dt vbar^p, v^{n-1} <- v^n, v^n <- v^{n+1,p+1}; fields of pass p
+  launch_finalize(s, P, S->x, S->v, S->vprev, S->vit, S->vnew, S->sc);
+  if (S->np <= 0) {
+    launch_reset_slots(s, S->sc.red, S_K, 2);
+    launch_reset_slots(s, S->sc.red, S_WORK, 2);
+  }
+  launch_accept_A(s, nc, S->gbuf);
+  S->cur = 1 - S->cur;
+  HIPCHK(hipGetLastError());
+  ecpic_status st = sync_read(S, 0, S_NSLOTS);
+  if (st != ECPIC_OK) return st;
+  const double* h = S->host;
+  const double K1 = h[S_K], dK = h[S_DK], W1 = h[S_WNEXT], dW = h[S_DW], JE = h[S_JE];
+  if (!std::isfinite(K1) || !std::isfinite(W1))
+    return fail(ECPIC_ENONFINITE, "non-finite energy after the step");
+  S->en.R_field = dW + S->cfg.dt * JE;
+  S->en.R_total = dK + dW;
+  S->en.JE_mesh = JE;
+  if (S->cfg.diagnostics) {
+    S->en.work_particle = h[S_WORK];
+    S->en.R_particle = dK - S->cfg.dt * h[S_WORK];
+    S->en.RA_rms = S->np > 0 ? std::sqrt(h[S_RA2] / (3.0 * S->np)) : 0.0;
+    S->en.RA_max = h[S_RAMAX];
+    S->en.pou_max = h[S_POU];
+  }
+  S->en.step += 1;
+  S->K = K1;
+  S->W = W1;
+  if (info) {
+    info->iters = p + 1;
+    info->converged = converged ? 1 : 0;
+    info->err_v = err_v;
+    info->err_J = err_J;
+  }
+  return converged ? ECPIC_OK : ECPIC_ENOCONV;
+}
+
+ecpic_status ecpic_field_solve(ecpic_sim* S, const double* J_dev) {
+  if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  if (!S->initialized) return fail(ECPIC_ESTATE, "field solve before init_particles/set_state");
+  const int64_t nc = S->G.ncell;
+  hipStream_t s = S->stream;
+  const double* J = J_dev ? J_dev : S->Jb[S->jlast];
+  if (J_dev) {
+    HIPCHK(hipMemcpyAsync(S->Jb[S->jlast], J_dev, sizeof(double) * 3 * nc,
+                          hipMemcpyDeviceToDevice, s));
+    J = S->Jb[S->jlast];
+  }
+  RealIO jin = soa_io(const_cast<double*>(J), nc, 3);
+  double2* cur = S->spec[S->cur];
+  double2* nxt = S->spec[1 - S->cur];
+  fft3_forward(s, S->G, 3, S->Jh, &jin, nullptr, twp(S), S->sc);
+  launch_cn_update(s, S->fp(), cur, S->Jh, nxt, S->batch, S->sc);
+  RealIO gout = gather_fields_out(S);
+  fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));
+  launch_accept_A(s, nc, S->gbuf);
+  S->cur = 1 - S->cur;
+  HIPCHK(hipGetLastError());
+  ecpic_status st = sync_read(S, 0, S_NSLOTS);
+  if (st != ECPIC_OK) return st;
+  S->en.R_field = S->host[S_DW] + S->cfg.dt * S->host[S_JE];
+  S->en.JE_mesh = S->host[S_JE];
+  S->W = S->host[S_WNEXT];
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_energy_diagnostics(ecpic_sim* S, ecpic_energy* out) {
+  if (!S || !out) return fail(ECPIC_EINVAL, "null argument");
+  if (!S->initialized) return fail(ECPIC_ESTATE, "diagnostics before init_particles/set_state");
+  const int64_t nc = S->G.ncell;
+  hipStream_t s = S->stream;
+  launch_reset_slots(s, S->sc.red, S_GMAX, 2);
+  launch_constraint_spectra(s, S->fp(), S->spec[S->cur], S->batch, S->sc);
+  RealIO o = soa_io(S->realbuf, nc, 2);
+  fft3_inverse(s, S->G, 2, S->batch, &o, twp(S));
+  launch_constraint_norms(s, nc, S->realbuf, S->realbuf + nc, S->sc);
+  HIPCHK(hipGetLastError());
+  ecpic_status st = sync_read(S, 0, S_NSLOTS);
+  if (st != ECPIC_OK) return st;
+  const double* h = S->host;
+  S->en.K = S->K;
+  S->en.W = h[S_WCUR];
+  S->en.E_total = S->en.K + S->en.W;
+  S->en.gauge_max = h[S_GMAX];
+  S->en.gauss_max = h[S_RMAX];
+  S->en.gauge_l2 = std::sqrt(h[S_GL2] / (double)nc);
+  S->en.gauss_l2 = std::sqrt(h[S_RL2] / (double)nc);
+  *out = S->en;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_get_state(ecpic_sim* S, double* x, double* v, double* vprev, double* fields) {
+  if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  const int64_t np = S->np, nc = S->G.ncell;
+  hipStream_t s = S->stream;
+  if (np > 0) {
+    if (x) HIPCHK(hipMemcpyAsync(x, S->x, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s));
+    if (v) HIPCHK(hipMemcpyAsync(v, S->v, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s));
+    if (vprev)
+      HIPCHK(hipMemcpyAsync(vprev, S->vprev, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s));
+  }
+  if (fields) {
+    launch_spec_copy(s, 9 * nc, S->spec[S->cur], S->batch, 1.0 / (double)nc);
+    RealIO o = soa_io(S->realbuf, nc, 9);
+    fft3_inverse(s, S->G, 9, S->batch, &o, twp(S));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(fields, S->realbuf, sizeof(double) * 9 * nc, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_set_state(ecpic_sim* S, const double* x, const double* v, const double* vprev,
+                             const double* fields, double q, double m) {
+  if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  if (!(m > 0.0) || !std::isfinite(q)) return fail(ECPIC_EINVAL, "invalid q or m");
+  const int64_t np = S->np, nc = S->G.ncell;
+  hipStream_t s = S->stream;
+  S->q = q;
+  S->m = m;
+  if (np > 0) {
+    if (x) HIPCHK(hipMemcpyAsync(S->x, x, sizeof(double) * 3 * np, hipMemcpyHostToDevice, s));
+    if (v) HIPCHK(hipMemcpyAsync(S->v, v, sizeof(double) * 3 * np, hipMemcpyHostToDevice, s));
+    if (vprev)
+      HIPCHK(hipMemcpyAsync(S->vprev, vprev, sizeof(double) * 3 * np, hipMemcpyHostToDevice, s));
+  }
+  if (fields) {
+    HIPCHK(hipMemcpyAsync(S->realbuf, fields, sizeof(double) * 9 * nc, hipMemcpyHostToDevice, s));
+    ecpic_status st = load_fields_from_realbuf(S);
+    if (st != ECPIC_OK) return st;
+  } else if (!S->initialized) {
+    for (int b = 0; b < 2; ++b) launch_spec_copy(s, 9 * nc, S->spec[b], S->spec[b], 0.0);
+    launch_fill(s, kGbufStride * nc, S->gbuf, 0.0);
+  }
+  if (!S->initialized) {
+    launch_fill(s, 3 * nc, S->Jb[0], 0.0);
+    launch_fill(s, 3 * nc, S->Jb[1], 0.0);
+  }
+  HIPCHK(hipGetLastError());
+  S->initialized = true;
+  ecpic_status st = update_level_energies(S);
+  if (st != ECPIC_OK) return st;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_get_current(ecpic_sim* S, double* J) {
+  if (!S || !J) return fail(ECPIC_EINVAL, "null argument");
+  HIPCHK(hipMemcpyAsync(J, S->Jb[S->jlast], sizeof(double) * 3 * S->G.ncell,
+                        hipMemcpyDeviceToHost, S->stream));
+  HIPCHK(hipStreamSynchronize(S->stream));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_orbit_gather(const ecpic_config* cfg, int64_t n, const double* x0,
+                                const double* d, const double* gphi, const double* U,
+                                const double* A0, const double* A1, double* out,
+                                void* hip_stream) {
+  ecpic_status st = check_config(cfg, n);
+  if (st != ECPIC_OK) return st;
+  if (n > 0 && (!x0 || !d || !gphi || !U || !A0 || !A1 || !out))
+    return fail(ECPIC_EINVAL, "null device pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  launch_orbit_gather_soa(s, cfg->spline_degree, make_grid(cfg), n, x0, d, gphi, U, A0, A1, out);
+  HIPCHK(hipGetLastError());
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_orbit_deposit(const ecpic_config* cfg, int64_t n, const double* x0,
+                                 const double* d, const double* qv, double* J, void* hip_stream) {
+  ecpic_status st = check_config(cfg, n);
+  if (st != ECPIC_OK) return st;
+  if (n > 0 && (!x0 || !d || !qv || !J)) return fail(ECPIC_EINVAL, "null device pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  launch_orbit_deposit_soa(s, cfg->spline_degree, make_grid(cfg), n, x0, d, qv, J);
+  HIPCHK(hipGetLastError());
+  return ECPIC_OK;
+}
+
+const char* ecpic_last_error(void) { return g_err.c_str(); }
+
+const char* ecpic_version(void) { return "ecpic-gfx950 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Host-side declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "orbit.hpp"
+
+namespace ecpic {
+
+// Reduction slots (doubles) in the device scratch array.
+enum Slot : int {
+  S_DVMAX = 0,  // max_i |v^{p+1} - v^p|_inf            (bit-pattern max)
+  S_VMAX,       // max_i |v^{p+1}|_inf                  (bit-pattern max)
+  S_DJMAX,      // max_g |J^p - J^{p-1}|                (bit-pattern max)
+  S_JS,         // J_s = sum_i |q| |vbar_i|_inf / |Omega| (sum)
+  S_BAD,        // 1: an orbit had too many pieces, 2: a non-finite velocity (max)
+  S_JE,         // sum_g J . E^{n+1/2} dV               (sum)
+  S_WNEXT,      // W of the new field level             (sum)
+  S_DW,         // W^{n+1} - W^n, per-mode differences  (sum)
+  S_K,          // K of the new particle level          (sum)
+  S_DK,         // K^{n+1} - K^n, per-particle differences (sum)
+  S_WORK,       // sum_i q vbar . Ebar                  (sum)
+  S_RA2,        // sum_i |R_A,i|^2                      (sum)
+  S_RAMAX,      // max |R_A|                            (bit-pattern max)
+  S_POU,        // max_i |sum_g Sbar_ig - 1|            (bit-pattern max)
+  S_GMAX,       // max |G_h|                            (bit-pattern max)
+  S_RMAX,       // max |R_h|                            (bit-pattern max)
+  S_GL2,        // sum G_h^2                            (sum)
+  S_RL2,        // sum R_h^2                            (sum)
+  S_WCUR,       // W of the current field level         (sum)
+  S_NSLOTS
+};
+constexpr int kNumTickets = 8;
+
+struct StepParams {
+  Grid G;
+  double dt, q, m;
+  int64_t np;
+};
+
+struct Scratch {
+  double* red;       // S_NSLOTS
+  unsigned* ticket;  // kNumTickets
+  double* partials;  // max_values * max_blocks
+};
+
+// ---- particle kernels (particles.hip) ----
+void launch_extrapolate(hipStream_t s, int64_t np, const double* v, const double* vprev,
+                        double* vit);
+void launch_scatter(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
+                    const double* vit, double* J, Scratch sc);
+void launch_gather_push(hipStream_t s, int r, const StepParams& P, const double* x,
+                        const double* v, const double* vit, double* vnew, const double* gbuf,
+                        Scratch sc);
+void launch_sweep(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
+                  const double* vit, const double* vnew, const double* gbuf, const double* Uhalf,
+                  Scratch sc);
+void launch_finalize(hipStream_t s, const StepParams& P, double* x, double* v, double* vprev,
+                     const double* vit, const double* vnew, Scratch sc);
+void launch_kinetic(hipStream_t s, const StepParams& P, const double* v, Scratch sc);
+void launch_wrap_positions(hipStream_t s, const StepParams& P, double* x);
+void launch_deposit_rho(hipStream_t s, int r, const StepParams& P, const double* x, double* rho);
+void launch_orbit_gather_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
+                             const double* d, const double* gphi, const double* U,
+                             const double* A0, const double* A1, double* out);
+void launch_orbit_deposit_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
+                              const double* d, const double* qv, double* J);
+
+// ---- mesh kernels (mesh.hip) ----
+constexpr int kMaxBatch = 9;
+struct RealIO {
+  double* p[kMaxBatch];
+  int64_t stride[kMaxBatch];
+};
+
+// 3D FFT of nb fields held as complex arrays data[b*ncell + g], z fastest.
+// forward: real input from `in` (may be nullptr for complex in-place), and
+// optionally max|in - prev| folded into S_DJMAX.  inverse: real part of the
+// result to `out` (nullptr keeps the complex result in place).
+void fft3_forward(hipStream_t s, const Grid& G, int nb, double2* data, const RealIO* in,
+                  const double* prev, const double2* const* tw, Scratch sc);
+void fft3_inverse(hipStream_t s, const Grid& G, int nb, double2* data, const RealIO* out,
+                  const double2* const* tw);
+
+struct FieldParams {
+  Grid G;
+  double dt, kappa, sigma1, sigma2;
+};
+
+// Continuity + CN update of every mode; writes the next spectral level, the
+// inverse-transform inputs [i k (phi0+phi1)/2, A1] / ncell, and S_JE, S_WNEXT,
+// S_DW.
+void launch_cn_update(hipStream_t s, const FieldParams& F, const double2* cur, const double2* Jh,
+                      double2* next, double2* inv, Scratch sc);
+// (U0 + U1)/2 / ncell into inv[0..2]
+void launch_half_U(hipStream_t s, const Grid& G, const double2* cur, const double2* next,
+                   double2* inv);
+// Initial potentials from a forward-transformed charge in cur[8*ncell..].
+void launch_poisson_init(hipStream_t s, const FieldParams& F, double2* cur);
+// G_h and R_h spectra / ncell into inv[0..1]; W of cur into S_WCUR.
+void launch_constraint_spectra(hipStream_t s, const FieldParams& F, const double2* cur,
+                               double2* inv, Scratch sc);
+void launch_field_energy(hipStream_t s, const FieldParams& F, const double2* cur, Scratch sc);
+// max|f| and sum f^2 of two real arrays into (S_GMAX, S_GL2), (S_RMAX, S_RL2)
+void launch_constraint_norms(hipStream_t s, int64_t ncell, const double* g, const double* r,
+                             Scratch sc);
+// scale-copy nb spectral fields: dst[b] = src[b] * scale
+void launch_spec_copy(hipStream_t s, int64_t count, const double2* src, double2* dst, double scale);
+// gbuf A0 slots <- A1 slots
+void launch_accept_A(hipStream_t s, int64_t ncell, double* gbuf);
+// gbuf A0 slots <- real A (3 x ncell)
+void launch_set_A0(hipStream_t s, int64_t ncell, const double* A, double* gbuf);
+void launch_fill(hipStream_t s, int64_t count, double* p, double value);
+void launch_reset_slots(hipStream_t s, double* red, int first, int count);
+
+constexpr int kGbufStride = 10;  // [gphi x,y,z | A^n x,y,z | A^{n+1} x,y,z | pad]
+
+}  // namespace ecpic

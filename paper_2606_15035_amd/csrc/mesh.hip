@@ -1,0 +1,514 @@
+// Mesh-side kernels for gfx950: batched radix-2 FFT passes in LDS, the
+// per-mode continuity + Crank-Nicolson update, the initial Poisson solve and
+// the Parseval / constraint reductions.
+//
+// Spectral fields are full complex spectra data[b*ncell + g] with the node /
+// mode index g = (ix*Ny + iy)*Nz + iz.  The Fourier symbol of d/dx_a at mode
+// index m is i k~ with k~ = 2 pi m_s / L_a, m_s the signed index, and
+// k~ = 0 on the Nyquist index; Delta_h -> -|k~|^2 (Sec. 3.3).  Forward
+// transforms are unnormalised; the 1/ncell of the inverse is folded into the
+// kernel that prepares its input.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "reduce.hpp"
+
+namespace ecpic {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// i * k * a
+__device__ __forceinline__ double2 ik(double k, double2 a) { return make_double2(-k * a.y, k * a.x); }
+
+struct FftPass {
+  double2* data;
+  const double2* tw;  // exp(-2 pi i t / N), t < N/2
+  int64_t ncell;
+  int64_t stride;     // distance between consecutive elements of a pencil
+  int64_t npb;        // pencils per batch field = ncell / N
+  int64_t npencils;   // nb * npb
+  int N, logN;
+  double sgn;         // -1 forward, +1 inverse (sign of the exponent)
+  RealIO io;          // real input (forward first pass) or output (inverse last pass)
+  const double* prev; // optional: max |in - prev| -> S_DJMAX
+  double* red;
+};
+
+// MODE 0: complex in place; 1: real input -> complex; 2: complex -> real output.
+// Each block transforms 256 / (N/2) pencils held in LDS; one thread per
+// butterfly; input in bit-reversed order, decimation in time.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_fft(FftPass A) {
+  __shared__ double2 buf[2 * kBlock];
+  const int N = A.N, half = N >> 1, P = kBlock / half;
+  const int t = threadIdx.x;
+  int pl, j;
+  if (A.stride == 1) {
+    pl = t / half;
+    j = t % half;
+  } else {
+    pl = t % P;
+    j = t / P;
+  }
+  const int64_t pencil = (int64_t)blockIdx.x * P + pl;
+  const bool active = pencil < A.npencils;
+  int64_t b = 0, off = 0;
+  if (active) {
+    b = pencil / A.npb;
+    const int64_t pin = pencil % A.npb;
+    const int64_t outer = pin / A.stride, inner = pin % A.stride;
+    off = outer * N * A.stride + inner;
+  }
+  double2* lds = buf + pl * N;
+  double dmax = 0.0;
+  if (active) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = j + h * half;
+      const int64_t g = off + e * A.stride;
+      double2 val;
+      if constexpr (MODE == 1) {
+        const double re = A.io.p[b][g * A.io.stride[b]];
+        if (A.prev) dmax = fmax(dmax, fabs(re - A.prev[b * A.ncell + g]));
+        val = make_double2(re, 0.0);
+      } else {
+        val = A.data[b * A.ncell + g];
+      }
+      lds[__brev((unsigned)e) >> (32 - A.logN)] = val;
+    }
+  }
+  __syncthreads();
+  for (int hs = 1; hs < N; hs <<= 1) {
+    if (active) {
+      const int pos = j % hs;
+      const int i0 = (j / hs) * 2 * hs + pos, i1 = i0 + hs;
+      double2 w = A.tw[pos * (half / hs)];  // exp(-2 pi i pos / (2 hs))
+      if (A.sgn > 0.0) w.y = -w.y;           // inverse: conjugate twiddle
+      const double2 a = lds[i0];
+      const double2 bb = cmul(lds[i1], w);
+      lds[i0] = cadd(a, bb);
+      lds[i1] = csub(a, bb);
+    }
+    __syncthreads();
+  }
+  if (active) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = j + h * half;
+      const int64_t g = off + e * A.stride;
+      if constexpr (MODE == 2)
+        A.io.p[b][g * A.io.stride[b]] = lds[e].x;
+      else
+        A.data[b * A.ncell + g] = lds[e];
+    }
+  }
+  if constexpr (MODE == 1) {
+    if (A.prev) block_max_to(dmax, A.red + S_DJMAX);
+  }
+}
+
+__device__ __forceinline__ double ktil(int m, int N, double L) {
+  if (2 * m == N) return 0.0;
+  const int ms = (2 * m < N) ? m : m - N;
+  return 6.283185307179586476925286766559 * (double)ms / L;
+}
+
+__device__ __forceinline__ void mode_k(const Grid& G, int64_t g, double* k) {
+  const int iz = (int)(g % G.n[2]);
+  const int iy = (int)((g / G.n[2]) % G.n[1]);
+  const int ix = (int)(g / ((int64_t)G.n[2] * G.n[1]));
+  k[0] = ktil(ix, G.n[0], G.L[0]);
+  k[1] = ktil(iy, G.n[1], G.L[1]);
+  k[2] = ktil(iz, G.n[2], G.L[2]);
+}
+
+// field order in a spectral level: phi, psi, Ax, Ay, Az, Ux, Uy, Uz, rho
+enum { F_PHI = 0, F_PSI = 1, F_A = 2, F_U = 5, F_RHO = 8 };
+
+__device__ __forceinline__ double2 ld(const double2* p, int f, int64_t nc, int64_t g) {
+  return p[f * nc + g];
+}
+
+// |E|^2 / (2 sigma1) + |B|^2 / (2 sigma2) of one mode (E = -i k phi - U, B = i k x A)
+__device__ __forceinline__ double mode_energy(const double* k, double2 phi, const double2* A,
+                                              const double2* U, double h1, double h2) {
+  double e = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double2 E = csub(make_double2(k[l] * phi.y, -k[l] * phi.x), U[l]);
+    e += h1 * (E.x * E.x + E.y * E.y);
+  }
+  const double2 B0 = csub(ik(k[1], A[2]), ik(k[2], A[1]));
+  const double2 B1 = csub(ik(k[2], A[0]), ik(k[0], A[2]));
+  const double2 B2 = csub(ik(k[0], A[1]), ik(k[1], A[0]));
+  e += h2 * (B0.x * B0.x + B0.y * B0.y + B1.x * B1.x + B1.y * B1.y + B2.x * B2.x + B2.y * B2.y);
+  return e;
+}
+
+// Continuity (eq. cn-continuity) and CN (eq. cn-field-update) for every mode:
+//   rho1 = rho0 - dt i k.J,  rho_h = (rho0 + rho1)/2,
+//   psi1 = [(1 - a^2 w^2) psi0 - 2 a w^2 phi0 + dt kappa^2 sigma1 rho_h] / (1 + a^2 w^2),
+//   phi1 = phi0 + a (psi0 + psi1),  a = dt/2, w^2 = kappa^2 |k|^2,
+// and (A_l, U_l) likewise with sigma2 J_l.  The closed form is the exact
+// inverse of the 2x2 CN system of each (value, rate) pair.
+struct CNArgs {
+  FieldParams F;
+  const double2* cur;
+  const double2* Jh;
+  double2* next;
+  double2* inv;
+  Scratch sc;
+};
+
+__global__ __launch_bounds__(kBlock) void k_cn(CNArgs C) {
+  const Grid& G = C.F.G;
+  const int64_t nc = G.ncell;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double sums[3] = {0.0, 0.0, 0.0};  // JE, W^{n+1}, W^{n+1} - W^n (before the dV/ncell factor)
+  if (g < nc) {
+    double k[3];
+    mode_k(G, g, k);
+    const double dt = C.F.dt, a = 0.5 * dt, kap2 = C.F.kappa * C.F.kappa;
+    const double w2 = kap2 * (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    const double inv_den = 1.0 / (1.0 + a * a * w2);
+    const double c_old = 1.0 - a * a * w2, c_x = 2.0 * a * w2;
+    double2 J[3], A0[3], U0[3], A1[3], U1[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      J[l] = C.Jh[l * nc + g];
+      A0[l] = ld(C.cur, F_A + l, nc, g);
+      U0[l] = ld(C.cur, F_U + l, nc, g);
+    }
+    const double2 phi0 = ld(C.cur, F_PHI, nc, g), psi0 = ld(C.cur, F_PSI, nc, g);
+    const double2 rho0 = ld(C.cur, F_RHO, nc, g);
+    const double2 divJ = cadd(cadd(ik(k[0], J[0]), ik(k[1], J[1])), ik(k[2], J[2]));
+    const double2 rho1 = csub(rho0, cscale(divJ, dt));
+    const double2 rhoh = cscale(cadd(rho0, rho1), 0.5);
+    const double src1 = dt * kap2 * C.F.sigma1, src2 = dt * kap2 * C.F.sigma2;
+    double2 psi1, phi1;
+    psi1.x = (c_old * psi0.x - c_x * phi0.x + src1 * rhoh.x) * inv_den;
+    psi1.y = (c_old * psi0.y - c_x * phi0.y + src1 * rhoh.y) * inv_den;
+    phi1 = cadd(phi0, cscale(cadd(psi0, psi1), a));
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      U1[l].x = (c_old * U0[l].x - c_x * A0[l].x + src2 * J[l].x) * inv_den;
+      U1[l].y = (c_old * U0[l].y - c_x * A0[l].y + src2 * J[l].y) * inv_den;
+      A1[l] = cadd(A0[l], cscale(cadd(U0[l], U1[l]), a));
+    }
+    double2* nx = C.next;
+    nx[F_PHI * nc + g] = phi1;
+    nx[F_PSI * nc + g] = psi1;
+    nx[F_RHO * nc + g] = rho1;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      nx[(F_A + l) * nc + g] = A1[l];
+      nx[(F_U + l) * nc + g] = U1[l];
+    }
+    // inverse-transform inputs: grad_h phi^{n+1/2} and A^{n+1}, scaled by 1/ncell
+    const double sc = 1.0 / (double)nc;
+    const double2 phih = cscale(cadd(phi0, phi1), 0.5);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      C.inv[l * nc + g] = cscale(ik(k[l], phih), sc);
+      C.inv[(3 + l) * nc + g] = cscale(A1[l], sc);
+    }
+    // Parseval: sum_g f_g h_g = (1/ncell) sum_k Re(conj(f^_k) h^_k)
+    const double h1 = 0.5 / C.F.sigma1, h2 = 0.5 / C.F.sigma2;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const double2 Uh = cscale(cadd(U0[l], U1[l]), 0.5);
+      const double2 Eh = csub(make_double2(k[l] * phih.y, -k[l] * phih.x), Uh);  // -i k phi - U
+      sums[0] += J[l].x * Eh.x + J[l].y * Eh.y;
+    }
+    const double e1 = mode_energy(k, phi1, A1, U1, h1, h2);
+    sums[1] = e1;
+    // W^{n+1} - W^n per mode as (f1 - f0).(f1 + f0) to keep the difference accurate
+    {
+      double de = 0.0;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const double2 E1 = csub(make_double2(k[l] * phi1.y, -k[l] * phi1.x), U1[l]);
+        const double2 E0 = csub(make_double2(k[l] * phi0.y, -k[l] * phi0.x), U0[l]);
+        const double2 dE = csub(E1, E0), sE = cadd(E1, E0);
+        de += h1 * (dE.x * sE.x + dE.y * sE.y);
+      }
+      double2 dA[3], sA[3];
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        dA[l] = csub(A1[l], A0[l]);
+        sA[l] = cadd(A1[l], A0[l]);
+      }
+      const double2 dB[3] = {csub(ik(k[1], dA[2]), ik(k[2], dA[1])),
+                             csub(ik(k[2], dA[0]), ik(k[0], dA[2])),
+                             csub(ik(k[0], dA[1]), ik(k[1], dA[0]))};
+      const double2 sB[3] = {csub(ik(k[1], sA[2]), ik(k[2], sA[1])),
+                             csub(ik(k[2], sA[0]), ik(k[0], sA[2])),
+                             csub(ik(k[0], sA[1]), ik(k[1], sA[0]))};
+#pragma unroll
+      for (int l = 0; l < 3; ++l) de += h2 * (dB[l].x * sB[l].x + dB[l].y * sB[l].y);
+      sums[2] = de;
+    }
+    const double f = G.dV / (double)nc;
+    sums[0] *= f;
+    sums[1] *= f;
+    sums[2] *= f;
+  }
+  grid_sum<3>(sums, C.sc.partials, C.sc.ticket + 3, C.sc.red + S_JE);  // S_JE, S_WNEXT, S_DW
+}
+
+__global__ __launch_bounds__(kBlock) void k_half_U(Grid G, const double2* cur, const double2* next,
+                                                  double2* inv) {
+  const int64_t nc = G.ncell;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= nc) return;
+  const double sc = 0.5 / (double)nc;
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+    inv[l * nc + g] = cscale(cadd(cur[(F_U + l) * nc + g], next[(F_U + l) * nc + g]), sc);
+}
+
+// phi^0 from -Delta_h phi = sigma1 rho on modes with k~ != 0; rho and phi zero
+// on every mode where k~ = 0 (this removes the mean and the uniform
+// background); psi = A = U = 0.
+__global__ __launch_bounds__(kBlock) void k_poisson_init(FieldParams F, double2* cur) {
+  const Grid& G = F.G;
+  const int64_t nc = G.ncell;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= nc) return;
+  double k[3];
+  mode_k(G, g, k);
+  const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+  double2 rho = cur[F_RHO * nc + g];
+  double2 phi = make_double2(0.0, 0.0);
+  if (k2 == 0.0)
+    rho = make_double2(0.0, 0.0);
+  else
+    phi = cscale(rho, F.sigma1 / k2);
+  cur[F_RHO * nc + g] = rho;
+  cur[F_PHI * nc + g] = phi;
+  cur[F_PSI * nc + g] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    cur[(F_A + l) * nc + g] = make_double2(0.0, 0.0);
+    cur[(F_U + l) * nc + g] = make_double2(0.0, 0.0);
+  }
+}
+
+// G_h = psi/kappa^2 + i k.A and R_h = i k.E - sigma1 rho (E = -i k phi - U),
+// scaled by 1/ncell, and W of the level.
+__global__ __launch_bounds__(kBlock) void k_constraints(FieldParams F, const double2* cur,
+                                                       double2* inv, Scratch sc) {
+  const Grid& G = F.G;
+  const int64_t nc = G.ncell;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double w[1] = {0.0};
+  if (g < nc) {
+    double k[3];
+    mode_k(G, g, k);
+    const double2 phi = cur[F_PHI * nc + g], psi = cur[F_PSI * nc + g], rho = cur[F_RHO * nc + g];
+    double2 A[3], U[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      A[l] = cur[(F_A + l) * nc + g];
+      U[l] = cur[(F_U + l) * nc + g];
+    }
+    const double kap2 = F.kappa * F.kappa;
+    double2 gh = cscale(psi, 1.0 / kap2);
+    double2 divE = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      gh = cadd(gh, ik(k[l], A[l]));
+      const double2 E = csub(make_double2(k[l] * phi.y, -k[l] * phi.x), U[l]);
+      divE = cadd(divE, ik(k[l], E));
+    }
+    const double2 rh = csub(divE, cscale(rho, F.sigma1));
+    const double s = 1.0 / (double)nc;
+    inv[g] = cscale(gh, s);
+    inv[nc + g] = cscale(rh, s);
+    w[0] = mode_energy(k, phi, A, U, 0.5 / F.sigma1, 0.5 / F.sigma2) * G.dV / (double)nc;
+  }
+  grid_sum<1>(w, sc.partials, sc.ticket + 4, sc.red + S_WCUR);
+}
+
+__global__ __launch_bounds__(kBlock) void k_field_energy(FieldParams F, const double2* cur,
+                                                        Scratch sc) {
+  const Grid& G = F.G;
+  const int64_t nc = G.ncell;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double w[1] = {0.0};
+  if (g < nc) {
+    double k[3];
+    mode_k(G, g, k);
+    double2 A[3], U[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      A[l] = cur[(F_A + l) * nc + g];
+      U[l] = cur[(F_U + l) * nc + g];
+    }
+    w[0] = mode_energy(k, cur[F_PHI * nc + g], A, U, 0.5 / F.sigma1, 0.5 / F.sigma2) * G.dV /
+           (double)nc;
+  }
+  grid_sum<1>(w, sc.partials, sc.ticket + 4, sc.red + S_WCUR);
+}
+
+__global__ __launch_bounds__(kBlock) void k_norms(int64_t nc, const double* gf, const double* rf,
+                                                 Scratch sc) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double gv = 0.0, rv = 0.0;
+  if (g < nc) {
+    gv = gf[g];
+    rv = rf[g];
+  }
+  block_max_to(fabs(gv), sc.red + S_GMAX);
+  block_max_to(fabs(rv), sc.red + S_RMAX);
+  double s[2] = {gv * gv, rv * rv};
+  grid_sum<2>(s, sc.partials, sc.ticket + 5, sc.red + S_GL2);  // S_GL2, S_RL2 adjacent
+}
+
+__global__ __launch_bounds__(kBlock) void k_spec_copy(int64_t n, const double2* src, double2* dst,
+                                                     double scale) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) dst[i] = cscale(src[i], scale);
+}
+
+__global__ __launch_bounds__(kBlock) void k_accept_A(int64_t nc, double* gbuf) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= nc) return;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) gbuf[g * kGbufStride + 3 + l] = gbuf[g * kGbufStride + 6 + l];
+}
+
+__global__ __launch_bounds__(kBlock) void k_set_A0(int64_t nc, const double* A, double* gbuf) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= nc) return;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    gbuf[g * kGbufStride + 3 + l] = A[l * nc + g];
+    gbuf[g * kGbufStride + 6 + l] = A[l * nc + g];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, double* p, double v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+// One pass along `axis` over nb batch fields.
+template <int MODE>
+void fft_pass(hipStream_t s, const Grid& G, int nb, double2* data, int axis, double sgn,
+              const double2* tw, const RealIO* io, const double* prev, double* red) {
+  FftPass A;
+  A.data = data;
+  A.tw = tw;
+  A.ncell = G.ncell;
+  A.N = G.n[axis];
+  A.logN = ilog2(A.N);
+  int64_t stride = 1;
+  for (int a = axis + 1; a < 3; ++a) stride *= G.n[a];
+  A.stride = stride;
+  A.npb = G.ncell / A.N;
+  A.npencils = (int64_t)nb * A.npb;
+  A.sgn = sgn;
+  if (io) A.io = *io;
+  else
+    for (int b = 0; b < kMaxBatch; ++b) {
+      A.io.p[b] = nullptr;
+      A.io.stride[b] = 1;
+    }
+  A.prev = prev;
+  A.red = red;
+  const int P = kBlock / (A.N / 2);
+  const unsigned nblk = (unsigned)((A.npencils + P - 1) / P);
+  k_fft<MODE><<<nblk, kBlock, 0, s>>>(A);
+}
+
+}  // namespace
+
+void fft3_forward(hipStream_t s, const Grid& G, int nb, double2* data, const RealIO* in,
+                  const double* prev, const double2* const* tw, Scratch sc) {
+  // z (contiguous) first, reading the real input; then y and x in place
+  if (in)
+    fft_pass<1>(s, G, nb, data, 2, -1.0, tw[2], in, prev, sc.red);
+  else
+    fft_pass<0>(s, G, nb, data, 2, -1.0, tw[2], nullptr, nullptr, sc.red);
+  fft_pass<0>(s, G, nb, data, 1, -1.0, tw[1], nullptr, nullptr, sc.red);
+  fft_pass<0>(s, G, nb, data, 0, -1.0, tw[0], nullptr, nullptr, sc.red);
+}
+
+void fft3_inverse(hipStream_t s, const Grid& G, int nb, double2* data, const RealIO* out,
+                  const double2* const* tw) {
+  fft_pass<0>(s, G, nb, data, 0, +1.0, tw[0], nullptr, nullptr, nullptr);
+  fft_pass<0>(s, G, nb, data, 1, +1.0, tw[1], nullptr, nullptr, nullptr);
+  if (out)
+    fft_pass<2>(s, G, nb, data, 2, +1.0, tw[2], out, nullptr, nullptr);
+  else
+    fft_pass<0>(s, G, nb, data, 2, +1.0, tw[2], nullptr, nullptr, nullptr);
+}
+
+void launch_cn_update(hipStream_t s, const FieldParams& F, const double2* cur, const double2* Jh,
+                      double2* next, double2* inv, Scratch sc) {
+  CNArgs C{F, cur, Jh, next, inv, sc};
+  k_cn<<<blocks_for(F.G.ncell), kBlock, 0, s>>>(C);
+}
+
+void launch_half_U(hipStream_t s, const Grid& G, const double2* cur, const double2* next,
+                   double2* inv) {
+  k_half_U<<<blocks_for(G.ncell), kBlock, 0, s>>>(G, cur, next, inv);
+}
+
+void launch_poisson_init(hipStream_t s, const FieldParams& F, double2* cur) {
+  k_poisson_init<<<blocks_for(F.G.ncell), kBlock, 0, s>>>(F, cur);
+}
+
+void launch_constraint_spectra(hipStream_t s, const FieldParams& F, const double2* cur,
+                               double2* inv, Scratch sc) {
+  k_constraints<<<blocks_for(F.G.ncell), kBlock, 0, s>>>(F, cur, inv, sc);
+}
+
+void launch_field_energy(hipStream_t s, const FieldParams& F, const double2* cur, Scratch sc) {
+  k_field_energy<<<blocks_for(F.G.ncell), kBlock, 0, s>>>(F, cur, sc);
+}
+
+void launch_constraint_norms(hipStream_t s, int64_t ncell, const double* g, const double* r,
+                             Scratch sc) {
+  k_norms<<<blocks_for(ncell), kBlock, 0, s>>>(ncell, g, r, sc);
+}
+
+void launch_spec_copy(hipStream_t s, int64_t count, const double2* src, double2* dst,
+                      double scale) {
+  if (count <= 0) return;
+  k_spec_copy<<<blocks_for(count), kBlock, 0, s>>>(count, src, dst, scale);
+}
+
+void launch_accept_A(hipStream_t s, int64_t ncell, double* gbuf) {
+  k_accept_A<<<blocks_for(ncell), kBlock, 0, s>>>(ncell, gbuf);
+}
+
+void launch_set_A0(hipStream_t s, int64_t ncell, const double* A, double* gbuf) {
+  k_set_A0<<<blocks_for(ncell), kBlock, 0, s>>>(ncell, A, gbuf);
+}
+
+void launch_fill(hipStream_t s, int64_t count, double* p, double value) {
+  if (count <= 0) return;
+  k_fill<<<blocks_for(count), kBlock, 0, s>>>(count, p, value);
+}
+
+void launch_reset_slots(hipStream_t s, double* red, int first, int count) {
+  launch_fill(s, count, red + first, 0.0);
+}
+
+}  // namespace ecpic

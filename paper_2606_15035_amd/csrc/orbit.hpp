@@ -1,0 +1,206 @@
+// Device-side particle shapes and orbit segmentation for gfx950.
+//
+// Shapes: centred cardinal B-splines of degree r on nodes x_g = g H
+// (eq. Ah-mesh).  A point at cell coordinate u = x / H is written against a
+// base node: degree 1 uses floor(u) and the two nodes {base, base+1};
+// degree 2 uses the nearest node floor(u + 1/2) and {base-1, base, base+1}.
+// Knots sit at integer u (degree 1) and half-integer u (degree 2).
+//
+// Orbits: x(s) = x0 + s d, 0 <= s <= 1, with unwrapped displacement d
+// (eq. particle-orbit).  The breakpoints are the parameters s in (0, 1) where
+// one coordinate crosses a knot (eq. breakpoint-set); the three per-axis
+// crossing sequences are each monotone in s, so they are merged on the fly
+// (no list is stored) and equal values from different axes collapse into one
+// breakpoint.  Every piece between breakpoints is integrated with an n_q-point
+// Gauss-Legendre rule against the polynomial pieces of the stencil found at
+// the piece midpoint; 2 n_q - 1 >= 3 r makes this exact (Sec. 4.7).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ecpic {
+
+struct Grid {
+  int n[3];
+  double L[3];
+  double H[3];
+  double invH[3];
+  double dV;
+  double vol;
+  int64_t ncell;
+};
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Convert a floor()ed double to int without undefined behaviour for huge or
+// non-finite values (clamped; such particles are flagged elsewhere).
+__device__ __forceinline__ int to_int_clamped(double f) {
+  f = fmin(fmax(f, -1.0e9), 1.0e9);
+  return (int)f;
+}
+
+__device__ __forceinline__ double wrap_pos(double x, double L) {
+  double w = x - L * floor(x / L);
+  if (w < 0.0) w += L;
+  if (w >= L) w -= L;
+  return w;
+}
+
+template <int R>
+struct Spline;
+
+template <>
+struct Spline<1> {
+  static constexpr int W = 2;
+  static constexpr double knot_off = 0.0;  // knots at u = k
+  static constexpr double base_off = 0.0;  // base = floor(u)
+  static constexpr int first_off = 0;      // stencil = {base, base + 1}
+  __device__ __forceinline__ static void w(double t, double* o) {
+    o[0] = 1.0 - t;
+    o[1] = t;
+  }
+  __device__ __forceinline__ static void wd(double t, double* o, double* d) {
+    o[0] = 1.0 - t;
+    o[1] = t;
+    d[0] = -1.0;
+    d[1] = 1.0;
+  }
+};
+
+template <>
+struct Spline<2> {
+  static constexpr int W = 3;
+  static constexpr double knot_off = 0.5;  // knots at u = k + 1/2
+  static constexpr double base_off = 0.5;  // base = floor(u + 1/2)
+  static constexpr int first_off = -1;     // stencil = {base - 1, base, base + 1}
+  __device__ __forceinline__ static void w(double t, double* o) {
+    const double a = 0.5 - t, b = 0.5 + t;
+    o[0] = 0.5 * a * a;
+    o[1] = 0.75 - t * t;
+    o[2] = 0.5 * b * b;
+  }
+  __device__ __forceinline__ static void wd(double t, double* o, double* d) {
+    const double a = 0.5 - t, b = 0.5 + t;
+    o[0] = 0.5 * a * a;
+    o[1] = 0.75 - t * t;
+    o[2] = 0.5 * b * b;
+    d[0] = -a;
+    d[1] = -2.0 * t;
+    d[2] = b;
+  }
+};
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Abramowitz & Stegun, Table 25.4).
+template <int NQ>
+struct Gauss;
+
+template <>
+struct Gauss<2> {
+  __device__ __forceinline__ static double x(int q) {
+    return q == 0 ? -0.57735026918962576451 : 0.57735026918962576451;
+  }
+  __device__ __forceinline__ static double w(int) { return 1.0; }
+};
+
+template <>
+struct Gauss<4> {
+  __device__ __forceinline__ static double x(int q) {
+    const double a = 0.86113631159405257522, b = 0.33998104358485626480;
+    return q == 0 ? -a : (q == 1 ? -b : (q == 2 ? b : a));
+  }
+  __device__ __forceinline__ static double w(int q) {
+    const double wa = 0.34785484513745385737, wb = 0.65214515486254614263;
+    return (q == 0 || q == 3) ? wa : wb;
+  }
+};
+
+// Streaming merge of the three per-axis knot-crossing sequences of an orbit.
+template <int R>
+struct Crossings {
+  double sn[3];   // next crossing parameter per axis (>= 2 when exhausted)
+  double knot[3]; // cell coordinate of that knot
+  double dir[3];
+  double x0[3], d[3], H[3];
+
+  __device__ __forceinline__ double s_of(int a) const { return (knot[a] * H[a] - x0[a]) / d[a]; }
+
+  __device__ __forceinline__ void init(const double* x0_, const double* d_, const Grid& G) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      x0[a] = x0_[a];
+      d[a] = d_[a];
+      H[a] = G.H[a];
+      sn[a] = 2.0;
+      knot[a] = 0.0;
+      dir[a] = 0.0;
+      if (d[a] != 0.0) {
+        const double u0 = x0[a] * G.invH[a];
+        const double off = Spline<R>::knot_off;
+        if (d[a] > 0.0) {
+          dir[a] = 1.0;
+          knot[a] = floor(u0 - off) - 1.0 + off;
+        } else {
+          dir[a] = -1.0;
+          knot[a] = floor(u0 - off) + 1.0 + off;
+        }
+        double s = s_of(a);
+        for (int it = 0; it < 4 && !(s > 0.0); ++it) {
+          knot[a] += dir[a];
+          s = s_of(a);
+        }
+        sn[a] = (s > 0.0 && s < 1.0) ? s : 2.0;
+      }
+    }
+  }
+
+  __device__ __forceinline__ double next() const {
+    return fmin(fmin(sn[0], sn[1]), fmin(sn[2], 1.0));
+  }
+
+  __device__ __forceinline__ void consume(double s1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (sn[a] == s1) {
+        knot[a] += dir[a];
+        const double s = s_of(a);
+        sn[a] = (s > sn[a] && s < 1.0) ? s : 2.0;
+      }
+    }
+  }
+};
+
+constexpr int kMaxPieces = 64;
+
+// Calls f(s0, s1) for every piece [s0, s1] of positive length, in order.
+// Returns false if the orbit had more than kMaxPieces pieces (the rest is
+// skipped; the caller flags the particle).
+template <int R, class F>
+__device__ __forceinline__ bool for_each_piece(const double* x0, const double* d, const Grid& G,
+                                               F&& f) {
+  Crossings<R> c;
+  c.init(x0, d, G);
+  double s0 = 0.0;
+  for (int k = 0; k < kMaxPieces; ++k) {
+    const double s1 = c.next();
+    if (s1 > s0) f(s0, s1);
+    if (s1 >= 1.0) return true;
+    c.consume(s1);
+    s0 = s1;
+  }
+  return false;
+}
+
+// Base node of the stencil of a piece, from its midpoint.
+template <int R>
+__device__ __forceinline__ void piece_base(const double* x0, const double* d, double smid,
+                                           const Grid& G, double* base) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    base[a] = floor((x0[a] + smid * d[a]) * G.invH[a] + Spline<R>::base_off);
+}
+
+}  // namespace ecpic

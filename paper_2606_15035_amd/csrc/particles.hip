@@ -1,0 +1,608 @@
+// Particle-side kernels for gfx950: orbit current scatter, orbit gather with
+// the orbit-discrete gradient and canonical-momentum push, the consistency
+// sweep, and the end-of-step update.
+//
+// One lane per particle; particle arrays are structure-of-arrays doubles
+// (component a of particle i at a*np + i).  The mesh fields a particle reads
+// during the gather are interleaved per node (kGbufStride doubles per node:
+// grad_h phi^{n+1/2}, A^n, A^{n+1}) so that one stencil node costs one short
+// run of contiguous loads.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "orbit.hpp"
+#include "reduce.hpp"
+
+namespace ecpic {
+
+namespace {
+
+template <int R>
+struct Quad;
+template <>
+struct Quad<1> {
+  static constexpr int NQ = 2;  // 2 n_q - 1 >= 3 r  ->  n_q = 2 for r = 1
+};
+template <>
+struct Quad<2> {
+  static constexpr int NQ = 4;  // n_q = 4 for r = 2
+};
+
+// ---- field accessors ------------------------------------------------------
+struct AosFields {
+  const double* __restrict__ g;
+  __device__ __forceinline__ void load9(int64_t node, double* f) const {
+    const double* p = g + node * kGbufStride;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) f[k] = p[k];
+  }
+  __device__ __forceinline__ double A0(int64_t node, int l) const { return g[node * kGbufStride + 3 + l]; }
+  __device__ __forceinline__ double A1(int64_t node, int l) const { return g[node * kGbufStride + 6 + l]; }
+};
+
+struct SoaFields {
+  const double* __restrict__ gphi;
+  const double* __restrict__ a0;
+  const double* __restrict__ a1;
+  int64_t nc;
+  __device__ __forceinline__ void load9(int64_t node, double* f) const {
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      f[l] = gphi[l * nc + node];
+      f[3 + l] = a0[l * nc + node];
+      f[6 + l] = a1[l * nc + node];
+    }
+  }
+  __device__ __forceinline__ double A0(int64_t node, int l) const { return a0[l * nc + node]; }
+  __device__ __forceinline__ double A1(int64_t node, int l) const { return a1[l * nc + node]; }
+};
+
+__device__ __forceinline__ int64_t node_of(const Grid& G, int ix, int iy, int iz) {
+  return ((int64_t)ix * G.n[1] + iy) * G.n[2] + iz;
+}
+
+// ---- one orbit piece: current scatter -------------------------------------
+// J_g += (q vbar / dV) int_{s0}^{s1} S_g(x(s)) ds   (eq. orbit-current, split form)
+template <int R>
+__device__ __forceinline__ void scatter_piece(const Grid& G, const double* x0, const double* d,
+                                              double s0, double s1, const double* c3,
+                                              double* __restrict__ J) {
+  constexpr int W = R + 1, NQ = Quad<R>::NQ;
+  const double h = s1 - s0;
+  double base[3];
+  piece_base<R>(x0, d, 0.5 * (s0 + s1), G, base);
+  double I[W][W][W];
+#pragma unroll
+  for (int a = 0; a < W; ++a)
+#pragma unroll
+    for (int b = 0; b < W; ++b)
+#pragma unroll
+      for (int c = 0; c < W; ++c) I[a][b][c] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double s = s0 + 0.5 * h * (1.0 + Gauss<NQ>::x(q));
+    const double wt = 0.5 * h * Gauss<NQ>::w(q);
+    double wx[W], wy[W], wz[W];
+    Spline<R>::w((x0[0] + s * d[0]) * G.invH[0] - base[0], wx);
+    Spline<R>::w((x0[1] + s * d[1]) * G.invH[1] - base[1], wy);
+    Spline<R>::w((x0[2] + s * d[2]) * G.invH[2] - base[2], wz);
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      const double xa = wt * wx[a];
+#pragma unroll
+      for (int b = 0; b < W; ++b) {
+        const double xy = xa * wy[b];
+#pragma unroll
+        for (int c = 0; c < W; ++c) I[a][b][c] += xy * wz[c];
+      }
+    }
+  }
+  const int fx = to_int_clamped(base[0]) + Spline<R>::first_off;
+  const int fy = to_int_clamped(base[1]) + Spline<R>::first_off;
+  const int fz = to_int_clamped(base[2]) + Spline<R>::first_off;
+  const int64_t nc = G.ncell;
+#pragma unroll
+  for (int a = 0; a < W; ++a) {
+    const int ix = wrapi(fx + a, G.n[0]);
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      const int iy = wrapi(fy + b, G.n[1]);
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        const int64_t g = node_of(G, ix, iy, wrapi(fz + c, G.n[2]));
+        const double w = I[a][b][c];
+        unsafeAtomicAdd(J + g, w * c3[0]);
+        unsafeAtomicAdd(J + nc + g, w * c3[1]);
+        unsafeAtomicAdd(J + 2 * nc + g, w * c3[2]);
+      }
+    }
+  }
+}
+
+// ---- one orbit piece: gather --------------------------------------------
+// gp_l  += sum_g (grad_h phi)_lg int S_g ds                 (eq. gphibar-definition)
+// D_lj  += sum_g int A_lg(s) d_j S_g(x(s)) ds, A_g(s) = (1-s) A^n + s A^{n+1}  (eq. split-DA)
+// with WITH_U also Ub_l += sum_g U_lg int S_g ds and pou += int sum_g S_g ds.
+// The n_q-point rule is evaluated once per piece; each stencil node then
+// accumulates its weight integrals over the quadrature points and is
+// contracted with the node's field values.
+template <int R, bool WITH_U, class Acc>
+__device__ __forceinline__ void gather_piece(const Grid& G, const double* x0, const double* d,
+                                             double s0, double s1, const Acc& acc,
+                                             const double* __restrict__ Uh, double* gp,
+                                             double (*D)[3], double* Ub, double& pou) {
+  constexpr int W = R + 1, NQ = Quad<R>::NQ;
+  const double h = s1 - s0;
+  double base[3];
+  piece_base<R>(x0, d, 0.5 * (s0 + s1), G, base);
+  double X[NQ][W], dX[NQ][W], Y[NQ][W], dY[NQ][W];
+  double Zw[NQ][W], Z0[NQ][W], Z1[NQ][W], dZ0[NQ][W], dZ1[NQ][W];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double s = s0 + 0.5 * h * (1.0 + Gauss<NQ>::x(q));
+    const double wt = 0.5 * h * Gauss<NQ>::w(q);
+    const double w0 = wt * (1.0 - s), w1 = wt * s;
+    double wz[W], dz[W];
+    Spline<R>::wd((x0[0] + s * d[0]) * G.invH[0] - base[0], X[q], dX[q]);
+    Spline<R>::wd((x0[1] + s * d[1]) * G.invH[1] - base[1], Y[q], dY[q]);
+    Spline<R>::wd((x0[2] + s * d[2]) * G.invH[2] - base[2], wz, dz);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      dX[q][k] *= G.invH[0];
+      dY[q][k] *= G.invH[1];
+      const double dzk = dz[k] * G.invH[2];
+      Zw[q][k] = wt * wz[k];
+      Z0[q][k] = w0 * wz[k];
+      Z1[q][k] = w1 * wz[k];
+      dZ0[q][k] = w0 * dzk;
+      dZ1[q][k] = w1 * dzk;
+    }
+  }
+  const int fx = to_int_clamped(base[0]) + Spline<R>::first_off;
+  const int fy = to_int_clamped(base[1]) + Spline<R>::first_off;
+  const int fz = to_int_clamped(base[2]) + Spline<R>::first_off;
+#pragma unroll
+  for (int a = 0; a < W; ++a) {
+    const int ix = wrapi(fx + a, G.n[0]);
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      const int iy = wrapi(fy + b, G.n[1]);
+      double xy[NQ], dxy[NQ], xdy[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        xy[q] = X[q][a] * Y[q][b];
+        dxy[q] = dX[q][a] * Y[q][b];
+        xdy[q] = X[q][a] * dY[q][b];
+      }
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        const int64_t g = node_of(G, ix, iy, wrapi(fz + c, G.n[2]));
+        double f[9];
+        acc.load9(g, f);
+        double I = 0.0, K0x = 0.0, K1x = 0.0, K0y = 0.0, K1y = 0.0, K0z = 0.0, K1z = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          I += xy[q] * Zw[q][c];
+          K0x += dxy[q] * Z0[q][c];
+          K1x += dxy[q] * Z1[q][c];
+          K0y += xdy[q] * Z0[q][c];
+          K1y += xdy[q] * Z1[q][c];
+          K0z += xy[q] * dZ0[q][c];
+          K1z += xy[q] * dZ1[q][c];
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          gp[l] += f[l] * I;
+          D[l][0] += f[3 + l] * K0x + f[6 + l] * K1x;
+          D[l][1] += f[3 + l] * K0y + f[6 + l] * K1y;
+          D[l][2] += f[3 + l] * K0z + f[6 + l] * K1z;
+        }
+        if constexpr (WITH_U) {
+#pragma unroll
+          for (int l = 0; l < 3; ++l) Ub[l] += Uh[l * G.ncell + g] * I;
+          pou += I;
+        }
+      }
+    }
+  }
+}
+
+// point interpolant F_h(x) = sum_g F_g S_g(x) of A^n (which = 0) or A^{n+1} (which = 1)
+template <int R, class Acc>
+__device__ __forceinline__ void point_A(const Grid& G, const double* x, const Acc& acc, int which,
+                                        double* out) {
+  constexpr int W = R + 1;
+  double w[3][W];
+  int f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = x[a] * G.invH[a];
+    const double base = floor(u + Spline<R>::base_off);
+    Spline<R>::w(u - base, w[a]);
+    f[a] = to_int_clamped(base) + Spline<R>::first_off;
+  }
+  out[0] = out[1] = out[2] = 0.0;
+#pragma unroll
+  for (int a = 0; a < W; ++a) {
+    const int ix = wrapi(f[0] + a, G.n[0]);
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      const int iy = wrapi(f[1] + b, G.n[1]);
+      const double wxy = w[0][a] * w[1][b];
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        const int64_t g = node_of(G, ix, iy, wrapi(f[2] + c, G.n[2]));
+        const double wt = wxy * w[2][c];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) out[l] += (which ? acc.A1(g, l) : acc.A0(g, l)) * wt;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void load3(const double* __restrict__ p, int64_t np, int64_t i,
+                                      double* o) {
+  o[0] = p[i];
+  o[1] = p[np + i];
+  o[2] = p[2 * np + i];
+}
+
+// ---- kernels ---------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const double* __restrict__ v,
+                                                       const double* __restrict__ vprev,
+                                                       double* __restrict__ vit) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n3) vit[i] = 2.0 * v[i] - vprev[i];  // v^{n+1,0} = 2 v^n - v^{n-1}
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* __restrict__ x,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ vit,
+                                                   double* __restrict__ J, Scratch sc) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double js[1] = {0.0};
+  double bad = 0.0;
+  if (i < P.np) {
+    double x0[3], vb[3], d[3], c3[3];
+    load3(x, P.np, i, x0);
+    double va[3], vi[3];
+    load3(v, P.np, i, va);
+    load3(vit, P.np, i, vi);
+    const double qdv = P.q / P.G.dV;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      vb[a] = 0.5 * (vi[a] + va[a]);  // vbar^p = (v^{n+1,p} + v^n) / 2
+      d[a] = P.dt * vb[a];            // unwrapped displacement
+      c3[a] = qdv * vb[a];
+    }
+    js[0] = fabs(P.q) * fmax(fabs(vb[0]), fmax(fabs(vb[1]), fabs(vb[2]))) / P.G.vol;
+    const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
+      scatter_piece<R>(P.G, x0, d, s0, s1, c3, J);
+    });
+    if (!ok) bad = 1.0;
+  }
+  block_max_to(bad, sc.red + S_BAD);
+  grid_sum<1>(js, sc.partials, sc.ticket + 0, sc.red + S_JS);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, const double* __restrict__ x,
+                                                       const double* __restrict__ v,
+                                                       const double* __restrict__ vit,
+                                                       double* __restrict__ vnew, AosFields F,
+                                                       Scratch sc) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double dvm = 0.0, vm = 0.0, bad = 0.0;
+  if (i < P.np) {
+    double x0[3], va[3], vi[3], vb[3], d[3];
+    load3(x, P.np, i, x0);
+    load3(v, P.np, i, va);
+    load3(vit, P.np, i, vi);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      vb[a] = 0.5 * (vi[a] + va[a]);
+      d[a] = P.dt * vb[a];
+    }
+    double gp[3] = {0.0, 0.0, 0.0};
+    double D[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    double Ub[3];
+    double pou = 0.0;
+    const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
+      gather_piece<R, false>(P.G, x0, d, s0, s1, F, nullptr, gp, D, Ub, pou);
+    });
+    if (!ok) bad = 1.0;
+    // A_h^n(x^n) rebuilds P^n = m v^n + q A_h^n(x^n) (eq. discrete-canonical-relation);
+    // A_h^{n+1}(x^{n+1}) at the wrapped end point closes the velocity (eq. orbit-v-update).
+    double x1[3], A0s[3], A1e[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], P.G.L[a]);
+    point_A<R>(P.G, x0, F, 0, A0s);
+    point_A<R>(P.G, x1, F, 1, A1e);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double DTv = D[0][j] * vb[0] + D[1][j] * vb[1] + D[2][j] * vb[2];  // ((D A)^T vbar)_j
+      const double Pn = P.m * va[j] + P.q * A0s[j];
+      const double P1 = Pn + P.dt * (-P.q * gp[j] + P.q * DTv);  // eq. orbit-P-update
+      const double vn = (P1 - P.q * A1e[j]) / P.m;               // eq. orbit-v-update
+      vnew[j * P.np + i] = vn;
+      dvm = fmax(dvm, fabs(vn - vi[j]));
+      vm = fmax(vm, fabs(vn));
+      if (!isfinite(vn)) bad = 2.0;  // max-reductions drop NaN: flag it explicitly
+    }
+  }
+  block_max_to(dvm, sc.red + S_DVMAX);
+  block_max_to(vm, sc.red + S_VMAX);
+  block_max_to(bad, sc.red + S_BAD);
+}
+
+// Consistency sweep of the accepted iterate: Ubar, Ebar = -gphibar - Ubar,
+// sum_i q vbar . Ebar, R_A = A_h^{n+1}(x^{n+1}) - A_h^n(x^n) - dt (Ubar + D vbar)
+// (eq. RA-test) and the partition of unity sum_g Sbar_g.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, const double* __restrict__ x,
+                                                 const double* __restrict__ v,
+                                                 const double* __restrict__ vit, AosFields F,
+                                                 const double* __restrict__ Uh, Scratch sc) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double sums[2] = {0.0, 0.0};  // work, |R_A|^2
+  double ramax = 0.0, poudev = 0.0;
+  if (i < P.np) {
+    double x0[3], va[3], vi[3], vb[3], d[3];
+    load3(x, P.np, i, x0);
+    load3(v, P.np, i, va);
+    load3(vit, P.np, i, vi);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      vb[a] = 0.5 * (vi[a] + va[a]);
+      d[a] = P.dt * vb[a];
+    }
+    double gp[3] = {0.0, 0.0, 0.0}, Ub[3] = {0.0, 0.0, 0.0};
+    double D[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    double pou = 0.0;
+    for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
+      gather_piece<R, true>(P.G, x0, d, s0, s1, F, Uh, gp, D, Ub, pou);
+    });
+    double x1[3], A0s[3], A1e[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], P.G.L[a]);
+    point_A<R>(P.G, x0, F, 0, A0s);
+    point_A<R>(P.G, x1, F, 1, A1e);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const double Dv = D[l][0] * vb[0] + D[l][1] * vb[1] + D[l][2] * vb[2];
+      const double ra = A1e[l] - A0s[l] - P.dt * (Ub[l] + Dv);
+      sums[1] += ra * ra;
+      ramax = fmax(ramax, fabs(ra));
+      sums[0] += P.q * vb[l] * (-gp[l] - Ub[l]);
+    }
+    poudev = fabs(pou - 1.0);
+  }
+  block_max_to(ramax, sc.red + S_RAMAX);
+  block_max_to(poudev, sc.red + S_POU);
+  double s2[2] = {sums[0], sums[1]};
+  grid_sum<2>(s2, sc.partials, sc.ticket + 1, sc.red + S_WORK);  // S_WORK, S_RA2 adjacent
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, double* __restrict__ x,
+                                                    double* __restrict__ v,
+                                                    double* __restrict__ vprev,
+                                                    const double* __restrict__ vit,
+                                                    const double* __restrict__ vnew, Scratch sc) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double s[2] = {0.0, 0.0};  // K^{n+1}, K^{n+1} - K^n
+  if (i < P.np) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int64_t k = a * P.np + i;
+      const double vo = v[k], vi = vit[k], vn = vnew[k];
+      x[k] = wrap_pos(x[k] + P.dt * 0.5 * (vi + vo), P.G.L[a]);  // x^{n+1} = x^n + dt vbar^p
+      vprev[k] = vo;
+      v[k] = vn;
+      s[0] += 0.5 * P.m * vn * vn;
+      s[1] += 0.5 * P.m * (vn - vo) * (vn + vo);
+    }
+  }
+  grid_sum<2>(s, sc.partials, sc.ticket + 2, sc.red + S_K);  // S_K, S_DK adjacent
+}
+
+__global__ __launch_bounds__(kBlock) void k_kinetic(StepParams P, const double* __restrict__ v,
+                                                   Scratch sc) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double s[2] = {0.0, 0.0};
+  if (i < P.np) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double va = v[a * P.np + i];
+      s[0] += 0.5 * P.m * va * va;
+    }
+  }
+  grid_sum<2>(s, sc.partials, sc.ticket + 2, sc.red + S_K);
+}
+
+__global__ __launch_bounds__(kBlock) void k_wrap(StepParams P, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < P.np)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a * P.np + i] = wrap_pos(x[a * P.np + i], P.G.L[a]);
+}
+
+// rho_g += q S_g(x_i) / dV (eq. source-moments), point shape
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_deposit_rho(StepParams P, const double* __restrict__ x,
+                                                       double* __restrict__ rho) {
+  constexpr int W = R + 1;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= P.np) return;
+  double w[3][W];
+  int f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = x[a * P.np + i] * P.G.invH[a];
+    const double base = floor(u + Spline<R>::base_off);
+    Spline<R>::w(u - base, w[a]);
+    f[a] = to_int_clamped(base) + Spline<R>::first_off;
+  }
+  const double c = P.q / P.G.dV;
+#pragma unroll
+  for (int a = 0; a < W; ++a)
+#pragma unroll
+    for (int b = 0; b < W; ++b)
+#pragma unroll
+      for (int cc = 0; cc < W; ++cc) {
+        const int64_t g = node_of(P.G, wrapi(f[0] + a, P.G.n[0]), wrapi(f[1] + b, P.G.n[1]),
+                                  wrapi(f[2] + cc, P.G.n[2]));
+        unsafeAtomicAdd(rho + g, c * w[0][a] * w[1][b] * w[2][cc]);
+      }
+}
+
+// Orbit integrals of independent particles against SoA fields (kernel-level check).
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_orbit_gather_soa(Grid G, int64_t n,
+                                                            const double* __restrict__ x0s,
+                                                            const double* __restrict__ ds,
+                                                            SoaFields F,
+                                                            const double* __restrict__ Uh,
+                                                            double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double x0[3], d[3];
+  load3(x0s, n, i, x0);
+  load3(ds, n, i, d);
+  double gp[3] = {0.0, 0.0, 0.0}, Ub[3] = {0.0, 0.0, 0.0};
+  double D[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  double pou = 0.0;
+  int pieces = 0;
+  const bool ok = for_each_piece<R>(x0, d, G, [&](double s0, double s1) {
+    gather_piece<R, true>(G, x0, d, s0, s1, F, Uh, gp, D, Ub, pou);
+    ++pieces;
+  });
+  double x1[3], A0s[3], A1e[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], G.L[a]);
+  point_A<R>(G, x0, F, 0, A0s);
+  point_A<R>(G, x1, F, 1, A1e);
+  double* o = out + 24 * i;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    o[l] = gp[l];
+    o[3 + l] = Ub[l];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) o[6 + 3 * l + j] = D[l][j];
+    o[15 + l] = A1e[l];
+    o[18 + l] = A0s[l];
+  }
+  o[21] = pou;
+  o[22] = ok ? (double)pieces : -1.0;
+  o[23] = 0.0;
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_orbit_deposit_soa(Grid G, int64_t n,
+                                                             const double* __restrict__ x0s,
+                                                             const double* __restrict__ ds,
+                                                             const double* __restrict__ qv,
+                                                             double* __restrict__ J) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double x0[3], d[3], c3[3];
+  load3(x0s, n, i, x0);
+  load3(ds, n, i, d);
+  load3(qv, n, i, c3);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c3[a] /= G.dV;
+  for_each_piece<R>(x0, d, G, [&](double s0, double s1) {
+    scatter_piece<R>(G, x0, d, s0, s1, c3, J);
+  });
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// ---- launchers ---------------------------------------------------------------
+
+void launch_extrapolate(hipStream_t s, int64_t np, const double* v, const double* vprev,
+                        double* vit) {
+  if (np <= 0) return;
+  k_extrapolate<<<blocks_for(3 * np), kBlock, 0, s>>>(3 * np, v, vprev, vit);
+}
+
+void launch_scatter(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
+                    const double* vit, double* J, Scratch sc) {
+  if (P.np <= 0) return;
+  if (r == 1)
+    k_scatter<1><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, J, sc);
+  else
+    k_scatter<2><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, J, sc);
+}
+
+void launch_gather_push(hipStream_t s, int r, const StepParams& P, const double* x,
+                        const double* v, const double* vit, double* vnew, const double* gbuf,
+                        Scratch sc) {
+  if (P.np <= 0) return;
+  AosFields F{gbuf};
+  if (r == 1)
+    k_gather_push<1><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, vnew, F, sc);
+  else
+    k_gather_push<2><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, vnew, F, sc);
+}
+
+void launch_sweep(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
+                  const double* vit, const double* vnew, const double* gbuf, const double* Uhalf,
+                  Scratch sc) {
+  (void)vnew;
+  if (P.np <= 0) return;
+  AosFields F{gbuf};
+  if (r == 1)
+    k_sweep<1><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, F, Uhalf, sc);
+  else
+    k_sweep<2><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, F, Uhalf, sc);
+}
+
+void launch_finalize(hipStream_t s, const StepParams& P, double* x, double* v, double* vprev,
+                     const double* vit, const double* vnew, Scratch sc) {
+  if (P.np <= 0) return;
+  k_finalize<<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vprev, vit, vnew, sc);
+}
+
+void launch_kinetic(hipStream_t s, const StepParams& P, const double* v, Scratch sc) {
+  if (P.np <= 0) return;
+  k_kinetic<<<blocks_for(P.np), kBlock, 0, s>>>(P, v, sc);
+}
+
+void launch_wrap_positions(hipStream_t s, const StepParams& P, double* x) {
+  if (P.np <= 0) return;
+  k_wrap<<<blocks_for(P.np), kBlock, 0, s>>>(P, x);
+}
+
+void launch_deposit_rho(hipStream_t s, int r, const StepParams& P, const double* x, double* rho) {
+  if (P.np <= 0) return;
+  if (r == 1)
+    k_deposit_rho<1><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, rho);
+  else
+    k_deposit_rho<2><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, rho);
+}
+
+void launch_orbit_gather_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
+                             const double* d, const double* gphi, const double* U,
+                             const double* A0, const double* A1, double* out) {
+  if (n <= 0) return;
+  SoaFields F{gphi, A0, A1, G.ncell};
+  if (r == 1)
+    k_orbit_gather_soa<1><<<blocks_for(n), kBlock, 0, s>>>(G, n, x0, d, F, U, out);
+  else
+    k_orbit_gather_soa<2><<<blocks_for(n), kBlock, 0, s>>>(G, n, x0, d, F, U, out);
+}
+
+void launch_orbit_deposit_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
+                              const double* d, const double* qv, double* J) {
+  if (n <= 0) return;
+  if (r == 1)
+    k_orbit_deposit_soa<1><<<blocks_for(n), kBlock, 0, s>>>(G, n, x0, d, qv, J);
+  else
+    k_orbit_deposit_soa<2><<<blocks_for(n), kBlock, 0, s>>>(G, n, x0, d, qv, J);
+}
+
+}  // namespace ecpic

@@ -1,0 +1,249 @@
+"""Thin Python binding of the C ABI in include/ecpic.h (libecpic.so).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  PyTorch provides the device memory (the caller-owned state
+and workspace buffers) and the HIP stream.  If the library is not built, or
+no GPU is visible, the binding raises; there is no CPU fallback.
+
+Function names follow the C ABI: ``state_bytes``, ``Sim.init_particles``,
+``Sim.picard_step``, ``Sim.field_solve``, ``Sim.energy_diagnostics``,
+``Sim.get_state``, ``Sim.set_state``, ``Sim.get_current``, ``orbit_gather``,
+``orbit_deposit``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libecpic.so")
+
+OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE = 0, 1, -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+
+
+class EcpicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ecpic status {status}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("spline_degree", C.c_int32), ("L", C.c_double * 3),
+                ("kappa", C.c_double), ("sigma1", C.c_double), ("sigma2", C.c_double),
+                ("dt", C.c_double), ("picard_tol", C.c_double), ("picard_max", C.c_int32),
+                ("split_orbit_at_knots", C.c_int32), ("quad_points", C.c_int32),
+                ("precision", C.c_int32), ("fixed_point_scale", C.c_double),
+                ("diagnostics", C.c_int32), ("reserved", C.c_int32)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("err_v", C.c_double),
+                ("err_J", C.c_double)]
+
+
+_ENERGY_FIELDS = ("K", "W", "E_total", "R_field", "R_particle", "R_total", "gauge_max",
+                  "gauge_l2", "gauss_max", "gauss_l2", "RA_rms", "RA_max", "pou_max", "JE_mesh",
+                  "work_particle")
+
+
+class Energy(C.Structure):
+    _fields_ = [(k, C.c_double) for k in _ENERGY_FIELDS] + [("step", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libecpic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2606_15035_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P, D, I64 = C.c_void_p, C.c_void_p, C.c_int64
+        cfgp = C.POINTER(Config)
+        L.ecpic_state_bytes.argtypes = [cfgp, I64, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+        L.ecpic_create.argtypes = [cfgp, I64, P, C.c_size_t, P, C.c_size_t, P, C.POINTER(P)]
+        L.ecpic_destroy.argtypes = [P]
+        L.ecpic_destroy.restype = None
+        L.ecpic_init_particles.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double]
+        L.ecpic_picard_step.argtypes = [P, C.POINTER(StepInfo)]
+        L.ecpic_field_solve.argtypes = [P, D]
+        L.ecpic_energy_diagnostics.argtypes = [P, C.POINTER(Energy)]
+        L.ecpic_get_state.argtypes = [P, D, D, D, D]
+        L.ecpic_set_state.argtypes = [P, D, D, D, D, C.c_double, C.c_double]
+        L.ecpic_get_current.argtypes = [P, D]
+        L.ecpic_orbit_gather.argtypes = [cfgp, I64, D, D, D, D, D, D, D, P]
+        L.ecpic_orbit_deposit.argtypes = [cfgp, I64, D, D, D, D, P]
+        L.ecpic_last_error.restype = C.c_char_p
+        L.ecpic_version.restype = C.c_char_p
+        for name in ("ecpic_state_bytes", "ecpic_create", "ecpic_init_particles",
+                     "ecpic_picard_step", "ecpic_field_solve", "ecpic_energy_diagnostics",
+                     "ecpic_get_state", "ecpic_set_state", "ecpic_get_current",
+                     "ecpic_orbit_gather", "ecpic_orbit_deposit"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, allow=(OK,)):
+    if status not in allow:
+        raise EcpicError(status, lib().ecpic_last_error().decode())
+    return status
+
+
+def make_config(n, L, dt, r=1, kappa=1.0, sigma1=1.0, sigma2=1.0, tol=1e-12, pmax=16,
+                split=True, quad_points=0, precision=FP64, fixed_point_scale=0.0,
+                diagnostics=False) -> Config:
+    c = Config()
+    for a in range(3):
+        c.n[a] = int(n[a])
+        c.L[a] = float(L[a])
+    c.spline_degree = int(r)
+    c.kappa, c.sigma1, c.sigma2, c.dt = float(kappa), float(sigma1), float(sigma2), float(dt)
+    c.picard_tol, c.picard_max = float(tol), int(pmax)
+    c.split_orbit_at_knots = int(bool(split))
+    c.quad_points = int(quad_points)
+    c.precision = int(precision)
+    c.fixed_point_scale = float(fixed_point_scale)
+    c.diagnostics = int(bool(diagnostics))
+    return c
+
+
+def state_bytes(cfg: Config, n_particles: int):
+    s, w = C.c_size_t(), C.c_size_t()
+    _check(lib().ecpic_state_bytes(C.byref(cfg), int(n_particles), C.byref(s), C.byref(w)))
+    return s.value, w.value
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the ecpic library needs a gfx950 device")
+    return torch
+
+
+def _host(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _hp(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Sim:
+    """A simulation over torch-allocated device buffers on the current stream."""
+
+    def __init__(self, cfg: Config, n_particles: int, device="cuda", stream=None):
+        torch = _torch()
+        self.torch = torch
+        self.cfg = cfg
+        self.np = int(n_particles)
+        self.n = tuple(cfg.n)
+        self.ncell = int(np.prod(self.n))
+        sb, wb = state_bytes(cfg, self.np)
+        self.state = torch.empty(sb, dtype=torch.uint8, device=device)
+        self.workspace = torch.empty(wb, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.state.device)
+        h = C.c_void_p()
+        _check(lib().ecpic_create(C.byref(cfg), self.np, C.c_void_p(self.state.data_ptr()), sb,
+                                  C.c_void_p(self.workspace.data_ptr()), wb,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.q = None
+        self.m = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ecpic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_particles(self, x, v, q, m, n0=1.0):
+        x = _host(x, (3, self.np))
+        v = _host(v, (3, self.np))
+        self.q, self.m = float(q), float(m)
+        _check(lib().ecpic_init_particles(self._h, _hp(x), _hp(v), float(q), float(m), float(n0)))
+
+    def picard_step(self):
+        info = StepInfo()
+        st = _check(lib().ecpic_picard_step(self._h, C.byref(info)), allow=(OK, ENOCONV))
+        return {"iters": info.iters, "converged": bool(info.converged), "err_v": info.err_v,
+                "err_J": info.err_J, "status": st}
+
+    def field_solve(self, J_dev=None):
+        ptr = None if J_dev is None else C.c_void_p(J_dev.data_ptr())
+        _check(lib().ecpic_field_solve(self._h, ptr))
+
+    def energy_diagnostics(self):
+        e = Energy()
+        _check(lib().ecpic_energy_diagnostics(self._h, C.byref(e)))
+        return e.as_dict()
+
+    def get_state(self):
+        x = np.zeros((3, self.np))
+        v = np.zeros((3, self.np))
+        vp = np.zeros((3, self.np))
+        f = np.zeros((9,) + self.n)
+        _check(lib().ecpic_get_state(self._h, _hp(x), _hp(v), _hp(vp), _hp(f)))
+        return {"x": x, "v": v, "vprev": vp, "fields": f}
+
+    def set_state(self, x=None, v=None, vprev=None, fields=None, q=None, m=None):
+        q = self.q if q is None else float(q)
+        m = self.m if m is None else float(m)
+        args = [None if a is None else _host(a) for a in (x, v, vprev, fields)]
+        self.q, self.m = q, m
+        _check(lib().ecpic_set_state(self._h, *[_hp(a) for a in args], q, m))
+
+    def get_current(self):
+        J = np.zeros((3,) + self.n)
+        _check(lib().ecpic_get_current(self._h, _hp(J)))
+        return J
+
+
+def orbit_gather(cfg: Config, x0, d, gphi, U, A0, A1, device="cuda"):
+    """Kernel-level orbit integrals of n particles; x0, d host arrays (n, 3);
+    fields host arrays (3,) + n.  Returns a dict of host arrays."""
+    torch = _torch()
+    x0 = np.ascontiguousarray(np.asarray(x0, dtype=np.float64).reshape(-1, 3).T)
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(-1, 3).T)
+    n = x0.shape[1]
+    t = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+         for a in (x0, d, gphi, U, A0, A1)]
+    out = torch.zeros((n, 24), dtype=torch.float64, device=device)
+    s = torch.cuda.current_stream()
+    _check(lib().ecpic_orbit_gather(C.byref(cfg), n, *[C.c_void_p(a.data_ptr()) for a in t],
+                                    C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream)))
+    o = out.cpu().numpy()
+    return {"gphibar": o[:, 0:3], "Ubar": o[:, 3:6], "D": o[:, 6:15].reshape(n, 3, 3),
+            "A1_end": o[:, 15:18], "A0_start": o[:, 18:21], "pou": o[:, 21],
+            "npieces": o[:, 22].astype(int)}
+
+
+def orbit_deposit(cfg: Config, x0, d, qv, device="cuda"):
+    torch = _torch()
+    x0 = np.ascontiguousarray(np.asarray(x0, dtype=np.float64).reshape(-1, 3).T)
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(-1, 3).T)
+    qv = np.ascontiguousarray(np.asarray(qv, dtype=np.float64).reshape(-1, 3).T)
+    n = x0.shape[1]
+    t = [torch.from_numpy(a).to(device) for a in (x0, d, qv)]
+    ncell = int(np.prod(tuple(cfg.n)))
+    J = torch.zeros(3 * ncell, dtype=torch.float64, device=device)
+    s = torch.cuda.current_stream()
+    _check(lib().ecpic_orbit_deposit(C.byref(cfg), n, *[C.c_void_p(a.data_ptr()) for a in t],
+                                     C.c_void_p(J.data_ptr()), C.c_void_p(s.cuda_stream)))
+    return J.cpu().numpy().reshape((3,) + tuple(cfg.n))

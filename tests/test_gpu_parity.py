@@ -1,0 +1,279 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+identical seeded inputs.
+
+Tolerances (FP64): particle velocities and positions within 1e-12 of the
+velocity / displacement scale, mesh fields within 1e-12 of each field's
+maximum, the orbit current within 1e-12 of the beam-current scale
+J_s = sum_i |q| |vbar_i|_inf / |Omega|, integer outputs (numbers of orbit
+pieces, Picard iteration counts in fixed-iteration mode) exactly.  The two
+sides differ only in rounding order (FP64 atomics, FFT versus DFT, fused
+multiply-adds, Gauss rule versus the App. A/B closed forms).
+"""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_15035_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+E = pytest.importorskip("paper_2606_15035_amd.ecpic")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    E.lib()
+    return torch
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_cfg(wl, **kw):
+    args = dict(n=wl.n, L=wl.L, dt=wl.dt, r=wl.r, kappa=wl.kappa, sigma1=wl.sigma1,
+                sigma2=wl.sigma2, tol=wl.tol, pmax=wl.pmax)
+    args.update(kw)
+    return E.make_config(**args)
+
+
+def orc_cfg(wl, **kw):
+    args = wl.cfg_kwargs()
+    m = {"diagnostics": None}
+    for k, v in kw.items():
+        if k in m:
+            continue
+        args[k] = v
+    return O.make_cfg(**args)
+
+
+def both(wl, **kw):
+    g = E.Sim(gpu_cfg(wl, **kw), wl.np)
+    g.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
+    o = O.OracleSim(orc_cfg(wl, **kw), wl.np)
+    o.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
+    return g, o
+
+
+def unwrap_delta(a, b, L):
+    d = a - b
+    for k in range(3):
+        d[k] -= L[k] * np.round(d[k] / L[k])
+    return d
+
+
+def compare_states(wl, g, o, tag, rtol=1e-12):
+    sg, so = g.get_state(), o.get_state()
+    vs = np.abs(so["v"]).max()
+    dv = np.abs(sg["v"] - so["v"]).max()
+    dvp = np.abs(sg["vprev"] - so["vprev"]).max()
+    dx = np.abs(unwrap_delta(sg["x"], so["x"], wl.L)).max()
+    xs = vs * wl.dt
+    log(f"[{tag}] max|dv|/|v| = {dv / vs:.2e}  max|dx|/(|v| dt) = {dx / xs:.2e}")
+    assert dv <= rtol * vs, (tag, dv, vs)
+    assert dvp <= rtol * vs, (tag, dvp, vs)
+    assert dx <= rtol * xs, (tag, dx, xs)
+    # scalar fields against their own maximum, vector fields against the
+    # maximum over their three components
+    for nm, ks in (("phi", [0]), ("psi", [1]), ("A", [2, 3, 4]), ("U", [5, 6, 7]), ("rho", [8])):
+        ref = so["fields"][ks]
+        scale = max(np.abs(ref).max(), 1e-300)
+        err = np.abs(sg["fields"][ks] - ref).max()
+        assert err <= rtol * scale, (tag, nm, err, scale)
+    Jg, Jo = g.get_current(), o.current()
+    Js = np.abs(wl.q) * np.abs(so["v"]).max(axis=0).sum() / np.prod(wl.L)
+    errJ = np.abs(Jg - Jo).max()
+    log(f"[{tag}] max|dJ|/J_s = {errJ / Js:.2e}")
+    assert errJ <= rtol * Js, (tag, errJ, Js)
+
+
+# --------------------------------------------------------------------------
+# kernel level
+# --------------------------------------------------------------------------
+N = (8, 4, 4)
+LB = (1.3, 0.9, 0.7)
+
+
+def rand_orbits(rng, k, cells=1.8):
+    h = [LB[a] / N[a] for a in range(3)]
+    x0 = np.stack([rng.uniform(0, LB[a], size=k) for a in range(3)], axis=1)
+    d = np.stack([rng.uniform(-cells, cells, size=k) * h[a] for a in range(3)], axis=1)
+    # a few special orbits: static, one axis only, start on a knot, tiny steps
+    x0[0] = [2 * h[0], 3 * h[1], 1.5 * h[2]]
+    d[0] = 0.0
+    x0[1] = [2 * h[0], 3.5 * h[1], 1.0 * h[2]]
+    d[1] = [0.7 * h[0], 0.0, 0.0]
+    x0[2] = [0.5 * h[0], 0.5 * h[1], 0.5 * h[2]]
+    d[2] = [-0.9 * h[0], 1e-14 * h[1], 0.3 * h[2]]
+    x0[3] = [LB[0] - 1e-15, 0.0, LB[2] * 0.5]
+    d[3] = [1.3 * h[0], -0.6 * h[1], 0.0]
+    return x0, d
+
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_kernel_orbit_gather_matches_oracle(r):
+    rng = np.random.default_rng(100 + r)
+    x0, d = rand_orbits(rng, 4000)
+    A0 = W.random_fields(N, 3, seed=1)
+    A1 = W.random_fields(N, 3, seed=2)
+    gphi = W.random_fields(N, 3, seed=3)
+    U = W.random_fields(N, 3, seed=4)
+    cfg = E.make_config(N, LB, 0.1, r=r)
+    got = E.orbit_gather(cfg, x0, d, gphi, U, A0, A1)
+    o = O.OracleSim(O.make_cfg(n=N, L=LB, dt=0.1, r=r), 1)
+    ref = o.orbit_gather(x0, d, gphi, U, A0, A1)
+    np.testing.assert_array_equal(got["npieces"], ref["npieces"])
+    assert got["npieces"].max() >= 4
+    for k, scale in (("gphibar", np.abs(gphi).max()), ("Ubar", np.abs(U).max()),
+                     ("A1_end", np.abs(A1).max()), ("A0_start", np.abs(A0).max()),
+                     ("D", np.abs(ref["D"]).max()), ("pou", 1.0)):
+        err = np.abs(got[k] - ref[k]).max()
+        log(f"r={r} {k}: max err {err:.2e} (scale {scale:.2e})")
+        assert err <= 1e-13 * scale, (k, err, scale)
+
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_kernel_orbit_deposit_matches_oracle(r):
+    rng = np.random.default_rng(200 + r)
+    x0, d = rand_orbits(rng, 4000)
+    qv = rng.normal(size=(4000, 3))
+    cfg = E.make_config(N, LB, 0.1, r=r)
+    got = E.orbit_deposit(cfg, x0, d, qv)
+    o = O.OracleSim(O.make_cfg(n=N, L=LB, dt=0.1, r=r), 1)
+    ref = o.orbit_deposit(x0, d, qv)
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max()
+    log(f"r={r} deposit: max err {err:.2e} (scale {scale:.2e})")
+    assert err <= 1e-13 * scale
+
+
+# --------------------------------------------------------------------------
+# whole steps
+# --------------------------------------------------------------------------
+def small_random(r, np_=3000, seed=5):
+    return W.random_plasma((8, 8, 4), (1.0, 1.0, 0.5), np_, r=r, dt=0.25, vth=0.06,
+                           drift=(0.03, -0.02, 0.01), seed=seed)
+
+
+@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("pmax", [0, 3])
+def test_step_parity_fixed_iterations(r, pmax):
+    wl = small_random(r)
+    g, o = both(wl, tol=0.0, pmax=pmax)
+    for step in range(3):
+        ig = g.picard_step()
+        io = o.step()
+        assert ig["iters"] == io["iters"] == pmax + 1
+        assert not ig["converged"] and not io["converged"]
+        np.testing.assert_allclose(ig["err_v"], io["err_v"], rtol=1e-6)
+        compare_states(wl, g, o, f"r={r} pmax={pmax} step {step}")
+
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_step_parity_tolerance_mode_and_energy(r):
+    wl = small_random(r, seed=9)
+    g, o = both(wl, tol=1e-11, pmax=30, diagnostics=True)
+    E0 = o.energy()["E_total"]
+    eg0 = g.energy_diagnostics()
+    assert abs(eg0["E_total"] - E0) <= 1e-13 * E0
+    for step in range(4):
+        ig, io = g.picard_step(), o.step()
+        assert abs(ig["iters"] - io["iters"]) <= 1, (ig, io)
+        if ig["iters"] == io["iters"]:
+            compare_states(wl, g, o, f"r={r} tol step {step}", rtol=1e-10)
+        eg, eo = g.energy_diagnostics(), o.energy()
+        for k in ("K", "W", "E_total"):
+            assert abs(eg[k] - eo[k]) <= 1e-12 * E0, (k, eg[k], eo[k])
+        for k in ("R_total", "R_field", "R_particle"):
+            assert abs(eg[k] - eo[k]) <= 1e-13 * E0, (k, eg[k], eo[k])
+        assert abs(eg["JE_mesh"] - eo["JE_mesh"]) <= 1e-10 * abs(eo["JE_mesh"]) + 1e-15 * E0
+        assert eg["RA_max"] < 1e-14 and eg["pou_max"] < 1e-14
+        assert eg["gauge_max"] < 1e-12 and eg["gauss_max"] < 1e-10
+
+
+def test_two_stream_16x4x4_tolerance_run():
+    """The 16x4x4 two-stream workload (linear shape, tol 1e-12): 20 steps side by
+    side; states agree while the instability is still linear."""
+    wl = W.two_stream("c1")
+    g, o = both(wl, diagnostics=True)
+    E0 = o.energy()["E_total"]
+    for step in range(20):
+        ig, io = g.picard_step(), o.step()
+        assert ig["converged"] and io["converged"]
+        assert abs(ig["iters"] - io["iters"]) <= 1
+        eg = g.energy_diagnostics()
+        assert abs(eg["R_total"]) <= 1e-13 * E0
+        assert abs(eg["E_total"] - E0) <= 1e-12 * E0
+        assert eg["RA_max"] < 1e-15 and eg["gauge_max"] < 1e-13 and eg["gauss_max"] < 1e-10
+    compare_states(wl, g, o, "c1 step 20", rtol=1e-10)
+
+
+def test_no_particles_vacuum_fields():
+    """Empty particle set: the step is the source-free CN update of the fields."""
+    wl = small_random(2, np_=1)
+    wl.x, wl.v = wl.x[:, :0], wl.v[:, :0]
+    g, o = both(wl, tol=1e-12)
+    f = np.zeros((9,) + wl.n)
+    x = np.arange(wl.n[0]) * wl.L[0] / wl.n[0]
+    f[3] = np.cos(2 * math.pi * x / wl.L[0]).reshape(-1, 1, 1)
+    g.set_state(fields=f, q=wl.q, m=wl.m)
+    o.set_state(None, None, None, None, f, wl.q, wl.m)
+    for _ in range(5):
+        g.picard_step()
+        o.step()
+    sg, so = g.get_state(), o.get_state()
+    np.testing.assert_allclose(sg["fields"], so["fields"], atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# full size, in the bench launch configuration
+# --------------------------------------------------------------------------
+def test_full_size_32cubed_step_matches_oracle():
+    """32^3 mesh, 2,097,152 particles, quadratic shape: one Picard step at the
+    workload's tolerance (1e-10) from the same initial state, every particle
+    and every node compared."""
+    wl = W.two_stream("c2")
+    t = time.time()
+    g, o = both(wl)
+    log(f"init both: {time.time() - t:.1f}s")
+    t = time.time()
+    ig = g.picard_step()
+    log(f"gpu step {ig} {time.time() - t:.2f}s")
+    t = time.time()
+    io = o.step()
+    log(f"oracle step {io} {time.time() - t:.1f}s")
+    assert ig["converged"] and io["converged"]
+    assert ig["iters"] == io["iters"]
+    compare_states(wl, g, o, "c2 step 1", rtol=1e-11)
+
+
+def test_errors_are_reported():
+    wl = small_random(1, np_=10)
+    with pytest.raises(E.EcpicError):
+        E.Sim(E.make_config((8, 8, 6), wl.L, wl.dt), wl.np)  # not a power of two
+    with pytest.raises(E.EcpicError):
+        E.Sim(E.make_config(wl.n, wl.L, wl.dt, kappa=2.0), wl.np)  # Maxwell scaling
+    s = E.Sim(gpu_cfg(wl), wl.np)
+    with pytest.raises(E.EcpicError) as ei:
+        s.picard_step()
+    assert ei.value.status == E.ESTATE
+    s.init_particles(wl.x, wl.v, wl.q, wl.m)
+    v = wl.v.copy()
+    v[0, 3] = np.nan
+    s.set_state(v=v)
+    with pytest.raises(E.EcpicError) as ei:
+        s.picard_step()
+    assert ei.value.status == E.ENONFINITE
+    # p_max = 0 with a positive tolerance cannot converge: warning status, step taken
+    s2 = E.Sim(gpu_cfg(wl, pmax=0), wl.np)
+    s2.init_particles(wl.x, wl.v, wl.q, wl.m)
+    info = s2.picard_step()
+    assert info["status"] == E.ENOCONV and info["iters"] == 1
