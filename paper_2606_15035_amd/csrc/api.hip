@@ -4,6 +4,7 @@
 // gather + push, then a read-back of the two fixed-point errors).
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -70,16 +71,26 @@ ecpic_status check_config(const ecpic_config* c, int64_t np) {
   return ECPIC_OK;
 }
 
+int ilog2i(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
 Grid make_grid(const ecpic_config* c) {
   Grid G;
   G.ncell = 1;
   for (int a = 0; a < 3; ++a) {
     G.n[a] = c->n[a];
+    G.mask[a] = c->n[a] - 1;
     G.L[a] = c->L[a];
+    G.invL[a] = 1.0 / c->L[a];
     G.H[a] = c->L[a] / c->n[a];
     G.invH[a] = 1.0 / G.H[a];
     G.ncell *= c->n[a];
   }
+  G.shy = ilog2i(c->n[2]);
+  G.shx = G.shy + ilog2i(c->n[1]);
   G.dV = G.H[0] * G.H[1] * G.H[2];
   G.vol = G.L[0] * G.L[1] * G.L[2];
   return G;
@@ -125,6 +136,10 @@ struct ecpic_sim {
   double2* tw[3];
   Scratch sc;
   double* host = nullptr;  // pinned read-back
+  // kernel timing
+  bool profiling = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  ecpic_profile prof{};
   // energy bookkeeping
   double K = 0.0, W = 0.0;
   ecpic_energy en{};
@@ -284,6 +299,8 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
 
 void ecpic_destroy(ecpic_sim* S) {
   if (!S) return;
+  for (auto& e : S->ev)
+    if (e) (void)hipEventDestroy(e);
   if (S->host) (void)hipHostFree(S->host);
   delete S;
 }
@@ -335,7 +352,10 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   double2* cur = S->spec[S->cur];
   double2* nxt = S->spec[1 - S->cur];
 
+  const auto t_start = std::chrono::steady_clock::now();
+  const bool prof = S->profiling;
   launch_extrapolate(s, S->np, S->v, S->vprev, S->vit);  // v^{n+1,0} = 2 v^n - v^{n-1}
+  launch_reset_slots(s, S->sc.red, S_PIECES, 1);
   int p = 0, jcur = 1 - S->jlast;
   bool converged = false;
   double err_v = 0.0, err_J = INFINITY;
@@ -344,15 +364,31 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     double* Jprev = S->Jb[1 - jcur];
     launch_reset_slots(s, S->sc.red, S_DVMAX, 5);  // DVMAX, VMAX, DJMAX, JS, BAD
     launch_fill(s, 3 * nc, J, 0.0);
+    if (prof) HIPCHK(hipEventRecord(S->ev[0], s));
     launch_scatter(s, r, P, S->x, S->v, S->vit, J, S->sc);  // J^{n+1/2,p}
+    if (prof) HIPCHK(hipEventRecord(S->ev[1], s));
     RealIO jin = soa_io(J, nc, 3);
     fft3_forward(s, S->G, 3, S->Jh, &jin, p >= 1 ? Jprev : nullptr, twp(S), S->sc);
     launch_cn_update(s, F, cur, S->Jh, nxt, S->batch, S->sc);  // continuity + CN
     fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));         // grad phi^{n+1/2}, A^{n+1}
+    if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
     launch_gather_push(s, r, P, S->x, S->v, S->vit, S->vnew, S->gbuf, S->sc);  // v^{n+1,p+1}
+    if (prof) HIPCHK(hipEventRecord(S->ev[3], s));
     HIPCHK(hipGetLastError());
     ecpic_status st = sync_read(S, S_DVMAX, 5);
     if (st != ECPIC_OK) return st;
+    if (prof) {
+      float t01 = 0.f, t12 = 0.f, t23 = 0.f;
+      HIPCHK(hipEventElapsedTime(&t01, S->ev[0], S->ev[1]));
+      HIPCHK(hipEventElapsedTime(&t12, S->ev[1], S->ev[2]));
+      HIPCHK(hipEventElapsedTime(&t23, S->ev[2], S->ev[3]));
+      S->prof.ms[0] += t01;
+      S->prof.ms[1] += t12;
+      S->prof.ms[2] += t23;
+      S->prof.launches[0] += 1;
+      S->prof.launches[1] += 1;
+      S->prof.launches[2] += 1;
+    }
     const double dv = S->host[0], vm = S->host[1], dj = S->host[2], js = S->host[3];
     if (S->host[4] >= 2.0 || S->host[4] != S->host[4])
       return fail(ECPIC_ENONFINITE, "non-finite velocity in Picard pass %d", p);
@@ -374,6 +410,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   if (p > S->cfg.picard_max) p = S->cfg.picard_max;
 
   // consistency sweep of the accepted iterate (its orbit, current and fields)
+  if (prof) HIPCHK(hipEventRecord(S->ev[0], s));
   if (S->cfg.diagnostics) {
     launch_reset_slots(s, S->sc.red, S_RAMAX, 2);
     launch_half_U(s, S->G, cur, nxt, S->batch);
@@ -381,6 +418,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     fft3_inverse(s, S->G, 3, S->batch, &uo, twp(S));
     launch_sweep(s, r, P, S->x, S->v, S->vit, S->vnew, S->gbuf, S->Uhalf, S->sc);
   }
+  if (prof) HIPCHK(hipEventRecord(S->ev[1], s));
   // accept: x^{n+1} = x^n + dt vbar^p, v^{n-1} <- v^n, v^n <- v^{n+1,p+1}; fields of pass p
   launch_finalize(s, P, S->x, S->v, S->vprev, S->vit, S->vnew, S->sc);
   if (S->np <= 0) {
@@ -388,11 +426,26 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     launch_reset_slots(s, S->sc.red, S_WORK, 2);
   }
   launch_accept_A(s, nc, S->gbuf);
+  if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
   S->cur = 1 - S->cur;
   HIPCHK(hipGetLastError());
   ecpic_status st = sync_read(S, 0, S_NSLOTS);
   if (st != ECPIC_OK) return st;
   const double* h = S->host;
+  if (prof) {
+    float ta = 0.f, tb = 0.f;
+    HIPCHK(hipEventElapsedTime(&ta, S->ev[0], S->ev[1]));
+    HIPCHK(hipEventElapsedTime(&tb, S->ev[1], S->ev[2]));
+    if (S->cfg.diagnostics) {
+      S->prof.ms[3] += ta;
+      S->prof.launches[3] += 1;
+    }
+    S->prof.ms[4] += tb;
+    S->prof.launches[4] += 1;
+    S->prof.pieces += h[S_PIECES];
+    S->prof.ms[5] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    S->prof.launches[5] += 1;
+  }
   const double K1 = h[S_K], dK = h[S_DK], W1 = h[S_WNEXT], dW = h[S_DW], JE = h[S_JE];
   if (!std::isfinite(K1) || !std::isfinite(W1))
     return fail(ECPIC_ENONFINITE, "non-finite energy after the step");
@@ -556,6 +609,22 @@ ecpic_status ecpic_orbit_deposit(const ecpic_config* cfg, int64_t n, const doubl
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   launch_orbit_deposit_soa(s, cfg->spline_degree, make_grid(cfg), n, x0, d, qv, J);
   HIPCHK(hipGetLastError());
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_set_profiling(ecpic_sim* S, int32_t enable) {
+  if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  if (enable)
+    for (auto& e : S->ev)
+      if (!e) HIPCHK(hipEventCreate(&e));
+  S->profiling = enable != 0;
+  S->prof = ecpic_profile{};
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_get_profile(ecpic_sim* S, ecpic_profile* out) {
+  if (!S || !out) return fail(ECPIC_EINVAL, "null argument");
+  *out = S->prof;
   return ECPIC_OK;
 }
 

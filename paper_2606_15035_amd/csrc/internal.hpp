@@ -29,6 +29,7 @@ enum Slot : int {
   S_GL2,        // sum G_h^2                            (sum)
   S_RL2,        // sum R_h^2                            (sum)
   S_WCUR,       // W of the current field level         (sum)
+  S_PIECES,     // orbit pieces summed over particles    (sum of integers)
   S_NSLOTS
 };
 constexpr int kNumTickets = 8;

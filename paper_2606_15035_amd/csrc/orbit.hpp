@@ -21,9 +21,14 @@
 
 namespace ecpic {
 
+// Mesh sizes are powers of two, so periodic wrapping of a node index is a
+// bit mask and flat node indices are built with shifts.
 struct Grid {
   int n[3];
+  int mask[3];  // n - 1
+  int shx, shy; // flat index = (ix << shx) | (iy << shy) | iz
   double L[3];
+  double invL[3];
   double H[3];
   double invH[3];
   double dV;
@@ -31,9 +36,10 @@ struct Grid {
   int64_t ncell;
 };
 
-__device__ __forceinline__ int wrapi(int i, int n) {
-  int r = i % n;
-  return r < 0 ? r + n : r;
+__device__ __forceinline__ int wrapi(int i, int n) { return i & (n - 1); }
+
+__device__ __forceinline__ int node_index(const Grid& G, int ix, int iy, int iz) {
+  return ((ix & G.mask[0]) << G.shx) | ((iy & G.mask[1]) << G.shy) | (iz & G.mask[2]);
 }
 
 // Convert a floor()ed double to int without undefined behaviour for huge or
@@ -43,8 +49,9 @@ __device__ __forceinline__ int to_int_clamped(double f) {
   return (int)f;
 }
 
-__device__ __forceinline__ double wrap_pos(double x, double L) {
-  double w = x - L * floor(x / L);
+// x wrapped into [0, L); invL = 1/L
+__device__ __forceinline__ double wrap_pos(double x, double L, double invL) {
+  double w = x - L * floor(x * invL);
   if (w < 0.0) w += L;
   if (w >= L) w -= L;
   return w;
@@ -69,6 +76,16 @@ struct Spline<1> {
     d[0] = -1.0;
     d[1] = 1.0;
   }
+  // weight and derivative of stencil node k alone (k a constant after unrolling)
+  __device__ __forceinline__ static void wk(int k, double t, double& w, double& dw) {
+    if (k == 0) {
+      w = 1.0 - t;
+      dw = -1.0;
+    } else {
+      w = t;
+      dw = 1.0;
+    }
+  }
 };
 
 template <>
@@ -91,6 +108,20 @@ struct Spline<2> {
     d[0] = -a;
     d[1] = -2.0 * t;
     d[2] = b;
+  }
+  __device__ __forceinline__ static void wk(int k, double t, double& w, double& dw) {
+    if (k == 0) {
+      const double a = 0.5 - t;
+      w = 0.5 * a * a;
+      dw = -a;
+    } else if (k == 1) {
+      w = 0.75 - t * t;
+      dw = -2.0 * t;
+    } else {
+      const double b = 0.5 + t;
+      w = 0.5 * b * b;
+      dw = b;
+    }
   }
 };
 

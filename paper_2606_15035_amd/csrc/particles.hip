@@ -58,26 +58,26 @@ struct SoaFields {
 };
 
 __device__ __forceinline__ int64_t node_of(const Grid& G, int ix, int iy, int iz) {
-  return ((int64_t)ix * G.n[1] + iy) * G.n[2] + iz;
+  return node_index(G, ix, iy, iz);
 }
 
 // ---- one orbit piece: current scatter -------------------------------------
-// J_g += (q vbar / dV) int_{s0}^{s1} S_g(x(s)) ds   (eq. orbit-current, split form)
+// Iw[a][b][c] = int_{s0}^{s1} S_g(x(s)) ds for the stencil node first + (a, b, c)
+// (eq. split-Sbar); first is the unwrapped index of the piece's first stencil node.
 template <int R>
-__device__ __forceinline__ void scatter_piece(const Grid& G, const double* x0, const double* d,
-                                              double s0, double s1, const double* c3,
-                                              double* __restrict__ J) {
+__device__ __forceinline__ void piece_sbar(const Grid& G, const double* x0, const double* d,
+                                           double s0, double s1, double (&Iw)[R + 1][R + 1][R + 1],
+                                           int* first) {
   constexpr int W = R + 1, NQ = Quad<R>::NQ;
   const double h = s1 - s0;
   double base[3];
   piece_base<R>(x0, d, 0.5 * (s0 + s1), G, base);
-  double I[W][W][W];
 #pragma unroll
   for (int a = 0; a < W; ++a)
 #pragma unroll
     for (int b = 0; b < W; ++b)
 #pragma unroll
-      for (int c = 0; c < W; ++c) I[a][b][c] = 0.0;
+      for (int c = 0; c < W; ++c) Iw[a][b][c] = 0.0;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const double s = s0 + 0.5 * h * (1.0 + Gauss<NQ>::x(q));
@@ -93,24 +93,35 @@ __device__ __forceinline__ void scatter_piece(const Grid& G, const double* x0, c
       for (int b = 0; b < W; ++b) {
         const double xy = xa * wy[b];
 #pragma unroll
-        for (int c = 0; c < W; ++c) I[a][b][c] += xy * wz[c];
+        for (int c = 0; c < W; ++c) Iw[a][b][c] += xy * wz[c];
       }
     }
   }
-  const int fx = to_int_clamped(base[0]) + Spline<R>::first_off;
-  const int fy = to_int_clamped(base[1]) + Spline<R>::first_off;
-  const int fz = to_int_clamped(base[2]) + Spline<R>::first_off;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) first[a] = to_int_clamped(base[a]) + Spline<R>::first_off;
+}
+
+// J_g += (q vbar / dV) int_{s0}^{s1} S_g(x(s)) ds straight into global memory
+// (eq. orbit-current, split form)
+template <int R>
+__device__ __forceinline__ void scatter_piece(const Grid& G, const double* x0, const double* d,
+                                              double s0, double s1, const double* c3,
+                                              double* __restrict__ J) {
+  constexpr int W = R + 1;
+  double Iw[W][W][W];
+  int f[3];
+  piece_sbar<R>(G, x0, d, s0, s1, Iw, f);
   const int64_t nc = G.ncell;
 #pragma unroll
   for (int a = 0; a < W; ++a) {
-    const int ix = wrapi(fx + a, G.n[0]);
+    const int ix = wrapi(f[0] + a, G.n[0]);
 #pragma unroll
     for (int b = 0; b < W; ++b) {
-      const int iy = wrapi(fy + b, G.n[1]);
+      const int iy = wrapi(f[1] + b, G.n[1]);
 #pragma unroll
       for (int c = 0; c < W; ++c) {
-        const int64_t g = node_of(G, ix, iy, wrapi(fz + c, G.n[2]));
-        const double w = I[a][b][c];
+        const int64_t g = node_of(G, ix, iy, wrapi(f[2] + c, G.n[2]));
+        const double w = Iw[a][b][c];
         unsafeAtomicAdd(J + g, w * c3[0]);
         unsafeAtomicAdd(J + nc + g, w * c3[1]);
         unsafeAtomicAdd(J + 2 * nc + g, w * c3[2]);
@@ -207,6 +218,81 @@ __device__ __forceinline__ void gather_piece(const Grid& G, const double* x0, co
   }
 }
 
+// ---- one orbit piece: gather for the push ----------------------------------
+// The push needs grad phi-bar and (D A)^T vbar only.  With b_g(s) = vbar . A_g(s),
+//   ((D A)^T vbar)_j = sum_g int b_g(s) d_j S_g(x(s)) ds,
+// so each node first contracts its A^n, A^{n+1} with vbar and the quadrature
+// then carries one scalar per node instead of the 3x3 matrix D.
+// Per piece only the quadrature positions and the z weights are kept; the x
+// and y weights of a stencil node are re-evaluated where they are used.
+template <int R, class Acc>
+__device__ __forceinline__ void push_piece(const Grid& G, const double* x0, const double* d,
+                                           double s0, double s1, const double* vb,
+                                           const Acc& acc, double* gp, double* dtv) {
+  constexpr int W = R + 1, NQ = Quad<R>::NQ;
+  const double h = s1 - s0;
+  double base[3];
+  piece_base<R>(x0, d, 0.5 * (s0 + s1), G, base);
+  double tx[NQ], ty[NQ], sq[NQ], wq[NQ], Z[NQ][W], dZ[NQ][W];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double s = s0 + 0.5 * h * (1.0 + Gauss<NQ>::x(q));
+    sq[q] = s;
+    wq[q] = 0.5 * h * Gauss<NQ>::w(q);
+    tx[q] = (x0[0] + s * d[0]) * G.invH[0] - base[0];
+    ty[q] = (x0[1] + s * d[1]) * G.invH[1] - base[1];
+    Spline<R>::wd((x0[2] + s * d[2]) * G.invH[2] - base[2], Z[q], dZ[q]);
+#pragma unroll
+    for (int k = 0; k < W; ++k) dZ[q][k] *= G.invH[2];
+  }
+  const int fx = to_int_clamped(base[0]) + Spline<R>::first_off;
+  const int fy = to_int_clamped(base[1]) + Spline<R>::first_off;
+  const int fz = to_int_clamped(base[2]) + Spline<R>::first_off;
+#pragma unroll
+  for (int a = 0; a < W; ++a) {
+    double X[NQ], dX[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      Spline<R>::wk(a, tx[q], X[q], dX[q]);
+      dX[q] *= G.invH[0];
+    }
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      double xy[NQ], xyw[NQ], dxy[NQ], xdy[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        double Yq, dYq;
+        Spline<R>::wk(b, ty[q], Yq, dYq);
+        xy[q] = X[q] * Yq;
+        xyw[q] = xy[q] * wq[q];
+        dxy[q] = dX[q] * Yq;
+        xdy[q] = X[q] * (dYq * G.invH[1]);
+      }
+      const int row = (((fx + a) & G.mask[0]) << G.shx) | (((fy + b) & G.mask[1]) << G.shy);
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        const int g = row | ((fz + c) & G.mask[2]);
+        double f[9];
+        acc.load9(g, f);
+        const double a0 = vb[0] * f[3] + vb[1] * f[4] + vb[2] * f[5];  // vbar . A^n_g
+        const double da = vb[0] * f[6] + vb[1] * f[7] + vb[2] * f[8] - a0;
+        double I = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          I += xyw[q] * Z[q][c];
+          const double bw = wq[q] * (a0 + sq[q] * da);  // wt_q vbar . A_g(s_q)
+          dtv[0] += bw * (dxy[q] * Z[q][c]);
+          dtv[1] += bw * (xdy[q] * Z[q][c]);
+          dtv[2] += bw * (xy[q] * dZ[q][c]);
+        }
+        gp[0] += f[0] * I;
+        gp[1] += f[1] * I;
+        gp[2] += f[2] * I;
+      }
+    }
+  }
+}
+
 // point interpolant F_h(x) = sum_g F_g S_g(x) of A^n (which = 0) or A^{n+1} (which = 1)
 template <int R, class Acc>
 __device__ __forceinline__ void point_A(const Grid& G, const double* x, const Acc& acc, int which,
@@ -256,32 +342,133 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const double
   if (i < n3) vit[i] = 2.0 * v[i] - vprev[i];  // v^{n+1,0} = 2 v^n - v^{n-1}
 }
 
+// Orbit current of a block of particles.  With cell-sorted particles the
+// orbits of one block touch a small box of nodes: the block finds that box
+// (unwrapped indices relative to its first particle), accumulates the
+// current of all its orbits in an LDS tile with LDS atomics, and flushes the
+// tile to global memory with one atomic per non-zero node value.  Blocks whose
+// box does not fit the tile add straight to global memory.
+constexpr int kTileNodes = 1024;
+
+__device__ __forceinline__ int min_image(int raw, int n) {
+  int r = raw % n;
+  if (2 * r > n) r -= n;
+  if (2 * r < -n) r += n;
+  return r;
+}
+
+__device__ __forceinline__ int block_min_int(int v) {
+  __shared__ int lds_i[kBlock / kWave];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+  if (lane == 0) lds_i[wid] = v;
+  __syncthreads();
+  int r = lds_i[0];
+#pragma unroll
+  for (int w = 1; w < kBlock / kWave; ++w) r = min(r, lds_i[w]);
+  __syncthreads();
+  return r;
+}
+
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* __restrict__ x,
                                                    const double* __restrict__ v,
                                                    const double* __restrict__ vit,
                                                    double* __restrict__ J, Scratch sc) {
+  constexpr int W = R + 1;
+  __shared__ double tile[3 * kTileNodes];
+  __shared__ int s_ref[3];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool active = i < P.np;
   double js[1] = {0.0};
   double bad = 0.0;
-  if (i < P.np) {
-    double x0[3], vb[3], d[3], c3[3];
-    load3(x, P.np, i, x0);
+  double x0[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0}, c3[3] = {0.0, 0.0, 0.0};
+  int lo[3] = {0, 0, 0}, span[3] = {0, 0, 0};
+  if (active) {
     double va[3], vi[3];
+    load3(x, P.np, i, x0);
     load3(v, P.np, i, va);
     load3(vit, P.np, i, vi);
     const double qdv = P.q / P.G.dV;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      vb[a] = 0.5 * (vi[a] + va[a]);  // vbar^p = (v^{n+1,p} + v^n) / 2
-      d[a] = P.dt * vb[a];            // unwrapped displacement
-      c3[a] = qdv * vb[a];
+      const double vb = 0.5 * (vi[a] + va[a]);  // vbar^p = (v^{n+1,p} + v^n) / 2
+      d[a] = P.dt * vb;                         // unwrapped displacement
+      c3[a] = qdv * vb;
+      js[0] = fmax(js[0], fabs(vb));
+      // stencil nodes touched by the whole orbit along this axis, with one node
+      // of margin on each side against rounding of the piece midpoints
+      const double u0 = x0[a] * P.G.invH[a], u1 = (x0[a] + d[a]) * P.G.invH[a];
+      lo[a] = to_int_clamped(floor(fmin(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off - 1;
+      span[a] = to_int_clamped(floor(fmax(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off +
+                W - lo[a];
     }
-    js[0] = fabs(P.q) * fmax(fabs(vb[0]), fmax(fabs(vb[1]), fabs(vb[2]))) / P.G.vol;
+    js[0] *= fabs(P.q) / P.G.vol;
+  }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s_ref[a] = lo[a];
+  __syncthreads();
+  int shift[3], tlo[3], dim[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int raw = lo[a] - s_ref[a];
+    const int rel = min_image(raw, P.G.n[a]);
+    shift[a] = rel - raw;  // multiple of n[a]: the particle's frame -> the block's frame
+    tlo[a] = block_min_int(active ? rel : 0x3fffffff);
+    const int thi = -block_min_int(active ? -(rel + span[a]) : 0x3fffffff);
+    dim[a] = thi - tlo[a] + 1;
+  }
+  const bool use_tile = (int64_t)dim[0] * dim[1] * dim[2] <= kTileNodes;  // uniform per block
+  const int nt = use_tile ? dim[0] * dim[1] * dim[2] : 0;
+  for (int t = threadIdx.x; t < 3 * nt; t += kBlock) tile[t] = 0.0;
+  __syncthreads();
+  if (active) {
     const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
-      scatter_piece<R>(P.G, x0, d, s0, s1, c3, J);
+      if (use_tile) {
+        double Iw[W][W][W];
+        int f[3];
+        piece_sbar<R>(P.G, x0, d, s0, s1, Iw, f);
+        const int ox = f[0] - s_ref[0] + shift[0] - tlo[0];
+        const int oy = f[1] - s_ref[1] + shift[1] - tlo[1];
+        const int oz = f[2] - s_ref[2] + shift[2] - tlo[2];
+        const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + W <= dim[0] &&
+                            oy + W <= dim[1] && oz + W <= dim[2];
+        if (inside) {
+#pragma unroll
+          for (int a = 0; a < W; ++a)
+#pragma unroll
+            for (int b = 0; b < W; ++b)
+#pragma unroll
+              for (int c = 0; c < W; ++c) {
+                const int t = ((ox + a) * dim[1] + (oy + b)) * dim[2] + (oz + c);
+                const double w = Iw[a][b][c];
+                atomicAdd(&tile[3 * t + 0], w * c3[0]);
+                atomicAdd(&tile[3 * t + 1], w * c3[1]);
+                atomicAdd(&tile[3 * t + 2], w * c3[2]);
+              }
+        } else {  // not reached for a box computed as above; kept as a safe path
+          scatter_piece<R>(P.G, x0, d, s0, s1, c3, J);
+        }
+      } else {
+        scatter_piece<R>(P.G, x0, d, s0, s1, c3, J);
+      }
     });
     if (!ok) bad = 1.0;
+  }
+  __syncthreads();
+  const int64_t nc = P.G.ncell;
+  for (int t = threadIdx.x; t < nt; t += kBlock) {
+    const int cz = t % dim[2], cy = (t / dim[2]) % dim[1], cx = t / (dim[2] * dim[1]);
+    const int64_t g = node_of(P.G, wrapi(s_ref[0] + tlo[0] + cx, P.G.n[0]),
+                              wrapi(s_ref[1] + tlo[1] + cy, P.G.n[1]),
+                              wrapi(s_ref[2] + tlo[2] + cz, P.G.n[2]));
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const double val = tile[3 * t + l];
+      if (val != 0.0) unsafeAtomicAdd(J + l * nc + g, val);
+    }
   }
   block_max_to(bad, sc.red + S_BAD);
   grid_sum<1>(js, sc.partials, sc.ticket + 0, sc.red + S_JS);
@@ -295,6 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, const doub
                                                        Scratch sc) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double dvm = 0.0, vm = 0.0, bad = 0.0;
+  double npieces[1] = {0.0};
   if (i < P.np) {
     double x0[3], va[3], vi[3], vb[3], d[3];
     load3(x, P.np, i, x0);
@@ -306,25 +494,23 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, const doub
       d[a] = P.dt * vb[a];
     }
     double gp[3] = {0.0, 0.0, 0.0};
-    double D[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-    double Ub[3];
-    double pou = 0.0;
+    double dtv[3] = {0.0, 0.0, 0.0};  // (D A)^T vbar
     const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
-      gather_piece<R, false>(P.G, x0, d, s0, s1, F, nullptr, gp, D, Ub, pou);
+      push_piece<R>(P.G, x0, d, s0, s1, vb, F, gp, dtv);
+      npieces[0] += 1.0;
     });
     if (!ok) bad = 1.0;
     // A_h^n(x^n) rebuilds P^n = m v^n + q A_h^n(x^n) (eq. discrete-canonical-relation);
     // A_h^{n+1}(x^{n+1}) at the wrapped end point closes the velocity (eq. orbit-v-update).
     double x1[3], A0s[3], A1e[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], P.G.L[a]);
+    for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], P.G.L[a], P.G.invL[a]);
     point_A<R>(P.G, x0, F, 0, A0s);
     point_A<R>(P.G, x1, F, 1, A1e);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const double DTv = D[0][j] * vb[0] + D[1][j] * vb[1] + D[2][j] * vb[2];  // ((D A)^T vbar)_j
       const double Pn = P.m * va[j] + P.q * A0s[j];
-      const double P1 = Pn + P.dt * (-P.q * gp[j] + P.q * DTv);  // eq. orbit-P-update
+      const double P1 = Pn + P.dt * (-P.q * gp[j] + P.q * dtv[j]);  // eq. orbit-P-update
       const double vn = (P1 - P.q * A1e[j]) / P.m;               // eq. orbit-v-update
       vnew[j * P.np + i] = vn;
       dvm = fmax(dvm, fabs(vn - vi[j]));
@@ -335,6 +521,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, const doub
   block_max_to(dvm, sc.red + S_DVMAX);
   block_max_to(vm, sc.red + S_VMAX);
   block_max_to(bad, sc.red + S_BAD);
+  block_sum<1>(npieces);  // integer counts: the atomic sum is exact and order-free
+  if (threadIdx.x == 0 && npieces[0] > 0.0) unsafeAtomicAdd(sc.red + S_PIECES, npieces[0]);
 }
 
 // Consistency sweep of the accepted iterate: Ubar, Ebar = -gphibar - Ubar,
@@ -366,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, const double* __
     });
     double x1[3], A0s[3], A1e[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], P.G.L[a]);
+    for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], P.G.L[a], P.G.invL[a]);
     point_A<R>(P.G, x0, F, 0, A0s);
     point_A<R>(P.G, x1, F, 1, A1e);
 #pragma unroll
@@ -397,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, double* __res
     for (int a = 0; a < 3; ++a) {
       const int64_t k = a * P.np + i;
       const double vo = v[k], vi = vit[k], vn = vnew[k];
-      x[k] = wrap_pos(x[k] + P.dt * 0.5 * (vi + vo), P.G.L[a]);  // x^{n+1} = x^n + dt vbar^p
+      x[k] = wrap_pos(x[k] + P.dt * 0.5 * (vi + vo), P.G.L[a], P.G.invL[a]);  // x^{n+1} = x^n + dt vbar^p
       vprev[k] = vo;
       v[k] = vn;
       s[0] += 0.5 * P.m * vn * vn;
@@ -425,7 +613,7 @@ __global__ __launch_bounds__(kBlock) void k_wrap(StepParams P, double* __restric
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < P.np)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) x[a * P.np + i] = wrap_pos(x[a * P.np + i], P.G.L[a]);
+    for (int a = 0; a < 3; ++a) x[a * P.np + i] = wrap_pos(x[a * P.np + i], P.G.L[a], P.G.invL[a]);
 }
 
 // rho_g += q S_g(x_i) / dV (eq. source-moments), point shape
@@ -480,7 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_orbit_gather_soa(Grid G, int64_t n,
   });
   double x1[3], A0s[3], A1e[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], G.L[a]);
+  for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], G.L[a], G.invL[a]);
   point_A<R>(G, x0, F, 0, A0s);
   point_A<R>(G, x1, F, 1, A1e);
   double* o = out + 24 * i;

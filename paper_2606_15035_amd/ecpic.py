@@ -56,6 +56,16 @@ class Energy(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Profile(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("pieces", C.c_double)]
+
+    PHASES = ("scatter", "field_solve", "gather_push", "sweep", "finalize", "step")
+
+    def as_dict(self):
+        return {name: {"ms": self.ms[i], "launches": self.launches[i]}
+                for i, name in enumerate(self.PHASES)} | {"pieces": self.pieces}
+
+
 _lib = None
 
 
@@ -81,12 +91,15 @@ def lib():
         L.ecpic_get_current.argtypes = [P, D]
         L.ecpic_orbit_gather.argtypes = [cfgp, I64, D, D, D, D, D, D, D, P]
         L.ecpic_orbit_deposit.argtypes = [cfgp, I64, D, D, D, D, P]
+        L.ecpic_set_profiling.argtypes = [P, C.c_int32]
+        L.ecpic_get_profile.argtypes = [P, C.POINTER(Profile)]
         L.ecpic_last_error.restype = C.c_char_p
         L.ecpic_version.restype = C.c_char_p
         for name in ("ecpic_state_bytes", "ecpic_create", "ecpic_init_particles",
                      "ecpic_picard_step", "ecpic_field_solve", "ecpic_energy_diagnostics",
                      "ecpic_get_state", "ecpic_set_state", "ecpic_get_current",
-                     "ecpic_orbit_gather", "ecpic_orbit_deposit"):
+                     "ecpic_orbit_gather", "ecpic_orbit_deposit", "ecpic_set_profiling",
+                     "ecpic_get_profile"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -208,6 +221,14 @@ class Sim:
         args = [None if a is None else _host(a) for a in (x, v, vprev, fields)]
         self.q, self.m = q, m
         _check(lib().ecpic_set_state(self._h, *[_hp(a) for a in args], q, m))
+
+    def set_profiling(self, enable=True):
+        _check(lib().ecpic_set_profiling(self._h, int(bool(enable))))
+
+    def get_profile(self):
+        p = Profile()
+        _check(lib().ecpic_get_profile(self._h, C.byref(p)))
+        return p.as_dict()
 
     def get_current(self):
         J = np.zeros((3,) + self.n)
