@@ -75,7 +75,9 @@ typedef struct {
                                    the per-particle charge unit (0 = 2^40) */
   int32_t diagnostics;          /* 1: after each accepted step run the consistency sweep
                                    (R_particle, R_A, partition of unity) */
-  int32_t reserved;
+  int32_t sort_interval;        /* particles are re-sorted by mesh cell at the start of every
+                                   k-th step: 0 or 1 = every step, k > 1 = every k steps,
+                                   -1 = never (results are the same up to rounding) */
 } ecpic_config;
 
 typedef struct {

@@ -109,8 +109,6 @@ struct Carver {
   }
 };
 
-constexpr int kMaxSumValues = 4;
-
 }  // namespace
 
 struct ecpic_sim {
@@ -120,8 +118,10 @@ struct ecpic_sim {
   hipStream_t stream;
   double q = -1.0, m = 1.0;
   bool initialized = false;
-  // particles (state)
+  // particles (state), stored in cell-sorted order; id[i] = caller index
   double *x, *v, *vprev, *vit, *vnew;
+  int* id;
+  SortBuffers sb;
   // mesh (state)
   double2* spec[2];  // spectral levels (9 fields each); spec[cur] is level n
   int cur = 0;
@@ -158,6 +158,21 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->vprev = st.take<double>(n3);
   S->vit = st.take<double>(n3);
   S->vnew = st.take<double>(n3);
+  const size_t n1 = (size_t)(np > 0 ? np : 1);
+  S->id = st.take<int>(n1);
+  S->sb.x = &S->x;
+  S->sb.v = &S->v;
+  S->sb.vprev = &S->vprev;
+  S->sb.id = &S->id;
+  S->sb.x2 = st.take<double>(n3);
+  S->sb.v2 = st.take<double>(n3);
+  S->sb.vprev2 = st.take<double>(n3);
+  S->sb.id2 = st.take<int>(n1);
+  S->sb.key = st.take<int>(n1);
+  S->sb.count = st.take<int>(8 * nc);
+  S->sb.offset = st.take<int>(8 * nc + 1);
+  S->sb.cursor = st.take<int>(8 * nc);
+  S->sb.scan_totals = st.take<int>(sort_scan_blocks(nc));
   S->spec[0] = st.take<double2>(9 * nc);
   S->spec[1] = st.take<double2>(9 * nc);
   S->gbuf = st.take<double>(kGbufStride * nc);
@@ -170,9 +185,10 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->Uhalf = w.take<double>(3 * nc);
   for (int a = 0; a < 3; ++a) S->tw[a] = w.take<double2>(S->G.n[a] / 2);
   S->sc.red = w.take<double>(S_NSLOTS);
-  S->sc.ticket = w.take<unsigned>(kNumTickets);
-  const int64_t maxblk = std::max<int64_t>((np + kBlock - 1) / kBlock, (nc + kBlock - 1) / kBlock);
-  S->sc.partials = w.take<double>((size_t)kMaxSumValues * (maxblk > 0 ? maxblk : 1));
+  const int64_t maxblk = std::max<int64_t>(
+      std::max<int64_t>(particle_blocks(np), scatter_blocks(np)), mesh_blocks(nc));
+  S->sc.part_stride = (int64_t)kMaxSumValues * (maxblk > 0 ? maxblk : 1);
+  S->sc.part = w.take<double>((size_t)P_NSITES * S->sc.part_stride);
   if (state_bytes) *state_bytes = st.off + 256;
   if (ws_bytes) *ws_bytes = w.off + 256;
 }
@@ -220,8 +236,11 @@ ecpic_status load_fields_from_realbuf(ecpic_sim* S) {
 ecpic_status update_level_energies(ecpic_sim* S) {
   launch_kinetic(S->stream, S->pp(), S->v, S->sc);
   launch_field_energy(S->stream, S->fp(), S->spec[S->cur], S->sc);
+  const FinishJob jobs[2] = {{P_K, (int)particle_blocks(S->np), 2, S_K},
+                             {P_W, (int)mesh_blocks(S->G.ncell), 1, S_WCUR}};
+  launch_finish(S->stream, S->sc, S->np > 0 ? jobs : jobs + 1, S->np > 0 ? 2 : 1);
   HIPCHK(hipGetLastError());
-  if (S->np <= 0) launch_fill(S->stream, 1, S->sc.red + S_K, 0.0);
+  if (S->np <= 0) launch_fill(S->stream, 2, S->sc.red + S_K, 0.0);
   ecpic_status st = sync_read(S, 0, S_NSLOTS);
   if (st != ECPIC_OK) return st;
   S->K = S->host[S_K];
@@ -286,8 +305,7 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
       return fail(ECPIC_EDEVICE, "twiddle upload failed");
     }
   }
-  if (hipMemsetAsync(S->sc.ticket, 0, sizeof(unsigned) * kNumTickets, S->stream) != hipSuccess ||
-      hipMemsetAsync(S->sc.red, 0, sizeof(double) * S_NSLOTS, S->stream) != hipSuccess ||
+  if (hipMemsetAsync(S->sc.red, 0, sizeof(double) * S_NSLOTS, S->stream) != hipSuccess ||
       hipStreamSynchronize(S->stream) != hipSuccess) {
     (void)hipHostFree(S->host);
     delete S;
@@ -320,6 +338,7 @@ ecpic_status ecpic_init_particles(ecpic_sim* S, const double* x, const double* v
     HIPCHK(hipMemcpyAsync(S->vprev, v, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
   }
   launch_wrap_positions(S->stream, S->pp(), S->x);
+  launch_iota(S->stream, np, S->id);
   // rho^0: point-shape deposit, transformed; then the Poisson solve
   launch_fill(S->stream, nc, S->realbuf, 0.0);
   launch_deposit_rho(S->stream, S->cfg.spline_degree, S->pp(), S->x, S->realbuf);
@@ -354,6 +373,9 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
 
   const auto t_start = std::chrono::steady_clock::now();
   const bool prof = S->profiling;
+  const int sort_every = S->cfg.sort_interval <= 0 ? 1 : S->cfg.sort_interval;
+  if (S->cfg.sort_interval >= 0 && (S->en.step % sort_every) == 0)
+    launch_sort(s, S->G, S->np, S->sb);  // cell order of x^n
   launch_extrapolate(s, S->np, S->v, S->vprev, S->vit);  // v^{n+1,0} = 2 v^n - v^{n-1}
   launch_reset_slots(s, S->sc.red, S_PIECES, 1);
   int p = 0, jcur = 1 - S->jlast;
@@ -374,6 +396,11 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
     launch_gather_push(s, r, P, S->x, S->v, S->vit, S->vnew, S->gbuf, S->sc);  // v^{n+1,p+1}
     if (prof) HIPCHK(hipEventRecord(S->ev[3], s));
+    {
+      const FinishJob jobs[2] = {{P_JS, (int)scatter_blocks(S->np), 1, S_JS},
+                                 {P_CN, (int)mesh_blocks(nc), 3, S_JE}};
+      launch_finish(s, S->sc, S->np > 0 ? jobs : jobs + 1, S->np > 0 ? 2 : 1);
+    }
     HIPCHK(hipGetLastError());
     ecpic_status st = sync_read(S, S_DVMAX, 5);
     if (st != ECPIC_OK) return st;
@@ -426,6 +453,11 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     launch_reset_slots(s, S->sc.red, S_WORK, 2);
   }
   launch_accept_A(s, nc, S->gbuf);
+  if (S->np > 0) {
+    const FinishJob jobs[2] = {{P_K, (int)particle_blocks(S->np), 2, S_K},
+                               {P_SWEEP, (int)particle_blocks(S->np), 2, S_WORK}};
+    launch_finish(s, S->sc, jobs, S->cfg.diagnostics ? 2 : 1);
+  }
   if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
   S->cur = 1 - S->cur;
   HIPCHK(hipGetLastError());
@@ -490,6 +522,10 @@ ecpic_status ecpic_field_solve(ecpic_sim* S, const double* J_dev) {
   RealIO gout = gather_fields_out(S);
   fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));
   launch_accept_A(s, nc, S->gbuf);
+  {
+    const FinishJob job = {P_CN, (int)mesh_blocks(nc), 3, S_JE};
+    launch_finish(s, S->sc, &job, 1);
+  }
   S->cur = 1 - S->cur;
   HIPCHK(hipGetLastError());
   ecpic_status st = sync_read(S, 0, S_NSLOTS);
@@ -510,6 +546,11 @@ ecpic_status ecpic_energy_diagnostics(ecpic_sim* S, ecpic_energy* out) {
   RealIO o = soa_io(S->realbuf, nc, 2);
   fft3_inverse(s, S->G, 2, S->batch, &o, twp(S));
   launch_constraint_norms(s, nc, S->realbuf, S->realbuf + nc, S->sc);
+  {
+    const FinishJob jobs[2] = {{P_W, (int)mesh_blocks(nc), 1, S_WCUR},
+                               {P_NORM, (int)mesh_blocks(nc), 2, S_GL2}};
+    launch_finish(s, S->sc, jobs, 2);
+  }
   HIPCHK(hipGetLastError());
   ecpic_status st = sync_read(S, 0, S_NSLOTS);
   if (st != ECPIC_OK) return st;
@@ -529,11 +570,16 @@ ecpic_status ecpic_get_state(ecpic_sim* S, double* x, double* v, double* vprev, 
   if (!S) return fail(ECPIC_EINVAL, "null simulation");
   const int64_t np = S->np, nc = S->G.ncell;
   hipStream_t s = S->stream;
-  if (np > 0) {
-    if (x) HIPCHK(hipMemcpyAsync(x, S->x, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s));
-    if (v) HIPCHK(hipMemcpyAsync(v, S->v, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s));
-    if (vprev)
-      HIPCHK(hipMemcpyAsync(vprev, S->vprev, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s));
+  if (np > 0) {  // stored (cell-sorted) order -> caller order, through the iterate buffers
+    const double* src[3] = {S->x, S->v, S->vprev};
+    double* dst[3] = {x, v, vprev};
+    for (int k = 0; k < 3; ++k) {
+      if (!dst[k]) continue;
+      launch_to_caller(s, np, S->id, src[k], S->vit);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(dst[k], S->vit, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
   }
   if (fields) {
     launch_spec_copy(s, 9 * nc, S->spec[S->cur], S->batch, 1.0 / (double)nc);
@@ -554,11 +600,17 @@ ecpic_status ecpic_set_state(ecpic_sim* S, const double* x, const double* v, con
   hipStream_t s = S->stream;
   S->q = q;
   S->m = m;
-  if (np > 0) {
-    if (x) HIPCHK(hipMemcpyAsync(S->x, x, sizeof(double) * 3 * np, hipMemcpyHostToDevice, s));
-    if (v) HIPCHK(hipMemcpyAsync(S->v, v, sizeof(double) * 3 * np, hipMemcpyHostToDevice, s));
-    if (vprev)
-      HIPCHK(hipMemcpyAsync(S->vprev, vprev, sizeof(double) * 3 * np, hipMemcpyHostToDevice, s));
+  if (np > 0) {  // caller order -> stored order
+    if (!S->initialized) launch_iota(s, np, S->id);
+    const double* src[3] = {x, v, vprev};
+    double* dst[3] = {S->x, S->v, S->vprev};
+    for (int k = 0; k < 3; ++k) {
+      if (!src[k]) continue;
+      HIPCHK(hipMemcpyAsync(S->vit, src[k], sizeof(double) * 3 * np, hipMemcpyHostToDevice, s));
+      launch_from_caller(s, np, S->id, S->vit, dst[k]);
+      HIPCHK(hipGetLastError());
+    }
+    if (x) launch_wrap_positions(s, S->pp(), S->x);
   }
   if (fields) {
     HIPCHK(hipMemcpyAsync(S->realbuf, fields, sizeof(double) * 9 * nc, hipMemcpyHostToDevice, s));

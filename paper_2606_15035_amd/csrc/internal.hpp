@@ -32,7 +32,9 @@ enum Slot : int {
   S_PIECES,     // orbit pieces summed over particles    (sum of integers)
   S_NSLOTS
 };
-constexpr int kNumTickets = 8;
+// Producer sites of block partial sums (each has its own region).
+enum Site : int { P_JS = 0, P_CN, P_SWEEP, P_K, P_W, P_NORM, P_NSITES };
+constexpr int kMaxSumValues = 4;
 
 struct StepParams {
   Grid G;
@@ -41,10 +43,22 @@ struct StepParams {
 };
 
 struct Scratch {
-  double* red;       // S_NSLOTS
-  unsigned* ticket;  // kNumTickets
-  double* partials;  // max_values * max_blocks
+  double* red;          // S_NSLOTS
+  double* part;         // P_NSITES regions of part_stride doubles
+  int64_t part_stride;  // kMaxSumValues * (largest grid of a producing kernel)
+  __host__ __device__ double* region(int site) const { return part + site * part_stride; }
 };
+
+// One row reduction for the finishing kernel: M values of site `site`, each
+// over nb block partials, into red[slot .. slot + M).
+struct FinishJob {
+  int site, nb, M, slot;
+};
+void launch_finish(hipStream_t s, Scratch sc, const FinishJob* jobs, int njobs);
+// grid sizes of the producing kernels
+int64_t scatter_blocks(int64_t np);
+int64_t particle_blocks(int64_t np);
+int64_t mesh_blocks(int64_t ncell);
 
 // ---- particle kernels (particles.hip) ----
 void launch_extrapolate(hipStream_t s, int64_t np, const double* v, const double* vprev,
@@ -67,6 +81,29 @@ void launch_orbit_gather_soa(hipStream_t s, int r, const Grid& G, int64_t n, con
                              const double* A0, const double* A1, double* out);
 void launch_orbit_deposit_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
                               const double* d, const double* qv, double* J);
+
+// ---- particle sort (sort.hip) ----
+// Pointers to the live particle arrays (swapped with the alternates by the sort).
+struct SortBuffers {
+  double** x;
+  double** v;
+  double** vprev;
+  int** id;
+  double* x2;
+  double* v2;
+  double* vprev2;
+  int* id2;
+  int* key;     // np
+  int* count;   // 8 * ncell (cell x velocity octant)
+  int* offset;  // 8 * ncell + 1
+  int* cursor;  // 8 * ncell
+  int* scan_totals;  // sort_scan_blocks(ncell)
+};
+int64_t sort_scan_blocks(int64_t ncell);
+void launch_iota(hipStream_t s, int64_t n, int* p);
+void launch_sort(hipStream_t s, const Grid& G, int64_t np, SortBuffers& b);
+void launch_to_caller(hipStream_t s, int64_t np, const int* id, const double* src, double* dst);
+void launch_from_caller(hipStream_t s, int64_t np, const int* id, const double* src, double* dst);
 
 // ---- mesh kernels (mesh.hip) ----
 constexpr int kMaxBatch = 9;

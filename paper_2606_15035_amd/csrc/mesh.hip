@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_cn(CNArgs C) {
     sums[1] *= f;
     sums[2] *= f;
   }
-  grid_sum<3>(sums, C.sc.partials, C.sc.ticket + 3, C.sc.red + S_JE);  // S_JE, S_WNEXT, S_DW
+  block_partials<3>(sums, C.sc.region(P_CN));  // -> S_JE, S_WNEXT, S_DW
 }
 
 __global__ __launch_bounds__(kBlock) void k_half_U(Grid G, const double2* cur, const double2* next,
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_constraints(FieldParams F, const dou
     inv[nc + g] = cscale(rh, s);
     w[0] = mode_energy(k, phi, A, U, 0.5 / F.sigma1, 0.5 / F.sigma2) * G.dV / (double)nc;
   }
-  grid_sum<1>(w, sc.partials, sc.ticket + 4, sc.red + S_WCUR);
+  block_partials<1>(w, sc.region(P_W));  // -> S_WCUR
 }
 
 __global__ __launch_bounds__(kBlock) void k_field_energy(FieldParams F, const double2* cur,
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_field_energy(FieldParams F, const do
     w[0] = mode_energy(k, cur[F_PHI * nc + g], A, U, 0.5 / F.sigma1, 0.5 / F.sigma2) * G.dV /
            (double)nc;
   }
-  grid_sum<1>(w, sc.partials, sc.ticket + 4, sc.red + S_WCUR);
+  block_partials<1>(w, sc.region(P_W));  // -> S_WCUR
 }
 
 __global__ __launch_bounds__(kBlock) void k_norms(int64_t nc, const double* gf, const double* rf,
@@ -368,7 +368,28 @@ __global__ __launch_bounds__(kBlock) void k_norms(int64_t nc, const double* gf, 
   block_max_to(fabs(gv), sc.red + S_GMAX);
   block_max_to(fabs(rv), sc.red + S_RMAX);
   double s[2] = {gv * gv, rv * rv};
-  grid_sum<2>(s, sc.partials, sc.ticket + 5, sc.red + S_GL2);  // S_GL2, S_RL2 adjacent
+  block_partials<2>(s, sc.region(P_NORM));  // -> S_GL2, S_RL2
+}
+
+struct FinishArgs {
+  Scratch sc;
+  FinishJob job[4];
+  int njobs;
+};
+
+// One block: each requested row of block partials summed in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_finish(FinishArgs F) {
+  for (int j = 0; j < F.njobs; ++j) {
+    const FinishJob jb = F.job[j];
+    const double* region = F.sc.region(jb.site);
+    for (int m = 0; m < jb.M; ++m) {
+      double acc[1] = {0.0};
+#pragma unroll 8
+      for (int b = threadIdx.x; b < jb.nb; b += kBlock) acc[0] += region[(size_t)m * jb.nb + b];
+      block_sum<1>(acc);
+      if (threadIdx.x == 0) F.sc.red[jb.slot + m] = acc[0];
+    }
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_spec_copy(int64_t n, const double2* src, double2* dst,
@@ -501,6 +522,16 @@ void launch_accept_A(hipStream_t s, int64_t ncell, double* gbuf) {
 void launch_set_A0(hipStream_t s, int64_t ncell, const double* A, double* gbuf) {
   k_set_A0<<<blocks_for(ncell), kBlock, 0, s>>>(ncell, A, gbuf);
 }
+
+void launch_finish(hipStream_t s, Scratch sc, const FinishJob* jobs, int njobs) {
+  FinishArgs F;
+  F.sc = sc;
+  F.njobs = njobs < 4 ? njobs : 4;
+  for (int j = 0; j < F.njobs; ++j) F.job[j] = jobs[j];
+  if (F.njobs > 0) k_finish<<<1, kBlock, 0, s>>>(F);
+}
+
+int64_t mesh_blocks(int64_t ncell) { return (ncell + kBlock - 1) / kBlock; }
 
 void launch_fill(hipStream_t s, int64_t count, double* p, double value) {
   if (count <= 0) return;

@@ -342,13 +342,19 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const double
   if (i < n3) vit[i] = 2.0 * v[i] - vprev[i];  // v^{n+1,0} = 2 v^n - v^{n-1}
 }
 
-// Orbit current of a block of particles.  With cell-sorted particles the
-// orbits of one block touch a small box of nodes: the block finds that box
-// (unwrapped indices relative to its first particle), accumulates the
-// current of all its orbits in an LDS tile with LDS atomics, and flushes the
-// tile to global memory with one atomic per non-zero node value.  Blocks whose
-// box does not fit the tile add straight to global memory.
-constexpr int kTileNodes = 1024;
+// Orbit current of a chunk of kChunk particles per block.  Lanes take
+// particles with a stride of kChunk / 64 inside the chunk, so that for
+// cell-sorted particles the 64 lanes of a wavefront sit in ~kChunk / 64 / ppc
+// different cells and their LDS atomics rarely hit the same address.
+// Pass 1 finds the box of nodes the chunk's orbits touch (unwrapped indices
+// relative to the chunk's first particle, one node of margin per side);
+// pass 2 accumulates the current in an LDS tile over that box; the tile is
+// then flushed with one global atomic per non-zero node value.  A chunk whose
+// box exceeds the tile adds straight to global memory.
+constexpr int kTileNodes = 2048;
+constexpr int kChunk = 2048;
+constexpr int kPerThread = kChunk / kBlock;  // particles per thread
+constexpr int kSlot = kChunk / kWave;        // sorted particles per lane slot
 
 __device__ __forceinline__ int min_image(int raw, int n) {
   int r = raw % n;
@@ -371,6 +377,27 @@ __device__ __forceinline__ int block_min_int(int v) {
   return r;
 }
 
+__device__ __forceinline__ int64_t chunk_particle(int64_t base, int k) {
+  return base + (int64_t)(threadIdx.x % kWave) * kSlot + threadIdx.x / kWave +
+         (int64_t)(kBlock / kWave) * k;
+}
+
+template <int R>
+__device__ __forceinline__ void orbit_of(const StepParams& P, const double* __restrict__ x,
+                                         const double* __restrict__ v,
+                                         const double* __restrict__ vit, int64_t i, double* x0,
+                                         double* d, double* vb) {
+  double va[3], vi[3];
+  load3(x, P.np, i, x0);
+  load3(v, P.np, i, va);
+  load3(vit, P.np, i, vi);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vb[a] = 0.5 * (vi[a] + va[a]);  // vbar^p = (v^{n+1,p} + v^n) / 2
+    d[a] = P.dt * vb[a];            // unwrapped displacement
+  }
+}
+
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* __restrict__ x,
                                                    const double* __restrict__ v,
@@ -379,80 +406,97 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* 
   constexpr int W = R + 1;
   __shared__ double tile[3 * kTileNodes];
   __shared__ int s_ref[3];
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool active = i < P.np;
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
   double js[1] = {0.0};
   double bad = 0.0;
-  double x0[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0}, c3[3] = {0.0, 0.0, 0.0};
-  int lo[3] = {0, 0, 0}, span[3] = {0, 0, 0};
-  if (active) {
-    double va[3], vi[3];
-    load3(x, P.np, i, x0);
-    load3(v, P.np, i, va);
-    load3(vit, P.np, i, vi);
-    const double qdv = P.q / P.G.dV;
+  if (threadIdx.x == 0) {  // the chunk's first particle is the reference cell
+    double x0[3];
+    load3(x, P.np, base, x0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      s_ref[a] = to_int_clamped(floor(x0[a] * P.G.invH[a] + Spline<R>::base_off));
+  }
+  __syncthreads();
+  // pass 1: node box of the chunk's orbits
+  int rmin[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, rmax[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t i = chunk_particle(base, k);
+    if (i >= P.np) continue;
+    double x0[3], d[3], vb[3];
+    orbit_of<R>(P, x, v, vit, i, x0, d, vb);
+    js[0] += fabs(P.q) * fmax(fabs(vb[0]), fmax(fabs(vb[1]), fabs(vb[2]))) / P.G.vol;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double vb = 0.5 * (vi[a] + va[a]);  // vbar^p = (v^{n+1,p} + v^n) / 2
-      d[a] = P.dt * vb;                         // unwrapped displacement
-      c3[a] = qdv * vb;
-      js[0] = fmax(js[0], fabs(vb));
-      // stencil nodes touched by the whole orbit along this axis, with one node
-      // of margin on each side against rounding of the piece midpoints
       const double u0 = x0[a] * P.G.invH[a], u1 = (x0[a] + d[a]) * P.G.invH[a];
-      lo[a] = to_int_clamped(floor(fmin(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off - 1;
-      span[a] = to_int_clamped(floor(fmax(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off +
-                W - lo[a];
+      const int lo = to_int_clamped(floor(fmin(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off - 1;
+      const int hi = to_int_clamped(floor(fmax(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off + W;
+      const int rel = min_image(lo - s_ref[a], P.G.n[a]);
+      rmin[a] = min(rmin[a], rel);
+      rmax[a] = max(rmax[a], rel + (hi - lo));
     }
-    js[0] *= fabs(P.q) / P.G.vol;
   }
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) s_ref[a] = lo[a];
-  __syncthreads();
-  int shift[3], tlo[3], dim[3];
+  int tlo[3], dim[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int raw = lo[a] - s_ref[a];
-    const int rel = min_image(raw, P.G.n[a]);
-    shift[a] = rel - raw;  // multiple of n[a]: the particle's frame -> the block's frame
-    tlo[a] = block_min_int(active ? rel : 0x3fffffff);
-    const int thi = -block_min_int(active ? -(rel + span[a]) : 0x3fffffff);
-    dim[a] = thi - tlo[a] + 1;
+    tlo[a] = block_min_int(rmin[a]);
+    dim[a] = -block_min_int(-rmax[a]) - tlo[a] + 1;
   }
-  const bool use_tile = (int64_t)dim[0] * dim[1] * dim[2] <= kTileNodes;  // uniform per block
+  const bool use_tile = dim[0] > 0 && (int64_t)dim[0] * dim[1] * dim[2] <= kTileNodes;  // block-uniform
   const int nt = use_tile ? dim[0] * dim[1] * dim[2] : 0;
   for (int t = threadIdx.x; t < 3 * nt; t += kBlock) tile[t] = 0.0;
   __syncthreads();
-  if (active) {
+  // pass 2: accumulate
+  const double qdv = P.q / P.G.dV;
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t i = chunk_particle(base, k);
+    if (i >= P.np) continue;
+    double x0[3], d[3], vb[3], c3[3];
+    orbit_of<R>(P, x, v, vit, i, x0, d, vb);
+    int shift[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c3[a] = qdv * vb[a];
+      const double u0 = x0[a] * P.G.invH[a], u1 = (x0[a] + d[a]) * P.G.invH[a];
+      const int lo = to_int_clamped(floor(fmin(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off - 1;
+      const int raw = lo - s_ref[a];
+      shift[a] = min_image(raw, P.G.n[a]) - raw;  // particle frame -> chunk frame
+    }
     const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
-      if (use_tile) {
-        double Iw[W][W][W];
-        int f[3];
-        piece_sbar<R>(P.G, x0, d, s0, s1, Iw, f);
-        const int ox = f[0] - s_ref[0] + shift[0] - tlo[0];
-        const int oy = f[1] - s_ref[1] + shift[1] - tlo[1];
-        const int oz = f[2] - s_ref[2] + shift[2] - tlo[2];
-        const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + W <= dim[0] &&
-                            oy + W <= dim[1] && oz + W <= dim[2];
-        if (inside) {
+      double Iw[W][W][W];
+      int f[3];
+      piece_sbar<R>(P.G, x0, d, s0, s1, Iw, f);
+      const int ox = f[0] - s_ref[0] + shift[0] - tlo[0];
+      const int oy = f[1] - s_ref[1] + shift[1] - tlo[1];
+      const int oz = f[2] - s_ref[2] + shift[2] - tlo[2];
+      const bool inside = use_tile && ox >= 0 && oy >= 0 && oz >= 0 && ox + W <= dim[0] &&
+                          oy + W <= dim[1] && oz + W <= dim[2];
+      if (inside) {
 #pragma unroll
-          for (int a = 0; a < W; ++a)
+        for (int a = 0; a < W; ++a)
 #pragma unroll
-            for (int b = 0; b < W; ++b)
+          for (int b = 0; b < W; ++b)
 #pragma unroll
-              for (int c = 0; c < W; ++c) {
-                const int t = ((ox + a) * dim[1] + (oy + b)) * dim[2] + (oz + c);
-                const double w = Iw[a][b][c];
-                atomicAdd(&tile[3 * t + 0], w * c3[0]);
-                atomicAdd(&tile[3 * t + 1], w * c3[1]);
-                atomicAdd(&tile[3 * t + 2], w * c3[2]);
-              }
-        } else {  // not reached for a box computed as above; kept as a safe path
-          scatter_piece<R>(P.G, x0, d, s0, s1, c3, J);
-        }
+            for (int c = 0; c < W; ++c) {
+              const int t = ((ox + a) * dim[1] + (oy + b)) * dim[2] + (oz + c);
+              const double w = Iw[a][b][c];
+              atomicAdd(&tile[3 * t + 0], w * c3[0]);
+              atomicAdd(&tile[3 * t + 1], w * c3[1]);
+              atomicAdd(&tile[3 * t + 2], w * c3[2]);
+            }
       } else {
-        scatter_piece<R>(P.G, x0, d, s0, s1, c3, J);
+        const int64_t nc = P.G.ncell;
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+#pragma unroll
+          for (int b = 0; b < W; ++b)
+#pragma unroll
+            for (int c = 0; c < W; ++c) {
+              const int64_t g = node_index(P.G, f[0] + a, f[1] + b, f[2] + c);
+              const double w = Iw[a][b][c];
+              unsafeAtomicAdd(J + g, w * c3[0]);
+              unsafeAtomicAdd(J + nc + g, w * c3[1]);
+              unsafeAtomicAdd(J + 2 * nc + g, w * c3[2]);
+            }
       }
     });
     if (!ok) bad = 1.0;
@@ -461,9 +505,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* 
   const int64_t nc = P.G.ncell;
   for (int t = threadIdx.x; t < nt; t += kBlock) {
     const int cz = t % dim[2], cy = (t / dim[2]) % dim[1], cx = t / (dim[2] * dim[1]);
-    const int64_t g = node_of(P.G, wrapi(s_ref[0] + tlo[0] + cx, P.G.n[0]),
-                              wrapi(s_ref[1] + tlo[1] + cy, P.G.n[1]),
-                              wrapi(s_ref[2] + tlo[2] + cz, P.G.n[2]));
+    const int64_t g = node_index(P.G, s_ref[0] + tlo[0] + cx, s_ref[1] + tlo[1] + cy,
+                                 s_ref[2] + tlo[2] + cz);
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       const double val = tile[3 * t + l];
@@ -471,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* 
     }
   }
   block_max_to(bad, sc.red + S_BAD);
-  grid_sum<1>(js, sc.partials, sc.ticket + 0, sc.red + S_JS);
+  block_partials<1>(js, sc.region(P_JS));
 }
 
 template <int R>
@@ -570,7 +613,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, const double* __
   block_max_to(ramax, sc.red + S_RAMAX);
   block_max_to(poudev, sc.red + S_POU);
   double s2[2] = {sums[0], sums[1]};
-  grid_sum<2>(s2, sc.partials, sc.ticket + 1, sc.red + S_WORK);  // S_WORK, S_RA2 adjacent
+  block_partials<2>(s2, sc.region(P_SWEEP));  // -> S_WORK, S_RA2
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, double* __restrict__ x,
@@ -592,7 +635,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, double* __res
       s[1] += 0.5 * P.m * (vn - vo) * (vn + vo);
     }
   }
-  grid_sum<2>(s, sc.partials, sc.ticket + 2, sc.red + S_K);  // S_K, S_DK adjacent
+  block_partials<2>(s, sc.region(P_K));  // -> S_K, S_DK
 }
 
 __global__ __launch_bounds__(kBlock) void k_kinetic(StepParams P, const double* __restrict__ v,
@@ -606,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(StepParams P, const double* 
       s[0] += 0.5 * P.m * va * va;
     }
   }
-  grid_sum<2>(s, sc.partials, sc.ticket + 2, sc.red + S_K);
+  block_partials<2>(s, sc.region(P_K));
 }
 
 __global__ __launch_bounds__(kBlock) void k_wrap(StepParams P, double* __restrict__ x) {
@@ -709,6 +752,9 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 }  // namespace
 
+int64_t scatter_blocks(int64_t np) { return (np + kChunk - 1) / kChunk; }
+int64_t particle_blocks(int64_t np) { return (np + kBlock - 1) / kBlock; }
+
 // ---- launchers ---------------------------------------------------------------
 
 void launch_extrapolate(hipStream_t s, int64_t np, const double* v, const double* vprev,
@@ -720,10 +766,11 @@ void launch_extrapolate(hipStream_t s, int64_t np, const double* v, const double
 void launch_scatter(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
                     const double* vit, double* J, Scratch sc) {
   if (P.np <= 0) return;
+  const unsigned nblk = (unsigned)((P.np + kChunk - 1) / kChunk);
   if (r == 1)
-    k_scatter<1><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, J, sc);
+    k_scatter<1><<<nblk, kBlock, 0, s>>>(P, x, v, vit, J, sc);
   else
-    k_scatter<2><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, J, sc);
+    k_scatter<2><<<nblk, kBlock, 0, s>>>(P, x, v, vit, J, sc);
 }
 
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const double* x,

@@ -1,8 +1,7 @@
 // Wavefront and block reductions for gfx950 (wave64).
 //
-// Sums are deterministic: every block writes its partial sums, the last
-// block to finish (found with an atomic ticket) adds all partials in a fixed
-// order and writes the totals.  Maxima of non-negative doubles use atomicMax
+// Sums are deterministic: every block writes its partial sums and a
+// one-block kernel adds them in a fixed order.  Maxima of non-negative doubles use atomicMax
 // on the IEEE bit pattern, which orders like the values and is
 // order-independent.
 #pragma once
@@ -69,40 +68,17 @@ __device__ __forceinline__ void block_max_to(double v, double* slot) {
     atomicMax(reinterpret_cast<unsigned long long*>(slot), (unsigned long long)__double_as_longlong(r));
 }
 
-// Deterministic grid-wide sum of M values per thread.  partials must hold
-// M * gridDim.x doubles, ticket one zero-initialised unsigned (left at zero
-// again on exit), out M doubles.
+// Grid-wide sums, deterministic: every block writes its M block sums to
+// region[m * gridDim.x + blockIdx.x]; a one-block finishing kernel (launched
+// by the host after the producing kernels) adds each row in a fixed order.
+// The kernel boundary in between makes the partials visible; no device-scope
+// fences are needed inside the producing kernels.
 template <int M>
-__device__ __forceinline__ void grid_sum(double (&v)[M], double* partials, unsigned* ticket,
-                                         double* out) {
+__device__ __forceinline__ void block_partials(double (&v)[M], double* region) {
   block_sum<M>(v);
-  __shared__ int is_last;
-  const unsigned nb = gridDim.x;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
 #pragma unroll
-    for (int m = 0; m < M; ++m) partials[(size_t)m * nb + blockIdx.x] = v[m];
-    __threadfence();
-    const unsigned prev = atomicAdd(ticket, 1u);
-    is_last = (prev == nb - 1);
-  }
-  __syncthreads();
-  if (is_last) {
-    __threadfence();
-    double acc[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      acc[m] = 0.0;
-      for (unsigned b = threadIdx.x; b < nb; b += kBlock)
-        acc[m] += __hip_atomic_load(&partials[(size_t)m * nb + b], __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-    }
-    block_sum<M>(acc);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int m = 0; m < M; ++m) out[m] = acc[m];
-      *ticket = 0u;
-    }
-  }
+    for (int m = 0; m < M; ++m) region[(size_t)m * gridDim.x + blockIdx.x] = v[m];
 }
 
 }  // namespace ecpic
