@@ -32,24 +32,32 @@ PEAK_HBM_GBS = 8000.0
 
 
 def gather_flops_per_push(r: int, pieces_per_orbit: float) -> float:
-    """FP64 operations of the gather + push kernel per particle-push (an FMA
-    counts 2).  Derivation in the design notes: per orbit piece the quadrature
-    setup, the per-(a, b) products and the per-node weight integrals and field
-    contraction; per particle the two point interpolants of A and the push."""
+    """Algorithmic FP64 operations of the gather + push kernel per
+    particle-push (an FMA counts 2), as written in push_piece / point_A /
+    k_gather_push.  Per orbit piece (r = 2, 4-point rule, 27 nodes):
+    27 nodes x 73 (vbar.A^n, vbar.(A^{n+1}-A^n), 4 x [I, weight, 3 products
+    of d_j S] , grad phi contraction) + 9 (a, b) pairs x 36 + 3 x 20 (x
+    weights) + 4 x 30 (positions, z weights) + 20 = 2500.  Per particle:
+    two point interpolants of A (2 x 230), the momentum update and velocity
+    closure (36), orbit set-up and error maxima (~34) = 530.  For r = 1 the
+    same terms give 510 per piece and 250 per particle."""
     if r == 2:
-        per_piece = 20 + 4 * 67 + 9 * 4 * 3 + 27 * (4 * 14 + 42)
-        per_particle = 550
-    else:
-        per_piece = 20 + 2 * 53 + 4 * 2 * 3 + 8 * (2 * 14 + 42)
-        per_particle = 200
-    return per_particle + pieces_per_orbit * per_piece
+        return 530.0 + pieces_per_orbit * 2500.0
+    return 250.0 + pieces_per_orbit * 510.0
 
 
 def gather_bytes_per_push() -> float:
     """Algorithmic HBM bytes of the gather + push kernel per particle-push:
     read x^n, v^n, v^{n+1,p} (3 x 24 B), write v^{n+1,p+1} (24 B); the mesh
-    fields (80 B per node) stay in L2 / MALL and are not counted."""
+    fields (80 B per node, 2.6 MB at 32^3) stay in L2 / MALL."""
     return 96.0
+
+
+# Calibrated HBM traffic per launch of k_gather_push<2> on the 32^3 /
+# 2,097,152-particle workload, from FETCH_SIZE and WRITE_SIZE runs scaled by
+# the same counters on a streaming kernel of known size; valid only for the
+# library version it was measured on (profiles/hbm_traffic_gather_scatter_32cubed_fp64.md).
+MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.2", "workload": "c2", "bytes": 207.5e6}
 
 
 def run_cpu_baseline(wl, seconds_budget=30.0):
@@ -128,8 +136,14 @@ def main():
     flops = gather_flops_per_push(wl.r, pieces_per_orbit) * wl.np
     achieved_tflops = flops / avg_gather_s / 1e12
     hbm_gbs = gather_bytes_per_push() * wl.np / avg_gather_s / 1e9
+    version = E.lib().ecpic_version().decode()
+    traffic = None
+    if (MEASURED_GATHER_TRAFFIC["version"] == version
+            and MEASURED_GATHER_TRAFFIC["workload"] == args.workload):
+        traffic = MEASURED_GATHER_TRAFFIC["bytes"]
     roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
+                "library": version,
                 "kernel": "orbit gather + push (k_gather_push<2>)",
                 "avg_launch_ms": avg_gather_s * 1e3, "pieces_per_orbit": pieces_per_orbit,
                 "hbm_algorithmic_GBs": hbm_gbs, "hbm_frac": hbm_gbs / PEAK_HBM_GBS}

@@ -682,6 +682,6 @@ ecpic_status ecpic_get_profile(ecpic_sim* S, ecpic_profile* out) {
 
 const char* ecpic_last_error(void) { return g_err.c_str(); }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.1"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.2"; }
 
 }  // extern "C"

@@ -1,0 +1,95 @@
+"""The C ABI library loads and exports every function include/ecpic.h
+declares; configuration checks and state sizing run on the host (no GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2606_15035_amd import ecpic as E
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ecpic.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(E.LIB_PATH):
+        from paper_2606_15035_amd import build as B
+        B.build()
+    return E.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ecpic_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    raw = C.CDLL(E.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+
+
+def test_version_and_empty_error(lib):
+    assert lib.ecpic_version().decode().startswith("ecpic-gfx950")
+    assert isinstance(lib.ecpic_last_error(), bytes)
+
+
+def good_cfg(**kw):
+    args = dict(n=(32, 32, 32), L=(1.0, 1.0, 1.0), dt=0.1, r=2)
+    args.update(kw)
+    return E.make_config(**args)
+
+
+def test_state_bytes_scale_with_particles(lib):
+    s1, w1 = E.state_bytes(good_cfg(), 1000)
+    s2, w2 = E.state_bytes(good_cfg(), 2000)
+    per = (s2 - s1) / 1000
+    # x, v, v^{n-1}, two iterates, the sort's second x, v, v^{n-1} (8 x 24 B)
+    # plus id, second id and key (3 x 4 B), up to 256-byte alignment padding
+    assert 204 <= per <= 210
+    assert w2 >= w1 > 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=(32, 32, 30)),                 # not a power of two
+    dict(n=(2, 32, 32)),                  # too small
+    dict(r=3),                            # spline degree
+    dict(kappa=2.0),                      # sigma1 != kappa^2 sigma2
+    dict(dt=0.0),
+    dict(pmax=-1),
+    dict(tol=-1.0),
+])
+def test_invalid_configurations_are_rejected(lib, bad):
+    with pytest.raises(E.EcpicError) as ei:
+        E.state_bytes(good_cfg(**bad), 10)
+    assert ei.value.status == E.EINVAL
+    assert len(lib.ecpic_last_error()) > 0
+
+
+def test_maxwell_scaling_accepted_when_consistent(lib):
+    E.state_bytes(good_cfg(kappa=2.0, sigma1=4.0, sigma2=1.0), 10)
+
+
+def test_negative_particle_count_rejected(lib):
+    with pytest.raises(E.EcpicError):
+        E.state_bytes(good_cfg(), -1)
+
+
+def test_create_rejects_small_or_misaligned_buffers(lib):
+    cfg = good_cfg()
+    s, w = E.state_bytes(cfg, 100)
+    h = C.c_void_p()
+    # buffers too small (addresses are never dereferenced: the size check comes first)
+    st = lib.ecpic_create(C.byref(cfg), 100, C.c_void_p(4096), 16, C.c_void_p(8192), 16, None,
+                          C.byref(h))
+    assert st == E.ENOMEM
+    st = lib.ecpic_create(C.byref(cfg), 100, C.c_void_p(4096 + 8), s, C.c_void_p(8192), w, None,
+                          C.byref(h))
+    assert st == E.EINVAL
+    st = lib.ecpic_create(C.byref(cfg), 100, None, s, None, w, None, C.byref(h))
+    assert st == E.EINVAL
