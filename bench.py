@@ -33,17 +33,20 @@ PEAK_HBM_GBS = 8000.0
 
 def gather_flops_per_push(r: int, pieces_per_orbit: float) -> float:
     """Algorithmic FP64 operations of the gather + push kernel per
-    particle-push (an FMA counts 2), as written in push_piece / point_A /
-    k_gather_push.  Per orbit piece (r = 2, 4-point rule, 27 nodes):
-    27 nodes x 73 (vbar.A^n, vbar.(A^{n+1}-A^n), 4 x [I, weight, 3 products
-    of d_j S] , grad phi contraction) + 9 (a, b) pairs x 36 + 3 x 20 (x
-    weights) + 4 x 30 (positions, z weights) + 20 = 2500.  Per particle:
-    two point interpolants of A (2 x 230), the momentum update and velocity
-    closure (36), orbit set-up and error maxima (~34) = 530.  For r = 1 the
-    same terms give 510 per piece and 250 per particle."""
+    particle-push (an FMA counts 2), as written in push_piece / point_A_acc /
+    gather_push_one.  Per orbit piece (r = 2, 4-point rule, 3x3x3 nodes):
+    quadrature positions and z weights 123; x weights 3 x 24; per z column
+    (9) y weights and column products 28 + closing (D A)^T vbar sums 24;
+    per node (27) vbar . A^n and vbar . (A^{n+1} - A^n) 11, per quadrature
+    point I, b_g(s_q), B_q, B'_q 8 (6 on a column's first node), grad phi
+    contraction 6: 1251; knot-merge bookkeeping 6; total 1920.  Per particle:
+    two point interpolants of A (2 x 228), the momentum update and velocity
+    closure (36), orbit set-up, end-point wrap, crossing set-up and error
+    maxima (~66) = 560.  For r = 1 (2-point rule, 2x2x2 nodes) the same
+    terms give 410 per piece and 250 per particle."""
     if r == 2:
-        return 530.0 + pieces_per_orbit * 2500.0
-    return 250.0 + pieces_per_orbit * 510.0
+        return 560.0 + pieces_per_orbit * 1920.0
+    return 250.0 + pieces_per_orbit * 410.0
 
 
 def gather_bytes_per_push() -> float:
@@ -57,7 +60,7 @@ def gather_bytes_per_push() -> float:
 # 2,097,152-particle workload, from FETCH_SIZE and WRITE_SIZE runs scaled by
 # the same counters on a streaming kernel of known size; valid only for the
 # library version it was measured on (profiles/hbm_traffic_gather_scatter_32cubed_fp64.md).
-MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.2", "workload": "c2", "bytes": 207.5e6}
+MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.3", "workload": "c2", "bytes": 209.7e6}
 
 
 def run_cpu_baseline(wl, seconds_budget=30.0):
@@ -144,7 +147,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "library": version,
-                "kernel": "orbit gather + push (k_gather_push<2>)",
+                "kernel": "orbit gather + push (k_gather_push<2, true>)",
                 "avg_launch_ms": avg_gather_s * 1e3, "pieces_per_orbit": pieces_per_orbit,
                 "hbm_algorithmic_GBs": hbm_gbs, "hbm_frac": hbm_gbs / PEAK_HBM_GBS}
 

@@ -133,6 +133,7 @@ struct ecpic_sim {
   double2* batch;
   double* realbuf;
   double* Uhalf;
+  int* gflags;  // per-block "box did not fit the LDS tile" flags of the gather
   double2* tw[3];
   Scratch sc;
   double* host = nullptr;  // pinned read-back
@@ -184,6 +185,7 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->realbuf = w.take<double>(9 * nc);
   S->Uhalf = w.take<double>(3 * nc);
   for (int a = 0; a < 3; ++a) S->tw[a] = w.take<double2>(S->G.n[a] / 2);
+  S->gflags = w.take<int>(particle_blocks(np) > 0 ? particle_blocks(np) : 1);
   S->sc.red = w.take<double>(S_NSLOTS);
   const int64_t maxblk = std::max<int64_t>(
       std::max<int64_t>(particle_blocks(np), scatter_blocks(np)), mesh_blocks(nc));
@@ -306,6 +308,8 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
     }
   }
   if (hipMemsetAsync(S->sc.red, 0, sizeof(double) * S_NSLOTS, S->stream) != hipSuccess ||
+      hipMemsetAsync(S->gflags, 0, sizeof(int) * std::max<int64_t>(particle_blocks(n_particles), 1),
+                     S->stream) != hipSuccess ||
       hipStreamSynchronize(S->stream) != hipSuccess) {
     (void)hipHostFree(S->host);
     delete S;
@@ -394,7 +398,8 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     launch_cn_update(s, F, cur, S->Jh, nxt, S->batch, S->sc);  // continuity + CN
     fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));         // grad phi^{n+1/2}, A^{n+1}
     if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
-    launch_gather_push(s, r, P, S->x, S->v, S->vit, S->vnew, S->gbuf, S->sc);  // v^{n+1,p+1}
+    launch_gather_push(s, r, P, S->x, S->v, S->vit, S->vnew, S->gbuf, S->gflags,
+                       S->sc);  // v^{n+1,p+1}
     if (prof) HIPCHK(hipEventRecord(S->ev[3], s));
     {
       const FinishJob jobs[2] = {{P_JS, (int)scatter_blocks(S->np), 1, S_JS},
@@ -682,6 +687,6 @@ ecpic_status ecpic_get_profile(ecpic_sim* S, ecpic_profile* out) {
 
 const char* ecpic_last_error(void) { return g_err.c_str(); }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.2"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.3"; }
 
 }  // extern "C"

@@ -65,9 +65,10 @@ void launch_extrapolate(hipStream_t s, int64_t np, const double* v, const double
                         double* vit);
 void launch_scatter(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
                     const double* vit, double* J, Scratch sc);
+// flags: one int per 256-particle block, zero on entry and on exit
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const double* x,
                         const double* v, const double* vit, double* vnew, const double* gbuf,
-                        Scratch sc);
+                        int* flags, Scratch sc);
 void launch_sweep(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
                   const double* vit, const double* vnew, const double* gbuf, const double* Uhalf,
                   Scratch sc);

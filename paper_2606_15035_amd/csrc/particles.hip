@@ -40,6 +40,33 @@ struct AosFields {
   __device__ __forceinline__ double A1(int64_t node, int l) const { return g[node * kGbufStride + 6 + l]; }
 };
 
+// Accessors of the push path.  A stencil node is addressed by its unwrapped
+// integer coordinates in the particle's frame; row() folds (ix, iy), node()
+// adds iz and returns the node's kGbufStride doubles
+// [grad_h phi (3) | A^n (3) | A^{n+1} (3) | pad].
+struct GlobalGather {  // the interleaved gather buffer in global memory
+  const double* __restrict__ g;
+  int mask0, mask1, mask2, shx, shy;
+  __device__ __forceinline__ int row(int ix, int iy) const {
+    return ((ix & mask0) << shx) | ((iy & mask1) << shy);
+  }
+  __device__ __forceinline__ const double* node(int row, int iz) const {
+    return g + (int64_t)(row | (iz & mask2)) * kGbufStride;
+  }
+};
+
+typedef __attribute__((address_space(3))) const double lds_cdouble;
+
+struct TileGather {  // a block's LDS copy of the nodes its orbits touch
+  lds_cdouble* t;
+  int ox, oy, oz;    // particle frame -> tile coordinates
+  int dy, dz;        // tile extents along y and z
+  __device__ __forceinline__ int row(int ix, int iy) const { return ((ix + ox) * dy + (iy + oy)) * dz + oz; }
+  __device__ __forceinline__ lds_cdouble* node(int row, int iz) const {
+    return t + (row + iz) * kGbufStride;
+  }
+};
+
 struct SoaFields {
   const double* __restrict__ gphi;
   const double* __restrict__ a0;
@@ -222,9 +249,11 @@ __device__ __forceinline__ void gather_piece(const Grid& G, const double* x0, co
 // The push needs grad phi-bar and (D A)^T vbar only.  With b_g(s) = vbar . A_g(s),
 //   ((D A)^T vbar)_j = sum_g int b_g(s) d_j S_g(x(s)) ds,
 // so each node first contracts its A^n, A^{n+1} with vbar and the quadrature
-// then carries one scalar per node instead of the 3x3 matrix D.
-// Per piece only the quadrature positions and the z weights are kept; the x
-// and y weights of a stencil node are re-evaluated where they are used.
+// then carries one scalar per node instead of the 3x3 matrix D.  The tensor
+// product S_g = X_a Y_b Z_c is used once more: along each z column of the
+// stencil the quadrature-point sums B_q = sum_c b_c(s_q) Z_c(q) and
+// B'_q = sum_c b_c(s_q) Z'_c(q) are formed first, and the x and y factors
+// multiply those column sums, not every node.
 template <int R, class Acc>
 __device__ __forceinline__ void push_piece(const Grid& G, const double* x0, const double* d,
                                            double s0, double s1, const double* vb,
@@ -250,44 +279,87 @@ __device__ __forceinline__ void push_piece(const Grid& G, const double* x0, cons
   const int fz = to_int_clamped(base[2]) + Spline<R>::first_off;
 #pragma unroll
   for (int a = 0; a < W; ++a) {
-    double X[NQ], dX[NQ];
+    double Xw[NQ], dXw[NQ];  // quadrature weight x X_a, x dX_a/dx
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      Spline<R>::wk(a, tx[q], X[q], dX[q]);
-      dX[q] *= G.invH[0];
+      double Xq, dXq;
+      Spline<R>::wk(a, tx[q], Xq, dXq);
+      Xw[q] = wq[q] * Xq;
+      dXw[q] = wq[q] * (dXq * G.invH[0]);
     }
 #pragma unroll
     for (int b = 0; b < W; ++b) {
-      double xy[NQ], xyw[NQ], dxy[NQ], xdy[NQ];
+      double xyw[NQ], dxyw[NQ], xdyw[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         double Yq, dYq;
         Spline<R>::wk(b, ty[q], Yq, dYq);
-        xy[q] = X[q] * Yq;
-        xyw[q] = xy[q] * wq[q];
-        dxy[q] = dX[q] * Yq;
-        xdy[q] = X[q] * (dYq * G.invH[1]);
+        xyw[q] = Xw[q] * Yq;
+        dxyw[q] = dXw[q] * Yq;
+        xdyw[q] = Xw[q] * (dYq * G.invH[1]);
       }
-      const int row = (((fx + a) & G.mask[0]) << G.shx) | (((fy + b) & G.mask[1]) << G.shy);
+      const int row = acc.row(fx + a, fy + b);
+      double B[NQ], dB[NQ];
 #pragma unroll
       for (int c = 0; c < W; ++c) {
-        const int g = row | ((fz + c) & G.mask[2]);
+        const auto p = acc.node(row, fz + c);
         double f[9];
-        acc.load9(g, f);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f[k] = p[k];
         const double a0 = vb[0] * f[3] + vb[1] * f[4] + vb[2] * f[5];  // vbar . A^n_g
         const double da = vb[0] * f[6] + vb[1] * f[7] + vb[2] * f[8] - a0;
         double I = 0.0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           I += xyw[q] * Z[q][c];
-          const double bw = wq[q] * (a0 + sq[q] * da);  // wt_q vbar . A_g(s_q)
-          dtv[0] += bw * (dxy[q] * Z[q][c]);
-          dtv[1] += bw * (xdy[q] * Z[q][c]);
-          dtv[2] += bw * (xy[q] * dZ[q][c]);
+          const double bq = a0 + sq[q] * da;  // vbar . A_g(s_q)
+          B[q] = c == 0 ? bq * Z[q][c] : B[q] + bq * Z[q][c];
+          dB[q] = c == 0 ? bq * dZ[q][c] : dB[q] + bq * dZ[q][c];
         }
         gp[0] += f[0] * I;
         gp[1] += f[1] * I;
         gp[2] += f[2] * I;
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        dtv[0] += dxyw[q] * B[q];
+        dtv[1] += xdyw[q] * B[q];
+        dtv[2] += xyw[q] * dB[q];
+      }
+    }
+  }
+}
+
+// point interpolant of A^n (which = 0) or A^{n+1} (which = 1) at x, whose
+// stencil nodes are moved into the particle frame by +shift[a] (a multiple
+// of n[a]; zero unless x is a wrapped end point)
+template <int R, class Acc>
+__device__ __forceinline__ void point_A_acc(const Grid& G, const double* x, const int* shift,
+                                            const Acc& acc, int which, double* out) {
+  constexpr int W = R + 1;
+  double w[3][W];
+  int f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double u = x[a] * G.invH[a];
+    const double base = floor(u + Spline<R>::base_off);
+    Spline<R>::w(u - base, w[a]);
+    f[a] = to_int_clamped(base) + Spline<R>::first_off + shift[a];
+  }
+  out[0] = out[1] = out[2] = 0.0;
+  const int off = which ? 6 : 3;
+#pragma unroll
+  for (int a = 0; a < W; ++a) {
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      const int row = acc.row(f[0] + a, f[1] + b);
+      const double wxy = w[0][a] * w[1][b];
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        const auto p = acc.node(row, f[2] + c);
+        const double wt = wxy * w[2][c];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) out[l] += p[off + l] * wt;
       }
     }
   }
@@ -441,7 +513,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* 
     tlo[a] = block_min_int(rmin[a]);
     dim[a] = -block_min_int(-rmax[a]) - tlo[a] + 1;
   }
-  const bool use_tile = dim[0] > 0 && (int64_t)dim[0] * dim[1] * dim[2] <= kTileNodes;  // block-uniform
+  // block-uniform; each extent is bounded first so that the product cannot overflow
+  const bool use_tile = dim[0] > 0 && dim[0] <= kTileNodes && dim[1] <= kTileNodes &&
+                        dim[2] <= kTileNodes && (int64_t)dim[0] * dim[1] * dim[2] <= kTileNodes;
   const int nt = use_tile ? dim[0] * dim[1] * dim[2] : 0;
   for (int t = threadIdx.x; t < 3 * nt; t += kBlock) tile[t] = 0.0;
   __syncthreads();
@@ -517,17 +591,67 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* 
   block_partials<1>(js, sc.region(P_JS));
 }
 
-template <int R>
+// Gather + push of one particle through accessor acc: grad phi-bar and
+// (D A)^T vbar over the orbit pieces, then P^{n+1,p} and v^{n+1,p+1}.
+template <int R, class Acc>
+__device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& acc,
+                                                const double* x0, const double* d,
+                                                const double* vb, const double* va,
+                                                double* vn, double& npieces, double& bad) {
+  double gp[3] = {0.0, 0.0, 0.0};
+  double dtv[3] = {0.0, 0.0, 0.0};  // (D A)^T vbar
+  const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
+    push_piece<R>(P.G, x0, d, s0, s1, vb, acc, gp, dtv);
+    npieces += 1.0;
+  });
+  if (!ok) bad = 1.0;
+  // A_h^n(x^n) rebuilds P^n = m v^n + q A_h^n(x^n) (eq. discrete-canonical-relation);
+  // A_h^{n+1}(x^{n+1}) at the wrapped end point closes the velocity (eq. orbit-v-update).
+  double x1[3], A0s[3], A1e[3];
+  int zero[3] = {0, 0, 0}, sh1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    x1[a] = wrap_pos(x0[a] + d[a], P.G.L[a], P.G.invL[a]);
+    sh1[a] = (int)rint((x0[a] + d[a] - x1[a]) * P.G.invL[a]) * P.G.n[a];
+  }
+  point_A_acc<R>(P.G, x0, zero, acc, 0, A0s);
+  point_A_acc<R>(P.G, x1, sh1, acc, 1, A1e);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double Pn = P.m * va[j] + P.q * A0s[j];
+    const double P1 = Pn + P.dt * (-P.q * gp[j] + P.q * dtv[j]);  // eq. orbit-P-update
+    vn[j] = (P1 - P.q * A1e[j]) / P.m;                          // eq. orbit-v-update
+  }
+}
+
+// One block = 256 cell-sorted particles.  TILED = true: the block finds the
+// box of nodes its orbits touch (one node of margin per side against rounding
+// of piece midpoints), copies the gather fields of that box into LDS, and
+// every stencil read of the node loop then comes from LDS; a block whose box
+// does not fit the tile only raises its flag.  TILED = false: the blocks
+// whose flag is raised (all blocks when flags is null) read the gather
+// buffer in global memory.  Two kernels keep each one's register budget.
+constexpr int kGatherTileNodes = 512;
+
+template <int R, bool TILED>
 __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, const double* __restrict__ x,
                                                        const double* __restrict__ v,
                                                        const double* __restrict__ vit,
                                                        double* __restrict__ vnew, AosFields F,
-                                                       Scratch sc) {
+                                                       int* __restrict__ flags, Scratch sc) {
+  constexpr int W = R + 1;
+  if (!TILED && flags) {
+    if (flags[blockIdx.x] == 0) return;  // done by the tiled kernel
+    __syncthreads();
+    if (threadIdx.x == 0) flags[blockIdx.x] = 0;
+  }
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool active = i < P.np;
   double dvm = 0.0, vm = 0.0, bad = 0.0;
   double npieces[1] = {0.0};
-  if (i < P.np) {
-    double x0[3], va[3], vi[3], vb[3], d[3];
+  double x0[3] = {0.0, 0.0, 0.0}, va[3] = {0.0, 0.0, 0.0}, vi[3] = {0.0, 0.0, 0.0};
+  double vb[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
+  if (active) {
     load3(x, P.np, i, x0);
     load3(v, P.np, i, va);
     load3(vit, P.np, i, vi);
@@ -536,29 +660,75 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, const doub
       vb[a] = 0.5 * (vi[a] + va[a]);
       d[a] = P.dt * vb[a];
     }
-    double gp[3] = {0.0, 0.0, 0.0};
-    double dtv[3] = {0.0, 0.0, 0.0};  // (D A)^T vbar
-    const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
-      push_piece<R>(P.G, x0, d, s0, s1, vb, F, gp, dtv);
-      npieces[0] += 1.0;
-    });
-    if (!ok) bad = 1.0;
-    // A_h^n(x^n) rebuilds P^n = m v^n + q A_h^n(x^n) (eq. discrete-canonical-relation);
-    // A_h^{n+1}(x^{n+1}) at the wrapped end point closes the velocity (eq. orbit-v-update).
-    double x1[3], A0s[3], A1e[3];
+  }
+  double vn[3] = {0.0, 0.0, 0.0};
+  if constexpr (TILED) {
+    __shared__ double2 tile2[kGatherTileNodes * kGbufStride / 2];
+    __shared__ int s_ref[3];
+    int lo[3] = {0, 0, 0}, span[3] = {0, 0, 0};
+    if (active) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], P.G.L[a], P.G.invL[a]);
-    point_A<R>(P.G, x0, F, 0, A0s);
-    point_A<R>(P.G, x1, F, 1, A1e);
+      for (int a = 0; a < 3; ++a) {
+        const double u0 = x0[a] * P.G.invH[a], u1 = (x0[a] + d[a]) * P.G.invH[a];
+        lo[a] = to_int_clamped(floor(fmin(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off - 1;
+        span[a] = to_int_clamped(floor(fmax(u0, u1) + Spline<R>::base_off)) +
+                  Spline<R>::first_off + W - lo[a];
+      }
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) s_ref[a] = lo[a];
+    __syncthreads();
+    int shift[3], tlo[3], dim[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int raw = lo[a] - s_ref[a];
+      const int rel = min_image(raw, P.G.n[a]);
+      shift[a] = rel - raw;
+      tlo[a] = block_min_int(active ? rel : 0x3fffffff);
+      dim[a] = -block_min_int(active ? -(rel + span[a]) : 0x3fffffff) - tlo[a] + 1;
+    }
+    // block-uniform; each extent is bounded first so that the product cannot overflow
+    const bool fits = dim[0] <= kGatherTileNodes && dim[1] <= kGatherTileNodes &&
+                      dim[2] <= kGatherTileNodes;
+    const int64_t vol = fits ? (int64_t)dim[0] * dim[1] * dim[2] : kGatherTileNodes + 1;
+    if (vol > kGatherTileNodes) {  // leave the block to the global kernel
+      if (threadIdx.x == 0) flags[blockIdx.x] = 1;
+      return;
+    }
+    const int nt2 = (int)vol * (kGbufStride / 2);
+    const double2* g2 = reinterpret_cast<const double2*>(F.g);
+    for (int t = threadIdx.x; t < nt2; t += kBlock) {
+      const int nd = t / (kGbufStride / 2), part = t % (kGbufStride / 2);
+      const int cz = nd % dim[2], cy = (nd / dim[2]) % dim[1], cx = nd / (dim[2] * dim[1]);
+      const int64_t g = node_index(P.G, s_ref[0] + tlo[0] + cx, s_ref[1] + tlo[1] + cy,
+                                   s_ref[2] + tlo[2] + cz);
+      tile2[t] = g2[g * (kGbufStride / 2) + part];
+    }
+    __syncthreads();
+    if (active) {
+      TileGather acc;
+      acc.t = (lds_cdouble*)(reinterpret_cast<double*>(tile2));
+      acc.ox = shift[0] - s_ref[0] - tlo[0];
+      acc.oy = shift[1] - s_ref[1] - tlo[1];
+      acc.oz = shift[2] - s_ref[2] - tlo[2];
+      acc.dy = dim[1];
+      acc.dz = dim[2];
+      gather_push_one<R>(P, acc, x0, d, vb, va, vn, npieces[0], bad);
+    }
+  } else {
+    if (active) {
+      GlobalGather acc{F.g, P.G.mask[0], P.G.mask[1], P.G.mask[2], P.G.shx, P.G.shy};
+      gather_push_one<R>(P, acc, x0, d, vb, va, vn, npieces[0], bad);
+    }
+  }
+  if (active) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const double Pn = P.m * va[j] + P.q * A0s[j];
-      const double P1 = Pn + P.dt * (-P.q * gp[j] + P.q * dtv[j]);  // eq. orbit-P-update
-      const double vn = (P1 - P.q * A1e[j]) / P.m;               // eq. orbit-v-update
-      vnew[j * P.np + i] = vn;
-      dvm = fmax(dvm, fabs(vn - vi[j]));
-      vm = fmax(vm, fabs(vn));
-      if (!isfinite(vn)) bad = 2.0;  // max-reductions drop NaN: flag it explicitly
+      vnew[j * P.np + i] = vn[j];
+      dvm = fmax(dvm, fabs(vn[j] - vi[j]));
+      vm = fmax(vm, fabs(vn[j]));
+      if (!isfinite(vn[j])) bad = 2.0;  // max-reductions drop NaN: flag it explicitly
     }
   }
   block_max_to(dvm, sc.red + S_DVMAX);
@@ -775,13 +945,17 @@ void launch_scatter(hipStream_t s, int r, const StepParams& P, const double* x, 
 
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const double* x,
                         const double* v, const double* vit, double* vnew, const double* gbuf,
-                        Scratch sc) {
+                        int* flags, Scratch sc) {
   if (P.np <= 0) return;
   AosFields F{gbuf};
-  if (r == 1)
-    k_gather_push<1><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, vnew, F, sc);
-  else
-    k_gather_push<2><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, vnew, F, sc);
+  const unsigned nb = blocks_for(P.np);
+  if (r == 1) {
+    k_gather_push<1, true><<<nb, kBlock, 0, s>>>(P, x, v, vit, vnew, F, flags, sc);
+    k_gather_push<1, false><<<nb, kBlock, 0, s>>>(P, x, v, vit, vnew, F, flags, sc);
+  } else {
+    k_gather_push<2, true><<<nb, kBlock, 0, s>>>(P, x, v, vit, vnew, F, flags, sc);
+    k_gather_push<2, false><<<nb, kBlock, 0, s>>>(P, x, v, vit, vnew, F, flags, sc);
+  }
 }
 
 void launch_sweep(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,

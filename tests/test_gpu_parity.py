@@ -47,7 +47,7 @@ def gpu_cfg(wl, **kw):
 
 def orc_cfg(wl, **kw):
     args = wl.cfg_kwargs()
-    m = {"diagnostics": None}
+    m = {"diagnostics": None, "sort_interval": None}
     for k, v in kw.items():
         if k in m:
             continue
@@ -214,6 +214,27 @@ def test_two_stream_16x4x4_tolerance_run():
         assert abs(eg["E_total"] - E0) <= 1e-12 * E0
         assert eg["RA_max"] < 1e-15 and eg["gauge_max"] < 1e-13 and eg["gauss_max"] < 1e-10
     compare_states(wl, g, o, "c1 step 20", rtol=1e-10)
+
+
+def test_gather_tiled_and_global_blocks():
+    """Particles never re-sorted: the first half is given in cell order, so
+    its 256-particle blocks (about 3 cells each) gather from an LDS copy of
+    their node box; the second half is in random order, so those blocks span
+    the whole 4x4x16 mesh and read the fields from global memory.  Both
+    against the oracle."""
+    wl = W.random_plasma((4, 4, 16), (0.5, 0.5, 2.0), 40000, r=2, dt=0.2, vth=0.05,
+                         drift=(0.02, 0.01, -0.01), seed=21)
+    h = [wl.L[a] / wl.n[a] for a in range(3)]
+    half = wl.np // 2
+    c = [np.floor(wl.x[a, :half] / h[a]).astype(np.int64) for a in range(3)]
+    order = np.argsort((c[0] * wl.n[1] + c[1]) * wl.n[2] + c[2], kind="stable")
+    wl.x[:, :half] = wl.x[:, :half][:, order]
+    wl.v[:, :half] = wl.v[:, :half][:, order]
+    g, o = both(wl, tol=0.0, pmax=2, sort_interval=-1)
+    for step in range(2):
+        g.picard_step()
+        o.step()
+        compare_states(wl, g, o, f"tiled+global step {step}")
 
 
 def test_no_particles_vacuum_fields():
