@@ -67,7 +67,10 @@ ecpic_status check_config(const ecpic_config* c, int64_t np) {
     return fail(ECPIC_EINVAL, "quad_points: only the minimal exact rule (%d) is built", nq_min);
   if (c->split_orbit_at_knots != 1)
     return fail(ECPIC_EINVAL, "only split orbit integrals (split_orbit_at_knots = 1) are built");
-  if (c->precision != ECPIC_FP64) return fail(ECPIC_EINVAL, "precision: only FP64 is built");
+  if (c->precision != ECPIC_FP64 && c->precision != ECPIC_MIXED)
+    return fail(ECPIC_EINVAL, "precision must be ECPIC_FP64 or ECPIC_MIXED");
+  if (!(c->fixed_point_scale >= 0.0) || c->fixed_point_scale > 0x1p52)
+    return fail(ECPIC_EINVAL, "fixed_point_scale must be in [0, 2^52] (0 = 2^40)");
   return ECPIC_OK;
 }
 
@@ -118,10 +121,16 @@ struct ecpic_sim {
   hipStream_t stream;
   double q = -1.0, m = 1.0;
   bool initialized = false;
-  // particles (state), stored in cell-sorted order; id[i] = caller index
-  double *x, *v, *vprev, *vit, *vnew;
-  int* id;
-  SortBuffers sb;
+  // particles (state), stored in cell-sorted order; id[i] = caller index.
+  // One of the two stores is live (cfg.precision); [1] is the sort's alternate.
+  Fp64Store f64[2];
+  MixedStore mx[2];
+  double *vit, *vnew;  // Picard iterates (FP64 in both forms)
+  int *id, *id2;
+  SortScratch sb;
+  unsigned long long* Jfix = nullptr;  // mixed: fixed-point current quanta
+  double fix_scale = 0.0;             // quanta per unit of vbar Sbar
+  bool mixed() const { return cfg.precision == ECPIC_MIXED; }
   // mesh (state)
   double2* spec[2];  // spectral levels (9 fields each); spec[cur] is level n
   int cur = 0;
@@ -150,25 +159,34 @@ struct ecpic_sim {
 
 namespace {
 
+// fn(live store, sort alternate) for the store the configuration selects
+template <class Fn>
+auto on_store(ecpic_sim* S, Fn&& fn) {
+  if (S->mixed()) return fn(S->mx[0], S->mx[1]);
+  return fn(S->f64[0], S->f64[1]);
+}
+
 void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_bytes) {
   const int64_t np = S->np, nc = S->G.ncell;
   const size_t n3 = (size_t)3 * (np > 0 ? np : 1);
+  const size_t n1 = (size_t)(np > 0 ? np : 1);
   Carver st{state};
-  S->x = st.take<double>(n3);
-  S->v = st.take<double>(n3);
-  S->vprev = st.take<double>(n3);
+  for (int k = 0; k < 2; ++k) {
+    if (S->mixed()) {
+      S->mx[k].cell = st.take<int>(n1);
+      S->mx[k].off = st.take<float>(n3);
+      S->mx[k].v = st.take<float>(n3);
+      S->mx[k].vp = st.take<float>(n3);
+    } else {
+      S->f64[k].x = st.take<double>(n3);
+      S->f64[k].v = st.take<double>(n3);
+      S->f64[k].vp = st.take<double>(n3);
+    }
+  }
   S->vit = st.take<double>(n3);
   S->vnew = st.take<double>(n3);
-  const size_t n1 = (size_t)(np > 0 ? np : 1);
   S->id = st.take<int>(n1);
-  S->sb.x = &S->x;
-  S->sb.v = &S->v;
-  S->sb.vprev = &S->vprev;
-  S->sb.id = &S->id;
-  S->sb.x2 = st.take<double>(n3);
-  S->sb.v2 = st.take<double>(n3);
-  S->sb.vprev2 = st.take<double>(n3);
-  S->sb.id2 = st.take<int>(n1);
+  S->id2 = st.take<int>(n1);
   S->sb.key = st.take<int>(n1);
   S->sb.count = st.take<int>(8 * nc);
   S->sb.offset = st.take<int>(8 * nc + 1);
@@ -186,6 +204,7 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->Uhalf = w.take<double>(3 * nc);
   for (int a = 0; a < 3; ++a) S->tw[a] = w.take<double2>(S->G.n[a] / 2);
   S->gflags = w.take<int>(particle_blocks(np) > 0 ? particle_blocks(np) : 1);
+  if (S->mixed()) S->Jfix = w.take<unsigned long long>(3 * nc);
   S->sc.red = w.take<double>(S_NSLOTS);
   const int64_t maxblk = std::max<int64_t>(
       std::max<int64_t>(particle_blocks(np), scatter_blocks(np)), mesh_blocks(nc));
@@ -236,7 +255,7 @@ ecpic_status load_fields_from_realbuf(ecpic_sim* S) {
 }
 
 ecpic_status update_level_energies(ecpic_sim* S) {
-  launch_kinetic(S->stream, S->pp(), S->v, S->sc);
+  on_store(S, [&](auto& st, auto&) { launch_kinetic(S->stream, S->pp(), st, S->sc); });
   launch_field_energy(S->stream, S->fp(), S->spec[S->cur], S->sc);
   const FinishJob jobs[2] = {{P_K, (int)particle_blocks(S->np), 2, S_K},
                              {P_W, (int)mesh_blocks(S->G.ncell), 1, S_WCUR}};
@@ -285,6 +304,7 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
   S->G = make_grid(cfg);
   S->np = n_particles;
   S->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  S->fix_scale = cfg->fixed_point_scale > 0.0 ? cfg->fixed_point_scale : 0x1p40;
   carve(S, static_cast<char*>(state_dev), static_cast<char*>(workspace_dev), nullptr, nullptr);
   if (hipHostMalloc(reinterpret_cast<void**>(&S->host), sizeof(double) * S_NSLOTS,
                     hipHostMallocDefault) != hipSuccess) {
@@ -310,6 +330,8 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
   if (hipMemsetAsync(S->sc.red, 0, sizeof(double) * S_NSLOTS, S->stream) != hipSuccess ||
       hipMemsetAsync(S->gflags, 0, sizeof(int) * std::max<int64_t>(particle_blocks(n_particles), 1),
                      S->stream) != hipSuccess ||
+      (S->Jfix && hipMemsetAsync(S->Jfix, 0, sizeof(unsigned long long) * 3 * S->G.ncell,
+                                 S->stream) != hipSuccess) ||
       hipStreamSynchronize(S->stream) != hipSuccess) {
     (void)hipHostFree(S->host);
     delete S;
@@ -336,16 +358,23 @@ ecpic_status ecpic_init_particles(ecpic_sim* S, const double* x, const double* v
   const int64_t np = S->np, nc = S->G.ncell;
   S->q = q;
   S->m = m;
-  if (np > 0) {
-    HIPCHK(hipMemcpyAsync(S->x, x, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
-    HIPCHK(hipMemcpyAsync(S->v, v, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
-    HIPCHK(hipMemcpyAsync(S->vprev, v, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
+  if (np > 0) {  // through the iterate buffers into the store (x wrapped; v^{-1} = v^0)
+    HIPCHK(hipMemcpyAsync(S->vit, x, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipMemcpyAsync(S->vnew, v, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
+    on_store(S, [&](auto& st, auto&) {
+      launch_import(S->stream, S->pp(), st, 0, S->vit);
+      launch_import(S->stream, S->pp(), st, 1, S->vnew);
+      launch_import(S->stream, S->pp(), st, 2, S->vnew);
+    });
   }
-  launch_wrap_positions(S->stream, S->pp(), S->x);
   launch_iota(S->stream, np, S->id);
   // rho^0: point-shape deposit, transformed; then the Poisson solve
   launch_fill(S->stream, nc, S->realbuf, 0.0);
-  launch_deposit_rho(S->stream, S->cfg.spline_degree, S->pp(), S->x, S->realbuf);
+  on_store(S, [&](auto& st, auto&) {
+    launch_deposit_rho(S->stream, S->cfg.spline_degree, S->pp(), st,
+                       CurrentOut{S->realbuf, S->Jfix, S->fix_scale});
+  });
+  if (S->mixed()) launch_fixed_current(S->stream, nc, S->Jfix, S->realbuf, q / S->G.dV / S->fix_scale);
   RealIO in{};
   in.p[0] = S->realbuf;
   in.stride[0] = 1;
@@ -379,8 +408,13 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   const bool prof = S->profiling;
   const int sort_every = S->cfg.sort_interval <= 0 ? 1 : S->cfg.sort_interval;
   if (S->cfg.sort_interval >= 0 && (S->en.step % sort_every) == 0)
-    launch_sort(s, S->G, S->np, S->sb);  // cell order of x^n
-  launch_extrapolate(s, S->np, S->v, S->vprev, S->vit);  // v^{n+1,0} = 2 v^n - v^{n-1}
+    on_store(S, [&](auto& st, auto& alt) {  // cell order of x^n
+      launch_sort(s, S->G, S->np, st, alt, S->id, S->id2, S->sb);
+    });
+  // v^{n+1,0} = 2 v^n - v^{n-1}
+  on_store(S, [&](auto& st, auto&) { launch_extrapolate(s, S->np, st, S->vit); });
+  const CurrentOut cout{nullptr, S->Jfix, S->fix_scale};
+  const double fix_unit = S->q / S->G.dV / S->fix_scale;
   launch_reset_slots(s, S->sc.red, S_PIECES, 1);
   int p = 0, jcur = 1 - S->jlast;
   bool converged = false;
@@ -389,17 +423,23 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     double* J = S->Jb[jcur];
     double* Jprev = S->Jb[1 - jcur];
     launch_reset_slots(s, S->sc.red, S_DVMAX, 5);  // DVMAX, VMAX, DJMAX, JS, BAD
-    launch_fill(s, 3 * nc, J, 0.0);
+    if (!S->mixed()) launch_fill(s, 3 * nc, J, 0.0);
     if (prof) HIPCHK(hipEventRecord(S->ev[0], s));
-    launch_scatter(s, r, P, S->x, S->v, S->vit, J, S->sc);  // J^{n+1/2,p}
+    on_store(S, [&](auto& st, auto&) {  // J^{n+1/2,p}
+      CurrentOut o = cout;
+      o.J = J;
+      launch_scatter(s, r, P, st, S->vit, o, S->sc);
+    });
+    if (S->mixed()) launch_fixed_current(s, 3 * nc, S->Jfix, J, fix_unit);
     if (prof) HIPCHK(hipEventRecord(S->ev[1], s));
     RealIO jin = soa_io(J, nc, 3);
     fft3_forward(s, S->G, 3, S->Jh, &jin, p >= 1 ? Jprev : nullptr, twp(S), S->sc);
     launch_cn_update(s, F, cur, S->Jh, nxt, S->batch, S->sc);  // continuity + CN
     fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));         // grad phi^{n+1/2}, A^{n+1}
     if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
-    launch_gather_push(s, r, P, S->x, S->v, S->vit, S->vnew, S->gbuf, S->gflags,
-                       S->sc);  // v^{n+1,p+1}
+    on_store(S, [&](auto& st, auto&) {  // v^{n+1,p+1}
+      launch_gather_push(s, r, P, st, S->vit, S->vnew, S->gbuf, S->gflags, S->sc);
+    });
     if (prof) HIPCHK(hipEventRecord(S->ev[3], s));
     {
       const FinishJob jobs[2] = {{P_JS, (int)scatter_blocks(S->np), 1, S_JS},
@@ -448,11 +488,13 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     launch_half_U(s, S->G, cur, nxt, S->batch);
     RealIO uo = soa_io(S->Uhalf, nc, 3);
     fft3_inverse(s, S->G, 3, S->batch, &uo, twp(S));
-    launch_sweep(s, r, P, S->x, S->v, S->vit, S->vnew, S->gbuf, S->Uhalf, S->sc);
+    on_store(S, [&](auto& st, auto&) {
+      launch_sweep(s, r, P, st, S->vit, S->gbuf, S->Uhalf, S->sc);
+    });
   }
   if (prof) HIPCHK(hipEventRecord(S->ev[1], s));
   // accept: x^{n+1} = x^n + dt vbar^p, v^{n-1} <- v^n, v^n <- v^{n+1,p+1}; fields of pass p
-  launch_finalize(s, P, S->x, S->v, S->vprev, S->vit, S->vnew, S->sc);
+  on_store(S, [&](auto& st, auto&) { launch_finalize(s, P, st, S->vit, S->vnew, S->sc); });
   if (S->np <= 0) {
     launch_reset_slots(s, S->sc.red, S_K, 2);
     launch_reset_slots(s, S->sc.red, S_WORK, 2);
@@ -575,12 +617,12 @@ ecpic_status ecpic_get_state(ecpic_sim* S, double* x, double* v, double* vprev, 
   if (!S) return fail(ECPIC_EINVAL, "null simulation");
   const int64_t np = S->np, nc = S->G.ncell;
   hipStream_t s = S->stream;
-  if (np > 0) {  // stored (cell-sorted) order -> caller order, through the iterate buffers
-    const double* src[3] = {S->x, S->v, S->vprev};
+  if (np > 0) {  // store -> FP64 (stored order) -> caller order, through the iterate buffers
     double* dst[3] = {x, v, vprev};
     for (int k = 0; k < 3; ++k) {
       if (!dst[k]) continue;
-      launch_to_caller(s, np, S->id, src[k], S->vit);
+      on_store(S, [&](auto& st, auto&) { launch_export(s, S->pp(), st, k, S->vnew); });
+      launch_to_caller(s, np, S->id, S->vnew, S->vit);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(dst[k], S->vit, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -608,14 +650,13 @@ ecpic_status ecpic_set_state(ecpic_sim* S, const double* x, const double* v, con
   if (np > 0) {  // caller order -> stored order
     if (!S->initialized) launch_iota(s, np, S->id);
     const double* src[3] = {x, v, vprev};
-    double* dst[3] = {S->x, S->v, S->vprev};
     for (int k = 0; k < 3; ++k) {
       if (!src[k]) continue;
       HIPCHK(hipMemcpyAsync(S->vit, src[k], sizeof(double) * 3 * np, hipMemcpyHostToDevice, s));
-      launch_from_caller(s, np, S->id, S->vit, dst[k]);
+      launch_from_caller(s, np, S->id, S->vit, S->vnew);
+      on_store(S, [&](auto& st, auto&) { launch_import(s, S->pp(), st, k, S->vnew); });
       HIPCHK(hipGetLastError());
     }
-    if (x) launch_wrap_positions(s, S->pp(), S->x);
   }
   if (fields) {
     HIPCHK(hipMemcpyAsync(S->realbuf, fields, sizeof(double) * 9 * nc, hipMemcpyHostToDevice, s));

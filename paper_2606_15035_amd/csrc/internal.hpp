@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "orbit.hpp"
+#include "store.hpp"
 
 namespace ecpic {
 
@@ -61,22 +62,48 @@ int64_t particle_blocks(int64_t np);
 int64_t mesh_blocks(int64_t ncell);
 
 // ---- particle kernels (particles.hip) ----
-void launch_extrapolate(hipStream_t s, int64_t np, const double* v, const double* vprev,
-                        double* vit);
-void launch_scatter(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
-                    const double* vit, double* J, Scratch sc);
+// PS = Fp64Store or MixedStore (store.hpp); explicit instantiations of both
+// live in particles.hip and sort.hip.
+//
+// Orbit current output: FP64 state adds into J (3 x ncell doubles); mixed
+// state adds int64 fixed-point quanta into Jfix (3 x ncell), turned into J
+// by launch_fixed_current.
+struct CurrentOut {
+  double* J;
+  unsigned long long* Jfix;
+  double fix_scale;  // quanta per unit of vbar Sbar (2^40 by default)
+};
+template <class PS>
+void launch_extrapolate(hipStream_t s, int64_t np, const PS& st, double* vit);
+template <class PS>
+void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
+                    CurrentOut out, Scratch sc);
 // flags: one int per 256-particle block, zero on entry and on exit
-void launch_gather_push(hipStream_t s, int r, const StepParams& P, const double* x,
-                        const double* v, const double* vit, double* vnew, const double* gbuf,
-                        int* flags, Scratch sc);
-void launch_sweep(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
-                  const double* vit, const double* vnew, const double* gbuf, const double* Uhalf,
-                  Scratch sc);
-void launch_finalize(hipStream_t s, const StepParams& P, double* x, double* v, double* vprev,
-                     const double* vit, const double* vnew, Scratch sc);
-void launch_kinetic(hipStream_t s, const StepParams& P, const double* v, Scratch sc);
-void launch_wrap_positions(hipStream_t s, const StepParams& P, double* x);
-void launch_deposit_rho(hipStream_t s, int r, const StepParams& P, const double* x, double* rho);
+template <class PS>
+void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
+                        const double* vit, double* vnew, const double* gbuf, int* flags,
+                        Scratch sc);
+template <class PS>
+void launch_sweep(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
+                  const double* gbuf, const double* Uhalf, Scratch sc);
+template <class PS>
+void launch_finalize(hipStream_t s, const StepParams& P, const PS& st, const double* vit,
+                     const double* vnew, Scratch sc);
+template <class PS>
+void launch_kinetic(hipStream_t s, const StepParams& P, const PS& st, Scratch sc);
+// rho^0 of the point shapes: FP64 adds into out.J (ncell); mixed adds
+// fixed-point quanta into out.Jfix (then launch_fixed_current)
+template <class PS>
+void launch_deposit_rho(hipStream_t s, int r, const StepParams& P, const PS& st, CurrentOut out);
+// which: 0 = x (wrapped into [0, L) on import), 1 = v^n, 2 = v^{n-1};
+// src/dst are 3 x np doubles in stored order
+template <class PS>
+void launch_import(hipStream_t s, const StepParams& P, const PS& st, int which, const double* src);
+template <class PS>
+void launch_export(hipStream_t s, const StepParams& P, const PS& st, int which, double* dst);
+// J = unit * Jfix (as signed integers), then Jfix = 0
+void launch_fixed_current(hipStream_t s, int64_t n, unsigned long long* Jfix, double* J,
+                          double unit);
 void launch_orbit_gather_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
                              const double* d, const double* gphi, const double* U,
                              const double* A0, const double* A1, double* out);
@@ -84,16 +111,7 @@ void launch_orbit_deposit_soa(hipStream_t s, int r, const Grid& G, int64_t n, co
                               const double* d, const double* qv, double* J);
 
 // ---- particle sort (sort.hip) ----
-// Pointers to the live particle arrays (swapped with the alternates by the sort).
-struct SortBuffers {
-  double** x;
-  double** v;
-  double** vprev;
-  int** id;
-  double* x2;
-  double* v2;
-  double* vprev2;
-  int* id2;
+struct SortScratch {
   int* key;     // np
   int* count;   // 8 * ncell (cell x velocity octant)
   int* offset;  // 8 * ncell + 1
@@ -102,7 +120,11 @@ struct SortBuffers {
 };
 int64_t sort_scan_blocks(int64_t ncell);
 void launch_iota(hipStream_t s, int64_t n, int* p);
-void launch_sort(hipStream_t s, const Grid& G, int64_t np, SortBuffers& b);
+// Sorts the particles of cur (with their ids) into alt, then swaps cur/alt
+// and id/id2, so that cur and id hold the sorted particles.
+template <class PS>
+void launch_sort(hipStream_t s, const Grid& G, int64_t np, PS& cur, PS& alt, int*& id, int*& id2,
+                 const SortScratch& b);
 void launch_to_caller(hipStream_t s, int64_t np, const int* id, const double* src, double* dst);
 void launch_from_caller(hipStream_t s, int64_t np, const int* id, const double* src, double* dst);
 

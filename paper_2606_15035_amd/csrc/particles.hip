@@ -407,11 +407,12 @@ __device__ __forceinline__ void load3(const double* __restrict__ p, int64_t np, 
 
 // ---- kernels ---------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const double* __restrict__ v,
-                                                       const double* __restrict__ vprev,
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const T* __restrict__ v,
+                                                       const T* __restrict__ vprev,
                                                        double* __restrict__ vit) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n3) vit[i] = 2.0 * v[i] - vprev[i];  // v^{n+1,0} = 2 v^n - v^{n-1}
+  if (i < n3) vit[i] = 2.0 * (double)v[i] - (double)vprev[i];  // v^{n+1,0} = 2 v^n - v^{n-1}
 }
 
 // Orbit current of a chunk of kChunk particles per block.  Lanes take
@@ -454,14 +455,13 @@ __device__ __forceinline__ int64_t chunk_particle(int64_t base, int k) {
          (int64_t)(kBlock / kWave) * k;
 }
 
-template <int R>
-__device__ __forceinline__ void orbit_of(const StepParams& P, const double* __restrict__ x,
-                                         const double* __restrict__ v,
+template <class PS>
+__device__ __forceinline__ void orbit_of(const StepParams& P, const PS& st,
                                          const double* __restrict__ vit, int64_t i, double* x0,
                                          double* d, double* vb) {
   double va[3], vi[3];
-  load3(x, P.np, i, x0);
-  load3(v, P.np, i, va);
+  st.x_of(P.G, P.np, i, x0);
+  st.v_of(P.np, i, va);
   load3(vit, P.np, i, vi);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -470,20 +470,28 @@ __device__ __forceinline__ void orbit_of(const StepParams& P, const double* __re
   }
 }
 
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* __restrict__ x,
-                                                   const double* __restrict__ v,
+// Fixed-point quantum count of a current contribution (round to nearest,
+// ties away from zero), as the two's-complement bit pattern that 64-bit
+// integer atomics add.
+__device__ __forceinline__ unsigned long long quantize(double w, double scale) {
+  return (unsigned long long)(long long)round(w * scale);
+}
+
+template <int R, class PS>
+__global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
                                                    const double* __restrict__ vit,
-                                                   double* __restrict__ J, Scratch sc) {
+                                                   CurrentOut out, Scratch sc) {
   constexpr int W = R + 1;
-  __shared__ double tile[3 * kTileNodes];
+  constexpr bool FIX = PS::kMixed;  // int64 fixed-point deposit
+  __shared__ double tile[3 * kTileNodes];  // FIX: int64 quanta in the same bytes
   __shared__ int s_ref[3];
+  unsigned long long* tile_q = reinterpret_cast<unsigned long long*>(tile);
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   double js[1] = {0.0};
   double bad = 0.0;
   if (threadIdx.x == 0) {  // the chunk's first particle is the reference cell
     double x0[3];
-    load3(x, P.np, base, x0);
+    st.x_of(P.G, P.np, base, x0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       s_ref[a] = to_int_clamped(floor(x0[a] * P.G.invH[a] + Spline<R>::base_off));
@@ -495,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* 
     const int64_t i = chunk_particle(base, k);
     if (i >= P.np) continue;
     double x0[3], d[3], vb[3];
-    orbit_of<R>(P, x, v, vit, i, x0, d, vb);
+    orbit_of(P, st, vit, i, x0, d, vb);
     js[0] += fabs(P.q) * fmax(fabs(vb[0]), fmax(fabs(vb[1]), fabs(vb[2]))) / P.G.vol;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -517,19 +525,21 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* 
   const bool use_tile = dim[0] > 0 && dim[0] <= kTileNodes && dim[1] <= kTileNodes &&
                         dim[2] <= kTileNodes && (int64_t)dim[0] * dim[1] * dim[2] <= kTileNodes;
   const int nt = use_tile ? dim[0] * dim[1] * dim[2] : 0;
-  for (int t = threadIdx.x; t < 3 * nt; t += kBlock) tile[t] = 0.0;
+  for (int t = threadIdx.x; t < 3 * nt; t += kBlock) tile[t] = 0.0;  // also integer zero
   __syncthreads();
   // pass 2: accumulate
   const double qdv = P.q / P.G.dV;
+  const int64_t nc = P.G.ncell;
   for (int k = 0; k < kPerThread; ++k) {
     const int64_t i = chunk_particle(base, k);
     if (i >= P.np) continue;
     double x0[3], d[3], vb[3], c3[3];
-    orbit_of<R>(P, x, v, vit, i, x0, d, vb);
+    orbit_of(P, st, vit, i, x0, d, vb);
     int shift[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      c3[a] = qdv * vb[a];
+      // FP64: q vbar / dV; fixed point: vbar in units of the quantum
+      c3[a] = FIX ? vb[a] : qdv * vb[a];
       const double u0 = x0[a] * P.G.invH[a], u1 = (x0[a] + d[a]) * P.G.invH[a];
       const int lo = to_int_clamped(floor(fmin(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off - 1;
       const int raw = lo - s_ref[a];
@@ -553,12 +563,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* 
             for (int c = 0; c < W; ++c) {
               const int t = ((ox + a) * dim[1] + (oy + b)) * dim[2] + (oz + c);
               const double w = Iw[a][b][c];
-              atomicAdd(&tile[3 * t + 0], w * c3[0]);
-              atomicAdd(&tile[3 * t + 1], w * c3[1]);
-              atomicAdd(&tile[3 * t + 2], w * c3[2]);
+#pragma unroll
+              for (int l = 0; l < 3; ++l) {
+                if constexpr (FIX)
+                  atomicAdd(&tile_q[3 * t + l], quantize(w * c3[l], out.fix_scale));
+                else
+                  atomicAdd(&tile[3 * t + l], w * c3[l]);
+              }
             }
       } else {
-        const int64_t nc = P.G.ncell;
 #pragma unroll
         for (int a = 0; a < W; ++a)
 #pragma unroll
@@ -567,24 +580,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, const double* 
             for (int c = 0; c < W; ++c) {
               const int64_t g = node_index(P.G, f[0] + a, f[1] + b, f[2] + c);
               const double w = Iw[a][b][c];
-              unsafeAtomicAdd(J + g, w * c3[0]);
-              unsafeAtomicAdd(J + nc + g, w * c3[1]);
-              unsafeAtomicAdd(J + 2 * nc + g, w * c3[2]);
+#pragma unroll
+              for (int l = 0; l < 3; ++l) {
+                if constexpr (FIX)
+                  atomicAdd(out.Jfix + l * nc + g, quantize(w * c3[l], out.fix_scale));
+                else
+                  unsafeAtomicAdd(out.J + l * nc + g, w * c3[l]);
+              }
             }
       }
     });
     if (!ok) bad = 1.0;
   }
   __syncthreads();
-  const int64_t nc = P.G.ncell;
   for (int t = threadIdx.x; t < nt; t += kBlock) {
     const int cz = t % dim[2], cy = (t / dim[2]) % dim[1], cx = t / (dim[2] * dim[1]);
     const int64_t g = node_index(P.G, s_ref[0] + tlo[0] + cx, s_ref[1] + tlo[1] + cy,
                                  s_ref[2] + tlo[2] + cz);
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      const double val = tile[3 * t + l];
-      if (val != 0.0) unsafeAtomicAdd(J + l * nc + g, val);
+      if constexpr (FIX) {
+        const unsigned long long val = tile_q[3 * t + l];
+        if (val != 0ull) atomicAdd(out.Jfix + l * nc + g, val);
+      } else {
+        const double val = tile[3 * t + l];
+        if (val != 0.0) unsafeAtomicAdd(out.J + l * nc + g, val);
+      }
     }
   }
   block_max_to(bad, sc.red + S_BAD);
@@ -633,9 +654,8 @@ __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& 
 // buffer in global memory.  Two kernels keep each one's register budget.
 constexpr int kGatherTileNodes = 512;
 
-template <int R, bool TILED>
-__global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, const double* __restrict__ x,
-                                                       const double* __restrict__ v,
+template <int R, bool TILED, class PS>
+__global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
                                                        const double* __restrict__ vit,
                                                        double* __restrict__ vnew, AosFields F,
                                                        int* __restrict__ flags, Scratch sc) {
@@ -652,8 +672,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, const doub
   double x0[3] = {0.0, 0.0, 0.0}, va[3] = {0.0, 0.0, 0.0}, vi[3] = {0.0, 0.0, 0.0};
   double vb[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
   if (active) {
-    load3(x, P.np, i, x0);
-    load3(v, P.np, i, va);
+    st.x_of(P.G, P.np, i, x0);
+    st.v_of(P.np, i, va);
     load3(vit, P.np, i, vi);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -741,9 +761,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, const doub
 // Consistency sweep of the accepted iterate: Ubar, Ebar = -gphibar - Ubar,
 // sum_i q vbar . Ebar, R_A = A_h^{n+1}(x^{n+1}) - A_h^n(x^n) - dt (Ubar + D vbar)
 // (eq. RA-test) and the partition of unity sum_g Sbar_g.
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, const double* __restrict__ x,
-                                                 const double* __restrict__ v,
+template <int R, class PS>
+__global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, PS st,
                                                  const double* __restrict__ vit, AosFields F,
                                                  const double* __restrict__ Uh, Scratch sc) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -751,8 +770,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, const double* __
   double ramax = 0.0, poudev = 0.0;
   if (i < P.np) {
     double x0[3], va[3], vi[3], vb[3], d[3];
-    load3(x, P.np, i, x0);
-    load3(v, P.np, i, va);
+    st.x_of(P.G, P.np, i, x0);
+    st.v_of(P.np, i, va);
     load3(vit, P.np, i, vi);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -786,61 +805,104 @@ __global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, const double* __
   block_partials<2>(s2, sc.region(P_SWEEP));  // -> S_WORK, S_RA2
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, double* __restrict__ x,
-                                                    double* __restrict__ v,
-                                                    double* __restrict__ vprev,
+// Accept the step: x^{n+1} = x^n + dt vbar^p (wrapped), v^{n-1} <- v^n,
+// v^n <- v^{n+1,p+1}.  The kinetic energies are those of the stored values.
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, PS st,
                                                     const double* __restrict__ vit,
                                                     const double* __restrict__ vnew, Scratch sc) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double s[2] = {0.0, 0.0};  // K^{n+1}, K^{n+1} - K^n
   if (i < P.np) {
+    double x0[3], vo[3], vi[3], vn[3], x1[3];
+    st.x_of(P.G, P.np, i, x0);
+    st.v_of(P.np, i, vo);
+    load3(vit, P.np, i, vi);
+    load3(vnew, P.np, i, vn);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const int64_t k = a * P.np + i;
-      const double vo = v[k], vi = vit[k], vn = vnew[k];
-      x[k] = wrap_pos(x[k] + P.dt * 0.5 * (vi + vo), P.G.L[a], P.G.invL[a]);  // x^{n+1} = x^n + dt vbar^p
-      vprev[k] = vo;
-      v[k] = vn;
-      s[0] += 0.5 * P.m * vn * vn;
-      s[1] += 0.5 * P.m * (vn - vo) * (vn + vo);
+      x1[a] = wrap_pos(x0[a] + P.dt * 0.5 * (vi[a] + vo[a]), P.G.L[a], P.G.invL[a]);
+      const double w = PS::stored(vn[a]);
+      s[0] += 0.5 * P.m * w * w;
+      s[1] += 0.5 * P.m * (w - vo[a]) * (w + vo[a]);
     }
+    st.set_x(P.G, P.np, i, x1);
+    st.set_vp(P.np, i, vo);
+    st.set_v(P.np, i, vn);
   }
   block_partials<2>(s, sc.region(P_K));  // -> S_K, S_DK
 }
 
-__global__ __launch_bounds__(kBlock) void k_kinetic(StepParams P, const double* __restrict__ v,
-                                                   Scratch sc) {
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_kinetic(StepParams P, PS st, Scratch sc) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double s[2] = {0.0, 0.0};
   if (i < P.np) {
+    double va[3];
+    st.v_of(P.np, i, va);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double va = v[a * P.np + i];
-      s[0] += 0.5 * P.m * va * va;
-    }
+    for (int a = 0; a < 3; ++a) s[0] += 0.5 * P.m * va[a] * va[a];
   }
   block_partials<2>(s, sc.region(P_K));
 }
 
-__global__ __launch_bounds__(kBlock) void k_wrap(StepParams P, double* __restrict__ x) {
+// which = 0: x (wrapped into [0, L)), 1: v^n, 2: v^{n-1}
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_import(StepParams P, PS st, int which,
+                                                  const double* __restrict__ src) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < P.np)
+  if (i >= P.np) return;
+  double w[3];
+  load3(src, P.np, i, w);
+  if (which == 0) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) x[a * P.np + i] = wrap_pos(x[a * P.np + i], P.G.L[a], P.G.invL[a]);
+    for (int a = 0; a < 3; ++a) w[a] = wrap_pos(w[a], P.G.L[a], P.G.invL[a]);
+    st.set_x(P.G, P.np, i, w);
+  } else if (which == 1) {
+    st.set_v(P.np, i, w);
+  } else {
+    st.set_vp(P.np, i, w);
+  }
 }
 
-// rho_g += q S_g(x_i) / dV (eq. source-moments), point shape
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_deposit_rho(StepParams P, const double* __restrict__ x,
-                                                       double* __restrict__ rho) {
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_export(StepParams P, PS st, int which,
+                                                  double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= P.np) return;
+  double w[3];
+  if (which == 0)
+    st.x_of(P.G, P.np, i, w);
+  else if (which == 1)
+    st.v_of(P.np, i, w);
+  else
+    st.vp_of(P.np, i, w);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) dst[a * P.np + i] = w[a];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fixed_current(int64_t n,
+                                                         unsigned long long* __restrict__ Jfix,
+                                                         double* __restrict__ J, double unit) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  J[i] = unit * (double)(long long)Jfix[i];
+  Jfix[i] = 0ull;
+}
+
+// rho_g += q S_g(x_i) / dV (eq. source-moments), point shape.  Mixed state:
+// S_g as fixed-point quanta into out.Jfix (rho = q / dV / scale x quanta).
+template <int R, class PS>
+__global__ __launch_bounds__(kBlock) void k_deposit_rho(StepParams P, PS st, CurrentOut out) {
   constexpr int W = R + 1;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= P.np) return;
-  double w[3][W];
+  double w[3][W], x0[3];
   int f[3];
+  st.x_of(P.G, P.np, i, x0);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double u = x[a * P.np + i] * P.G.invH[a];
+    const double u = x0[a] * P.G.invH[a];
     const double base = floor(u + Spline<R>::base_off);
     Spline<R>::w(u - base, w[a]);
     f[a] = to_int_clamped(base) + Spline<R>::first_off;
@@ -854,7 +916,11 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rho(StepParams P, const doub
       for (int cc = 0; cc < W; ++cc) {
         const int64_t g = node_of(P.G, wrapi(f[0] + a, P.G.n[0]), wrapi(f[1] + b, P.G.n[1]),
                                   wrapi(f[2] + cc, P.G.n[2]));
-        unsafeAtomicAdd(rho + g, c * w[0][a] * w[1][b] * w[2][cc]);
+        const double s = w[0][a] * w[1][b] * w[2][cc];
+        if constexpr (PS::kMixed)
+          atomicAdd(out.Jfix + g, quantize(s, out.fix_scale));
+        else
+          unsafeAtomicAdd(out.J + g, c * s);
       }
 }
 
@@ -927,72 +993,109 @@ int64_t particle_blocks(int64_t np) { return (np + kBlock - 1) / kBlock; }
 
 // ---- launchers ---------------------------------------------------------------
 
-void launch_extrapolate(hipStream_t s, int64_t np, const double* v, const double* vprev,
-                        double* vit) {
+template <class PS>
+void launch_extrapolate(hipStream_t s, int64_t np, const PS& st, double* vit) {
   if (np <= 0) return;
-  k_extrapolate<<<blocks_for(3 * np), kBlock, 0, s>>>(3 * np, v, vprev, vit);
+  k_extrapolate<<<blocks_for(3 * np), kBlock, 0, s>>>(3 * np, st.v, st.vp, vit);
 }
 
-void launch_scatter(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
-                    const double* vit, double* J, Scratch sc) {
+template <class PS>
+void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
+                    CurrentOut out, Scratch sc) {
   if (P.np <= 0) return;
   const unsigned nblk = (unsigned)((P.np + kChunk - 1) / kChunk);
   if (r == 1)
-    k_scatter<1><<<nblk, kBlock, 0, s>>>(P, x, v, vit, J, sc);
+    k_scatter<1, PS><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
   else
-    k_scatter<2><<<nblk, kBlock, 0, s>>>(P, x, v, vit, J, sc);
+    k_scatter<2, PS><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
 }
 
-void launch_gather_push(hipStream_t s, int r, const StepParams& P, const double* x,
-                        const double* v, const double* vit, double* vnew, const double* gbuf,
-                        int* flags, Scratch sc) {
+template <class PS>
+void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
+                        const double* vit, double* vnew, const double* gbuf, int* flags,
+                        Scratch sc) {
   if (P.np <= 0) return;
   AosFields F{gbuf};
   const unsigned nb = blocks_for(P.np);
   if (r == 1) {
-    k_gather_push<1, true><<<nb, kBlock, 0, s>>>(P, x, v, vit, vnew, F, flags, sc);
-    k_gather_push<1, false><<<nb, kBlock, 0, s>>>(P, x, v, vit, vnew, F, flags, sc);
+    k_gather_push<1, true, PS><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+    k_gather_push<1, false, PS><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
   } else {
-    k_gather_push<2, true><<<nb, kBlock, 0, s>>>(P, x, v, vit, vnew, F, flags, sc);
-    k_gather_push<2, false><<<nb, kBlock, 0, s>>>(P, x, v, vit, vnew, F, flags, sc);
+    k_gather_push<2, true, PS><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+    k_gather_push<2, false, PS><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
   }
 }
 
-void launch_sweep(hipStream_t s, int r, const StepParams& P, const double* x, const double* v,
-                  const double* vit, const double* vnew, const double* gbuf, const double* Uhalf,
-                  Scratch sc) {
-  (void)vnew;
+template <class PS>
+void launch_sweep(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
+                  const double* gbuf, const double* Uhalf, Scratch sc) {
   if (P.np <= 0) return;
   AosFields F{gbuf};
   if (r == 1)
-    k_sweep<1><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, F, Uhalf, sc);
+    k_sweep<1, PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
   else
-    k_sweep<2><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vit, F, Uhalf, sc);
+    k_sweep<2, PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
 }
 
-void launch_finalize(hipStream_t s, const StepParams& P, double* x, double* v, double* vprev,
-                     const double* vit, const double* vnew, Scratch sc) {
+template <class PS>
+void launch_finalize(hipStream_t s, const StepParams& P, const PS& st, const double* vit,
+                     const double* vnew, Scratch sc) {
   if (P.np <= 0) return;
-  k_finalize<<<blocks_for(P.np), kBlock, 0, s>>>(P, x, v, vprev, vit, vnew, sc);
+  k_finalize<PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, vnew, sc);
 }
 
-void launch_kinetic(hipStream_t s, const StepParams& P, const double* v, Scratch sc) {
+template <class PS>
+void launch_kinetic(hipStream_t s, const StepParams& P, const PS& st, Scratch sc) {
   if (P.np <= 0) return;
-  k_kinetic<<<blocks_for(P.np), kBlock, 0, s>>>(P, v, sc);
+  k_kinetic<PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, sc);
 }
 
-void launch_wrap_positions(hipStream_t s, const StepParams& P, double* x) {
-  if (P.np <= 0) return;
-  k_wrap<<<blocks_for(P.np), kBlock, 0, s>>>(P, x);
-}
-
-void launch_deposit_rho(hipStream_t s, int r, const StepParams& P, const double* x, double* rho) {
+template <class PS>
+void launch_deposit_rho(hipStream_t s, int r, const StepParams& P, const PS& st, CurrentOut out) {
   if (P.np <= 0) return;
   if (r == 1)
-    k_deposit_rho<1><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, rho);
+    k_deposit_rho<1, PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, out);
   else
-    k_deposit_rho<2><<<blocks_for(P.np), kBlock, 0, s>>>(P, x, rho);
+    k_deposit_rho<2, PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, out);
 }
+
+template <class PS>
+void launch_import(hipStream_t s, const StepParams& P, const PS& st, int which, const double* src) {
+  if (P.np <= 0) return;
+  k_import<PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, which, src);
+}
+
+template <class PS>
+void launch_export(hipStream_t s, const StepParams& P, const PS& st, int which, double* dst) {
+  if (P.np <= 0) return;
+  k_export<PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, which, dst);
+}
+
+void launch_fixed_current(hipStream_t s, int64_t n, unsigned long long* Jfix, double* J,
+                          double unit) {
+  if (n <= 0) return;
+  k_fixed_current<<<blocks_for(n), kBlock, 0, s>>>(n, Jfix, J, unit);
+}
+
+#define ECPIC_INSTANTIATE_STORE(PS)                                                              \
+  template void launch_extrapolate<PS>(hipStream_t, int64_t, const PS&, double*);                \
+  template void launch_scatter<PS>(hipStream_t, int, const StepParams&, const PS&, const double*, \
+                                   CurrentOut, Scratch);                                         \
+  template void launch_gather_push<PS>(hipStream_t, int, const StepParams&, const PS&,           \
+                                       const double*, double*, const double*, int*, Scratch);    \
+  template void launch_sweep<PS>(hipStream_t, int, const StepParams&, const PS&, const double*,  \
+                                 const double*, const double*, Scratch);                         \
+  template void launch_finalize<PS>(hipStream_t, const StepParams&, const PS&, const double*,     \
+                                    const double*, Scratch);                                     \
+  template void launch_kinetic<PS>(hipStream_t, const StepParams&, const PS&, Scratch);          \
+  template void launch_deposit_rho<PS>(hipStream_t, int, const StepParams&, const PS&,          \
+                                       CurrentOut);                                              \
+  template void launch_import<PS>(hipStream_t, const StepParams&, const PS&, int, const double*); \
+  template void launch_export<PS>(hipStream_t, const StepParams&, const PS&, int, double*);
+
+ECPIC_INSTANTIATE_STORE(Fp64Store)
+ECPIC_INSTANTIATE_STORE(MixedStore)
+#undef ECPIC_INSTANTIATE_STORE
 
 void launch_orbit_gather_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
                              const double* d, const double* gphi, const double* U,

@@ -57,9 +57,8 @@ __global__ __launch_bounds__(kBlock) void k_iota(int64_t n, int* p) {
 // key = 8 * cell + octant of v^n: inside a cell, particles moving the same
 // way stay together, which keeps the orbit-piece structure of a wavefront's
 // lanes alike (less divergence in the gather).
-__global__ __launch_bounds__(kBlock) void k_cell_keys(Grid G, int64_t np,
-                                                     const double* __restrict__ x,
-                                                     const double* __restrict__ v,
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_cell_keys(Grid G, int64_t np, PS st,
                                                      int* __restrict__ key,
                                                      int* __restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -67,12 +66,12 @@ __global__ __launch_bounds__(kBlock) void k_cell_keys(Grid G, int64_t np,
   int k = 0;
   if (active) {
     int c[3];
+    double va[3];
+    st.cell_of(G, np, i, c);
+    st.v_of(np, i, va);
     int oct = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      c[a] = to_int_clamped(floor(x[a * np + i] * G.invH[a]));
-      oct |= (v[a * np + i] > 0.0 ? 1 : 0) << a;
-    }
+    for (int a = 0; a < 3; ++a) oct |= (va[a] > 0.0 ? 1 : 0) << a;
     k = (node_index(G, c[0], c[1], c[2]) << 3) | oct;
     key[i] = k;
   }
@@ -159,22 +158,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int64_t n, const int* __r
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_permute(
-    int64_t np, const int* __restrict__ key, int* __restrict__ cursor,
-    const double* __restrict__ x, const double* __restrict__ v, const double* __restrict__ vp,
-    const int* __restrict__ id, double* __restrict__ x2, double* __restrict__ v2,
-    double* __restrict__ vp2, int* __restrict__ id2) {
+template <class PS>
+__global__ __launch_bounds__(kBlock) void k_permute(int64_t np, const int* __restrict__ key,
+                                                   int* __restrict__ cursor, PS src, PS dst,
+                                                   const int* __restrict__ id,
+                                                   int* __restrict__ id2) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < np;
   const int k = active ? key[i] : 0;
   const int64_t j = wave_aggregated_inc(cursor, k, active);
   if (!active) return;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    x2[a * np + j] = x[a * np + i];
-    v2[a * np + j] = v[a * np + i];
-    vp2[a * np + j] = vp[a * np + i];
-  }
+  src.move_to(dst, np, i, j);
   id2[j] = id[i];
 }
 
@@ -208,24 +202,31 @@ void launch_iota(hipStream_t s, int64_t n, int* p) {
   if (n > 0) k_iota<<<blocks_for(n), kBlock, 0, s>>>(n, p);
 }
 
-void launch_sort(hipStream_t s, const Grid& G, int64_t np, SortBuffers& b) {
+template <class PS>
+void launch_sort(hipStream_t s, const Grid& G, int64_t np, PS& cur, PS& alt, int*& id, int*& id2,
+                 const SortScratch& b) {
   if (np <= 0) return;
   const int64_t nkeys = 8 * G.ncell;
   k_fill_int<<<blocks_for(nkeys), kBlock, 0, s>>>(nkeys, b.count, 0);
-  k_cell_keys<<<blocks_for(np), kBlock, 0, s>>>(G, np, *b.x, *b.v, b.key, b.count);
+  k_cell_keys<PS><<<blocks_for(np), kBlock, 0, s>>>(G, np, cur, b.key, b.count);
   const int64_t nb = (nkeys + kScanTile - 1) / kScanTile;
   k_scan_totals<<<(unsigned)nb, kBlock, 0, s>>>(nkeys, b.count, b.scan_totals);
   k_scan_block_totals<<<1, kBlock, 0, s>>>(nb, b.scan_totals, b.offset, nkeys);
   k_scan_apply<<<(unsigned)nb, kBlock, 0, s>>>(nkeys, b.count, b.scan_totals, b.offset, b.cursor);
-  k_permute<<<blocks_for(np), kBlock, 0, s>>>(np, b.key, b.cursor, *b.x, *b.v, *b.vprev, *b.id,
-                                              b.x2, b.v2, b.vprev2, b.id2);
+  k_permute<PS><<<blocks_for(np), kBlock, 0, s>>>(np, b.key, b.cursor, cur, alt, id, id2);
   // the sorted copies become the particle arrays
-  double* t;
-  t = *b.x; *b.x = b.x2; b.x2 = t;
-  t = *b.v; *b.v = b.v2; b.v2 = t;
-  t = *b.vprev; *b.vprev = b.vprev2; b.vprev2 = t;
-  int* ti = *b.id; *b.id = b.id2; b.id2 = ti;
+  const PS t = cur;
+  cur = alt;
+  alt = t;
+  int* ti = id;
+  id = id2;
+  id2 = ti;
 }
+
+template void launch_sort<Fp64Store>(hipStream_t, const Grid&, int64_t, Fp64Store&, Fp64Store&,
+                                     int*&, int*&, const SortScratch&);
+template void launch_sort<MixedStore>(hipStream_t, const Grid&, int64_t, MixedStore&,
+                                      MixedStore&, int*&, int*&, const SortScratch&);
 
 void launch_to_caller(hipStream_t s, int64_t np, const int* id, const double* src, double* dst) {
   if (np > 0) k_to_caller<<<blocks_for(np), kBlock, 0, s>>>(np, id, src, dst);

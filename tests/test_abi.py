@@ -63,12 +63,27 @@ def test_state_bytes_scale_with_particles(lib):
     dict(dt=0.0),
     dict(pmax=-1),
     dict(tol=-1.0),
+    dict(precision=2),                    # no such precision
 ])
 def test_invalid_configurations_are_rejected(lib, bad):
     with pytest.raises(E.EcpicError) as ei:
         E.state_bytes(good_cfg(**bad), 10)
     assert ei.value.status == E.EINVAL
     assert len(lib.ecpic_last_error()) > 0
+
+
+def test_mixed_precision_state_is_smaller(lib):
+    s64, _ = E.state_bytes(good_cfg(), 100000)
+    smx, _ = E.state_bytes(good_cfg(precision=E.MIXED), 100000)
+    # per particle: x, v, v^{n-1} and their sort copies shrink from 144 B
+    # (FP64) to 80 B (int32 cell, FP32 offset, FP32 v, FP32 v^{n-1})
+    assert 60 <= (s64 - smx) / 100000 <= 68
+
+
+@pytest.mark.parametrize("scale", [-1.0, 2.0 ** 53])
+def test_fixed_point_scale_range(lib, scale):
+    with pytest.raises(E.EcpicError):
+        E.state_bytes(good_cfg(precision=E.MIXED, fixed_point_scale=scale), 10)
 
 
 def test_maxwell_scaling_accepted_when_consistent(lib):
