@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -63,6 +65,38 @@ def gather_bytes_per_push() -> float:
 MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.3", "workload": "c2", "bytes": 209.7e6}
 
 
+def time_workload(E, wl, precision, steps, warmup):
+    """Particle-pushes/s of `steps` timed steps of workload wl after `warmup`
+    steps, in the given precision; returns (value, ms/step, mean passes,
+    max |R_total|/E per step, |E - E0|/E0, profile)."""
+    import torch
+    cfg = E.make_config(wl.n, wl.L, wl.dt, r=wl.r, kappa=wl.kappa, sigma1=wl.sigma1,
+                        sigma2=wl.sigma2, tol=wl.tol, pmax=wl.pmax, precision=precision)
+    sim = E.Sim(cfg, wl.np)
+    sim.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
+    E0 = sim.energy_diagnostics()["E_total"]
+    for _ in range(warmup):
+        sim.picard_step()
+    torch.cuda.synchronize()
+    sim.set_profiling(True)
+    iters, rel = [], 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        iters.append(sim.picard_step()["iters"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = sim.get_profile()
+    sim.set_profiling(False)
+    e = sim.energy_diagnostics()  # the last step's R_total and the level's energy
+    rel = abs(e["R_total"]) / e["E_total"]
+    drift = abs(e["E_total"] - E0) / E0
+    out = (wl.np * sum(iters) / wall, wall / steps * 1e3, float(np.mean(iters)), rel, drift, prof)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_cpu_baseline(wl, seconds_budget=30.0):
     """The oracle (serial C, one core) on the first step of the same workload."""
     import oracle as O
@@ -84,6 +118,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision lines (32^3 and 64^3 workloads)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -91,7 +127,6 @@ def main():
               "the multi-GPU particle decomposition is a design note, not built.", flush=True)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2606_15035_amd import ecpic as E
@@ -172,6 +207,28 @@ def main():
                                for k in ("scatter", "field_solve", "gather_push")},
         "roofline": roofline,
     }
+    if not args.no_mixed:
+        # the same workload in the mixed form, and the 64^3 / 33.5M-particle
+        # workload (mixed by definition), a few steps each
+        del sim
+        torch.cuda.empty_cache()
+        mixed = {}
+        for name, steps in ((args.workload, max(5, args.steps // 2)), ("c4", 3)):
+            wlm = W.two_stream(name)
+            print(f"mixed precision: {name} ...", flush=True)
+            v_, ms_, it_, rel_, drift_, pr_ = time_workload(E, wlm, E.MIXED, steps, 1)
+            g_ = pr_["gather_push"]
+            mixed[name] = {"value": v_, "unit": "particle-pushes/s", "ms_per_step": ms_,
+                           "steps": steps, "warmup": 1, "particles": wlm.np,
+                           "mesh": list(wlm.n), "picard_passes_mean": it_,
+                           "dE_over_E_step": rel_, "dE_over_E_run": drift_,
+                           "phases_ms_per_pass": {k: pr_[k]["ms"] / max(pr_[k]["launches"], 1)
+                                                  for k in ("scatter", "field_solve",
+                                                            "gather_push")},
+                           "pieces_per_orbit": pr_["pieces"] / max(wlm.np * g_["launches"], 1),
+                           "workload": wlm.description}
+        out["mixed"] = mixed
+        out["mixed_vs_fp64"] = mixed[args.workload]["value"] / value
     if not args.no_cpu_baseline:
         print("cpu baseline: timing the oracle on the first step ...", flush=True)
         out["cpu_baseline"] = run_cpu_baseline(W.two_stream(args.workload))
