@@ -93,6 +93,10 @@ def lib():
         L.orc_ktilde.argtypes = [P, D]
         L.orc_gauss_rule.argtypes = [P, D, D]
         L.orc_gauss_legendre.argtypes = [C.c_int, D, D]
+        L.orc_adjoint_step.argtypes = [P, D, D, D, D, D, D, D, D, D, D, C.c_double, C.c_int,
+                                       C.POINTER(C.c_int)]
+        L.orc_rebuild_P.argtypes = [P]
+        L.orc_field_energy_grad.argtypes = [P, D]
         _lib = L
     return _lib
 
@@ -193,6 +197,37 @@ class OracleSim:
     def field_solve(self, J):
         J = _f64(J).reshape((3,) + self.n)
         lib().orc_field_solve(self._h, _p(J))
+
+    # -- adjoint ----------------------------------------------------------
+    def rebuild_P(self):
+        """P^n = m v^n + q A_h^n(x^n) from the present state."""
+        lib().orc_rebuild_P(self._h)
+
+    def field_energy_grad(self):
+        """dW/dF for the present real-space fields, shape (9,) + n."""
+        g = np.zeros((9,) + self.n)
+        lib().orc_field_energy_grad(self._h, _p(g))
+        return g
+
+    def adjoint_step(self, x, v, w, F, lx1=None, lv1=None, lF1=None, tol=1e-14, maxit=200):
+        """Adjoint of the converged step from (x, v, F) whose solution is w.
+        Returns (lx0, lv0, lF0, iterations)."""
+        x, v, w = (_f64(a).reshape(3, self.np) for a in (x, v, w))
+        F = _f64(F).reshape((9,) + self.n)
+        lx1, lv1 = (None if a is None else _f64(a).reshape(3, self.np) for a in (lx1, lv1))
+        lF1 = None if lF1 is None else _f64(lF1).reshape((9,) + self.n)
+        lx0 = np.zeros((3, self.np))
+        lv0 = np.zeros((3, self.np))
+        lF0 = np.zeros((9,) + self.n)
+        it = C.c_int(0)
+        rc = lib().orc_adjoint_step(self._h, _p(x), _p(v), _p(w), _p(F), _p(lx1), _p(lv1),
+                                    _p(lF1), _p(lx0), _p(lv0), _p(lF0), float(tol), int(maxit),
+                                    C.byref(it))
+        if rc < 0:
+            raise RuntimeError("orc_adjoint_step: degree 2 with split orbits only")
+        if rc > 0:
+            raise RuntimeError("orc_adjoint_step: transposed iteration did not converge")
+        return lx0, lv0, lF0, it.value
 
     # -- kernel-level helpers (tests) -------------------------------------
     def field_energy_of(self, phi, A, U):

@@ -1215,3 +1215,504 @@ int orc_ktilde(const orc_sim* S, double* k) {
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* adjoint of one converged step (degree 2, split orbits)                    */
+/* ------------------------------------------------------------------------- */
+/*
+ * The converged step is the solution w = v^{n+1} of w = G(w; x, v, F) with
+ * (rebuilding P^n = m v + q A_h^n(x), eq. discrete-canonical-relation)
+ *
+ *   G = v + (q/m) [A0_h(x) - A1_h(x + d)] + (q dt/m) [-gphibar + (D A)^T vbar],
+ *   vbar = (w + v)/2, d = dt vbar,
+ *   gphibar = sum_g gphi_g Sbar_g,  ((D A)^T vbar)_j = sum_g int b_g(s) d_j S_g(x(s)) ds,
+ *   b_g(s) = vbar . ((1-s) A0_g + s A1_g),
+ *
+ * where gphi = grad_h (phi^n + phi^{n+1})/2, A0 = A^n, A1 = A^{n+1} come from
+ * the continuity + CN update driven by J = (q/dV) sum_i vbar_i Sbar_i
+ * (eqs. orbit-current, cn-continuity, cn-field-update, orbit-push).  The
+ * outputs are x' = x + d, v' = w and the level-(n+1) fields.
+ *
+ * Given the adjoints (lx1, lv1, lF1) of the outputs, the adjoint xi of w
+ * solves xi = b + (dG/dw)^T xi (the transposed Picard iteration), and
+ *   lv0 = 2 xi - lv1   (w and v enter every term through vbar alike, and v
+ *                       once more directly),
+ *   lx0 = lx1 + x-derivatives of J and G,  lF0 = fields' share.
+ * Complex spectra follow dL = Re sum conj(lambda) dz.  Only degree 2: with
+ * degree 1 the derivative of the piecewise-constant grad S jumps at knots.
+ */
+
+/* degree-2 weights, first and second derivatives (per unit of u) */
+static void spline2_all(double t, double w[3], double dw[3], double ddw[3]) {
+  w[0] = 0.5 * (0.5 - t) * (0.5 - t);
+  w[1] = 0.75 - t * t;
+  w[2] = 0.5 * (0.5 + t) * (0.5 + t);
+  dw[0] = -(0.5 - t);
+  dw[1] = -2.0 * t;
+  dw[2] = 0.5 + t;
+  ddw[0] = 1.0;
+  ddw[1] = -2.0;
+  ddw[2] = 1.0;
+}
+
+/* S, grad S and the Hessian of S for the 27 nodes first + (i, j, k), at
+   position xp written against the given base nodes */
+static void node_derivs(const grid* G, const double xp[3], const long base[3], double S[27],
+                        double dS[27][3], double ddS[27][3][3]) {
+  double w[3][3], dw[3][3], ddw[3][3];
+  for (int a = 0; a < 3; ++a) {
+    spline2_all(xp[a] / G->H[a] - (double)base[a], w[a], dw[a], ddw[a]);
+    for (int o = 0; o < 3; ++o) {
+      dw[a][o] /= G->H[a];
+      ddw[a][o] /= G->H[a] * G->H[a];
+    }
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) {
+        int id = pidx(3, i, j, k);
+        int o[3] = {i, j, k};
+        S[id] = w[0][i] * w[1][j] * w[2][k];
+        for (int p = 0; p < 3; ++p) {
+          double f = 1.0;
+          for (int a = 0; a < 3; ++a) f *= (a == p) ? dw[a][o[a]] : w[a][o[a]];
+          dS[id][p] = f;
+          for (int r2 = 0; r2 < 3; ++r2) {
+            double h = 1.0;
+            for (int a = 0; a < 3; ++a) {
+              if (a == p && a == r2)
+                h *= ddw[a][o[a]];
+              else if (a == p || a == r2)
+                h *= dw[a][o[a]];
+              else
+                h *= w[a][o[a]];
+            }
+            ddS[id][p][r2] = h;
+          }
+        }
+      }
+}
+
+/* Per-particle adjoint contributions.  eta = (q/m) xi (push terms, may be
+   NULL), mu = (q/dV) lambda_J (deposit terms, may be NULL).  Accumulates
+   lx, ld, lvb (3 each) and, for eta, the mesh adjoints of gphi, A0, A1. */
+static int particle_adjoint(const orc_sim* S, const double x0[3], const double vb[3],
+                            const double* eta, const double* mu, const double* gphi,
+                            const double* A0, const double* A1, double lx[3], double ld[3],
+                            double lvb[3], double* lgphi, double* lA0, double* lA1) {
+  const grid* G = &S->G;
+  int64_t nc = G->ncell;
+  double dt = S->c.dt;
+  double d[3];
+  for (int a = 0; a < 3; ++a) d[a] = dt * vb[a];
+  double sb[MAX_BREAKS];
+  int nb = orbit_breakpoints(G, 2, x0, d, sb);
+  if (nb < 0) return -1;
+  double Sv[27], dS[27][3], ddS[27][3][3];
+  for (int m = 0; m + 1 < nb; ++m) {
+    double s0 = sb[m], s1 = sb[m + 1];
+    if (!(s1 > s0)) continue;
+    double smid = 0.5 * (s0 + s1), h = s1 - s0;
+    long base[3], first[3];
+    for (int a = 0; a < 3; ++a) {
+      base[a] = spline_base(2, (x0[a] + smid * d[a]) / G->H[a]);
+      first[a] = spline_first(2, base[a]);
+    }
+    for (int iq = 0; iq < S->nq; ++iq) {
+      double s = s0 + 0.5 * h * (1.0 + S->gx[iq]);
+      double wt = 0.5 * h * S->gw[iq];
+      double xp[3];
+      for (int a = 0; a < 3; ++a) xp[a] = x0[a] + s * d[a];
+      node_derivs(G, xp, base, Sv, dS, ddS);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k) {
+            int id = pidx(3, i, j, k);
+            int64_t g = node_id(G, first[0] + i, first[1] + j, first[2] + k);
+            if (eta) {
+              double Ag[3], bg = 0.0, edS = 0.0;
+              for (int l = 0; l < 3; ++l) {
+                Ag[l] = (1.0 - s) * A0[l * nc + g] + s * A1[l * nc + g];
+                bg += vb[l] * Ag[l];
+                edS += eta[l] * dS[id][l];
+              }
+              /* -dt gphibar */
+              double eg = 0.0;
+              for (int l = 0; l < 3; ++l) eg += eta[l] * gphi[l * nc + g];
+              for (int kk = 0; kk < 3; ++kk) {
+                lx[kk] -= dt * wt * eg * dS[id][kk];
+                ld[kk] -= dt * wt * s * eg * dS[id][kk];
+              }
+              for (int l = 0; l < 3; ++l) lgphi[l * nc + g] -= dt * wt * eta[l] * Sv[id];
+              /* dt (D A)^T vbar */
+              for (int l = 0; l < 3; ++l) lvb[l] += dt * wt * Ag[l] * edS;
+              for (int kk = 0; kk < 3; ++kk) {
+                double eH = 0.0;
+                for (int jj = 0; jj < 3; ++jj) eH += eta[jj] * ddS[id][jj][kk];
+                lx[kk] += dt * wt * bg * eH;
+                ld[kk] += dt * wt * s * bg * eH;
+              }
+              for (int l = 0; l < 3; ++l) {
+                lA0[l * nc + g] += dt * wt * (1.0 - s) * vb[l] * edS;
+                lA1[l * nc + g] += dt * wt * s * vb[l] * edS;
+              }
+            }
+            if (mu) {
+              double vm = 0.0;
+              for (int l = 0; l < 3; ++l) {
+                lvb[l] += wt * mu[l * nc + g] * Sv[id];
+                vm += vb[l] * mu[l * nc + g];
+              }
+              for (int kk = 0; kk < 3; ++kk) {
+                lx[kk] += wt * vm * dS[id][kk];
+                ld[kk] += wt * s * vm * dS[id][kk];
+              }
+            }
+          }
+    }
+  }
+  if (eta) { /* point terms: + A0_h(x0) - A1_h(x0 + d) */
+    for (int e = 0; e < 2; ++e) {
+      double sgn = e == 0 ? 1.0 : -1.0;
+      const double* F = e == 0 ? A0 : A1;
+      double* lF = e == 0 ? lA0 : lA1;
+      double xp[3];
+      long base[3], first[3];
+      for (int a = 0; a < 3; ++a) {
+        xp[a] = wrap_pos(x0[a] + (e == 0 ? 0.0 : d[a]), G->L[a]);
+        base[a] = spline_base(2, xp[a] / G->H[a]);
+        first[a] = spline_first(2, base[a]);
+      }
+      node_derivs(G, xp, base, Sv, dS, ddS);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k) {
+            int id = pidx(3, i, j, k);
+            int64_t g = node_id(G, first[0] + i, first[1] + j, first[2] + k);
+            double eF = 0.0;
+            for (int l = 0; l < 3; ++l) {
+              eF += eta[l] * F[l * nc + g];
+              lF[l * nc + g] += sgn * eta[l] * Sv[id];
+            }
+            for (int kk = 0; kk < 3; ++kk) {
+              lx[kk] += sgn * eF * dS[id][kk];
+              if (e == 1) ld[kk] += sgn * eF * dS[id][kk];
+            }
+          }
+    }
+  }
+  return 0;
+}
+
+/* adjoint of the continuity + CN update of one mode set: given the adjoints
+   of the new level (any may be NULL = zero), accumulate those of the old
+   level (9 spectra: phi, psi, A0..2, U0..2, rho; may be NULL) and of J^ */
+static void cn_adjoint(const orc_sim* S, const cplx* lphi1, const cplx* lpsi1, const cplx* lA1,
+                       const cplx* lU1, const cplx* lrho1, cplx* lF0, cplx* lJh) {
+  const grid* G = &S->G;
+  double dt = S->c.dt, kap2 = S->c.kappa * S->c.kappa, a = 0.5 * dt;
+  int64_t nc = G->ncell;
+  for (int64_t g = 0; g < nc; ++g) {
+    double k[3];
+    mode_k(G, g, k);
+    double w2 = kap2 * (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    double det = 1.0 + a * a * w2;
+    cplx lp1 = lphi1 ? lphi1[g] : 0.0, ls1 = lpsi1 ? lpsi1[g] : 0.0;
+    cplx lb1 = (lp1 - a * w2 * ls1) / det;
+    cplx lb2 = (a * lp1 + ls1) / det;
+    cplx lrhoh = dt * kap2 * S->c.sigma1 * lb2;
+    cplx lr1 = (lrho1 ? lrho1[g] : 0.0) + 0.5 * lrhoh;
+    if (lF0) {
+      lF0[g] += lb1 - a * w2 * lb2;
+      lF0[nc + g] += a * lb1 + lb2;
+      lF0[8 * nc + g] += lr1 + 0.5 * lrhoh;
+    }
+    for (int l = 0; l < 3; ++l) {
+      int64_t lg = (int64_t)l * nc + g;
+      cplx la = lA1 ? lA1[lg] : 0.0, lu = lU1 ? lU1[lg] : 0.0;
+      cplx lc1 = (la - a * w2 * lu) / det;
+      cplx lc2 = (a * la + lu) / det;
+      if (lF0) {
+        lF0[(2 + l) * nc + g] += lc1 - a * w2 * lc2;
+        lF0[(5 + l) * nc + g] += a * lc1 + lc2;
+      }
+      lJh[lg] += dt * kap2 * S->c.sigma2 * lc2 + dt * I * k[l] * lr1;
+    }
+  }
+}
+
+/* lambda of a spectrum from lambda of its real-space inverse transform */
+static void adj_of_to_real(const grid* G, const double* ly, cplx* lz) {
+  to_fourier(G, ly, lz);
+  for (int64_t g = 0; g < G->ncell; ++g) lz[g] /= (double)G->ncell;
+}
+
+/* lambda of a real array from lambda of its forward transform */
+static void adj_of_to_fourier(const grid* G, const cplx* lz, double* lx) {
+  cplx* t = (cplx*)malloc(sizeof(cplx) * G->ncell);
+  memcpy(t, lz, sizeof(cplx) * G->ncell);
+  dft3(G, t, +1);
+  for (int64_t g = 0; g < G->ncell; ++g) lx[g] = creal(t[g]) * (double)G->ncell;
+  free(t);
+}
+
+/* Mesh half of (dG/dw)^T: push-side mesh adjoints (gphi, A0, A1) -> adjoint
+   of J (real, 3 x nc) times q/dV, and the old level's share (lF0h, spectral,
+   accumulated when not NULL). */
+static void mesh_adjoint(const orc_sim* S, const double* lgphi, const double* lA0r,
+                         const double* lA1r, double* mu, cplx* lF0h) {
+  const grid* G = &S->G;
+  int64_t nc = G->ncell;
+  cplx* lphi1 = (cplx*)calloc(nc, sizeof(cplx));
+  cplx* lA1h = (cplx*)calloc(3 * nc, sizeof(cplx));
+  cplx* lJh = (cplx*)calloc(3 * nc, sizeof(cplx));
+  cplx* t = (cplx*)malloc(sizeof(cplx) * nc);
+  for (int l = 0; l < 3; ++l) {
+    adj_of_to_real(G, lgphi + l * nc, t);  /* gphi_l = Re IDFT(i k_l (phi + phi')/2) */
+    for (int64_t g = 0; g < nc; ++g) {
+      double k[3];
+      mode_k(G, g, k);
+      cplx c = -0.5 * I * k[l] * t[g];
+      lphi1[g] += c;
+      if (lF0h) lF0h[g] += c;
+    }
+    adj_of_to_real(G, lA1r + l * nc, lA1h + l * nc);
+    if (lF0h) {
+      adj_of_to_real(G, lA0r + l * nc, t);
+      for (int64_t g = 0; g < nc; ++g) lF0h[(2 + l) * nc + g] += t[g];
+    }
+  }
+  cn_adjoint(S, lphi1, NULL, lA1h, NULL, NULL, lF0h, lJh);
+  for (int l = 0; l < 3; ++l) {
+    adj_of_to_fourier(G, lJh + l * nc, mu + l * nc);
+    for (int64_t g = 0; g < nc; ++g) mu[l * nc + g] *= S->q / G->dV;
+  }
+  free(lphi1);
+  free(lA1h);
+  free(lJh);
+  free(t);
+}
+
+/* One step's adjoint.  x, v (3 x np, component-major), w = the converged
+   v^{n+1}, F = level-n fields (9 x nc real: phi, psi, A, U, rho); lx1, lv1,
+   lF1 = adjoints of x^{n+1}, v^{n+1}, F^{n+1} (any may be NULL = zero).
+   Outputs lx0, lv0, lF0.  Returns 0, 1 if the transposed iteration did not
+   reach tol within maxit, -1 on a configuration it does not cover. */
+int orc_adjoint_step(const orc_sim* S, const double* x, const double* v, const double* w,
+                     const double* F, const double* lx1, const double* lv1, const double* lF1,
+                     double* lx0, double* lv0, double* lF0, double tol, int maxit,
+                     int* iters_out) {
+  const grid* G = &S->G;
+  if (S->c.r != 2 || !S->c.split) return -1;
+  int64_t np = S->np, nc = G->ncell;
+  double dt = S->c.dt, q = S->q, m = S->m;
+  double* vb = (double*)malloc(sizeof(double) * 3 * np + 8);
+  double* J = (double*)calloc(3 * nc, sizeof(double));
+  cplx* Fh = (cplx*)malloc(sizeof(cplx) * 9 * nc);
+  cplx* F1h = (cplx*)malloc(sizeof(cplx) * 9 * nc);
+  cplx* Jh = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  cplx* t = (cplx*)malloc(sizeof(cplx) * nc);
+  double *gphi = (double*)malloc(sizeof(double) * 3 * nc), *A0r = (double*)malloc(sizeof(double) * 3 * nc),
+         *A1r = (double*)malloc(sizeof(double) * 3 * nc);
+  double *lgphi = (double*)malloc(sizeof(double) * 3 * nc), *lA0 = (double*)malloc(sizeof(double) * 3 * nc),
+         *lA1 = (double*)malloc(sizeof(double) * 3 * nc), *mu = (double*)malloc(sizeof(double) * 3 * nc);
+  cplx* lF0h = (cplx*)calloc(9 * nc, sizeof(cplx));
+  cplx* lJh = (cplx*)calloc(3 * nc, sizeof(cplx));
+  double *bw = (double*)malloc(sizeof(double) * 3 * np + 8), *xi = (double*)malloc(sizeof(double) * 3 * np + 8),
+         *xn = (double*)malloc(sizeof(double) * 3 * np + 8);
+  double* lxacc = (double*)malloc(sizeof(double) * 3 * np + 8);
+  piece* buf = (piece*)malloc(sizeof(piece) * MAX_PIECES);
+  int status = 0, it = 0;
+
+  /* forward quantities at the converged w */
+  for (int64_t i = 0; i < np; ++i) {
+    double x0[3], b[3], d[3], qv[3];
+    for (int a = 0; a < 3; ++a) {
+      x0[a] = x[a * np + i];
+      b[a] = 0.5 * (w[a * np + i] + v[a * np + i]);
+      vb[a * np + i] = b[a];
+      d[a] = dt * b[a];
+      qv[a] = q * b[a];
+    }
+    if (deposit_one(S, x0, d, qv, J, buf) != 0) { status = -1; goto done; }
+  }
+  for (int f = 0; f < 9; ++f) to_fourier(G, F + f * nc, Fh + f * nc);
+  for (int l = 0; l < 3; ++l) to_fourier(G, J + l * nc, Jh + l * nc);
+  field_update(S, Jh, Fh, Fh + nc, Fh + 2 * nc, Fh + 5 * nc, Fh + 8 * nc, F1h, F1h + nc,
+               F1h + 2 * nc, F1h + 5 * nc, F1h + 8 * nc);
+  for (int l = 0; l < 3; ++l) {
+    for (int64_t g = 0; g < nc; ++g) {
+      double k[3];
+      mode_k(G, g, k);
+      t[g] = I * k[l] * 0.5 * (F1h[g] + Fh[g]);
+    }
+    to_real(G, t, gphi + l * nc);
+    to_real(G, Fh + (2 + l) * nc, A0r + l * nc);
+    to_real(G, F1h + (2 + l) * nc, A1r + l * nc);
+  }
+
+  /* adjoints reaching w directly from the outputs */
+  if (lF1) {
+    cplx* lF1h = (cplx*)malloc(sizeof(cplx) * 9 * nc);
+    for (int f = 0; f < 9; ++f) adj_of_to_real(G, lF1 + f * nc, lF1h + f * nc);
+    cn_adjoint(S, lF1h, lF1h + nc, lF1h + 2 * nc, lF1h + 5 * nc, lF1h + 8 * nc, lF0h, lJh);
+    free(lF1h);
+  }
+  for (int l = 0; l < 3; ++l) {
+    adj_of_to_fourier(G, lJh + l * nc, mu + l * nc);
+    for (int64_t g = 0; g < nc; ++g) mu[l * nc + g] *= q / G->dV;
+  }
+  for (int64_t i = 0; i < np; ++i) {
+    double x0[3], b[3], lx[3] = {0, 0, 0}, ld[3] = {0, 0, 0}, lvb[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+      x0[a] = x[a * np + i];
+      b[a] = vb[a * np + i];
+    }
+    if (particle_adjoint(S, x0, b, NULL, mu, NULL, NULL, NULL, lx, ld, lvb, NULL, NULL, NULL)) {
+      status = -1;
+      goto done;
+    }
+    for (int a = 0; a < 3; ++a) {
+      int64_t id = a * np + i;
+      double lxo = lx1 ? lx1[id] : 0.0;
+      ld[a] += lxo; /* x' = x + d */
+      bw[id] = (lv1 ? lv1[id] : 0.0) + 0.5 * (lvb[a] + dt * ld[a]);
+      lxacc[id] = lxo + lx[a];
+    }
+  }
+
+  /* transposed Picard iteration xi = bw + (dG/dw)^T xi */
+  memcpy(xi, bw, sizeof(double) * 3 * np);
+  for (it = 1; it <= maxit + 1; ++it) {
+    int last = it == maxit + 1;
+    memset(lgphi, 0, sizeof(double) * 3 * nc);
+    memset(lA0, 0, sizeof(double) * 3 * nc);
+    memset(lA1, 0, sizeof(double) * 3 * nc);
+    double* lxs = (double*)calloc(3 * np + 1, sizeof(double));
+    double* lds = (double*)calloc(3 * np + 1, sizeof(double));
+    double* lvbs = (double*)calloc(3 * np + 1, sizeof(double));
+    for (int64_t i = 0; i < np; ++i) {
+      double x0[3], b[3], eta[3], lx[3] = {0, 0, 0}, ld[3] = {0, 0, 0}, lvb[3] = {0, 0, 0};
+      for (int a = 0; a < 3; ++a) {
+        x0[a] = x[a * np + i];
+        b[a] = vb[a * np + i];
+        eta[a] = q / m * xi[a * np + i];
+      }
+      particle_adjoint(S, x0, b, eta, NULL, gphi, A0r, A1r, lx, ld, lvb, lgphi, lA0, lA1);
+      for (int a = 0; a < 3; ++a) {
+        lxs[a * np + i] = lx[a];
+        lds[a * np + i] = ld[a];
+        lvbs[a * np + i] = lvb[a];
+      }
+    }
+    mesh_adjoint(S, lgphi, lA0, lA1, mu, NULL);
+    for (int64_t i = 0; i < np; ++i) {
+      double x0[3], b[3], lx[3] = {0, 0, 0}, ld[3] = {0, 0, 0}, lvb[3] = {0, 0, 0};
+      for (int a = 0; a < 3; ++a) {
+        x0[a] = x[a * np + i];
+        b[a] = vb[a * np + i];
+      }
+      particle_adjoint(S, x0, b, NULL, mu, NULL, NULL, NULL, lx, ld, lvb, NULL, NULL, NULL);
+      for (int a = 0; a < 3; ++a) {
+        lxs[a * np + i] += lx[a];
+        lds[a * np + i] += ld[a];
+        lvbs[a * np + i] += lvb[a];
+      }
+    }
+    double dmax = 0.0, xmax = 0.0;
+    for (int64_t id = 0; id < 3 * np; ++id) {
+      xn[id] = bw[id] + 0.5 * (lvbs[id] + dt * lds[id]);
+      dmax = fmax(dmax, fabs(xn[id] - xi[id]));
+      xmax = fmax(xmax, fabs(xn[id]));
+    }
+    int conv = dmax <= tol * xmax;
+    if (conv || last) {
+      /* xi is the fixed point (to tol): collect the inputs' adjoints with it */
+      for (int64_t id = 0; id < 3 * np; ++id) lxacc[id] += lxs[id];
+      mesh_adjoint(S, lgphi, lA0, lA1, mu, lF0h);
+      if (!conv) status = 1;
+      free(lxs);
+      free(lds);
+      free(lvbs);
+      break;
+    }
+    memcpy(xi, xn, sizeof(double) * 3 * np);
+    free(lxs);
+    free(lds);
+    free(lvbs);
+  }
+  if (lx0) memcpy(lx0, lxacc, sizeof(double) * 3 * np);
+  if (lv0)
+    for (int64_t id = 0; id < 3 * np; ++id) lv0[id] = 2.0 * xi[id] - (lv1 ? lv1[id] : 0.0);
+  if (lF0)
+    for (int f = 0; f < 9; ++f) adj_of_to_fourier(G, lF0h + f * nc, lF0 + f * nc);
+
+done:
+  if (iters_out) *iters_out = it;
+  free(vb); free(J); free(Fh); free(F1h); free(Jh); free(t);
+  free(gphi); free(A0r); free(A1r); free(lgphi); free(lA0); free(lA1); free(mu);
+  free(lF0h); free(lJh); free(bw); free(xi); free(xn); free(lxacc); free(buf);
+  return status;
+}
+
+/* P^n = m v^n + q A_h^n(x^n) from the present state (eq. discrete-canonical-relation) */
+int orc_rebuild_P(orc_sim* S) {
+  const grid* G = &S->G;
+  int64_t np = S->np, nc = G->ncell;
+  double* A0r = (double*)malloc(sizeof(double) * 3 * nc);
+  for (int l = 0; l < 3; ++l) to_real(G, S->A + l * nc, A0r + l * nc);
+  for (int64_t i = 0; i < np; ++i) {
+    double x0[3], Ax[3];
+    for (int a = 0; a < 3; ++a) x0[a] = S->x[a * np + i];
+    interp_point(G, S->c.r, x0, A0r, 3, Ax);
+    for (int a = 0; a < 3; ++a) S->P[a * np + i] = S->m * S->v[a * np + i] + S->q * Ax[a];
+  }
+  free(A0r);
+  return 0;
+}
+
+/* gradient of W (eq. field-energy) with respect to the real-space fields
+   (9 x nc: phi, psi, A, U, rho) of the present state */
+int orc_field_energy_grad(const orc_sim* S, double* lF) {
+  const grid* G = &S->G;
+  int64_t nc = G->ncell;
+  cplx* Eh = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  cplx* Bh = (cplx*)malloc(sizeof(cplx) * 3 * nc);
+  cplx* lFh = (cplx*)calloc(9 * nc, sizeof(cplx));
+  double* f = (double*)malloc(sizeof(double) * nc);
+  cplx* t = (cplx*)malloc(sizeof(cplx) * nc);
+  for (int64_t g = 0; g < nc; ++g) {
+    double k[3];
+    mode_k(G, g, k);
+    for (int l = 0; l < 3; ++l) Eh[l * nc + g] = -I * k[l] * S->phi[g] - S->U[l * nc + g];
+    Bh[0 * nc + g] = I * (k[1] * S->A[2 * nc + g] - k[2] * S->A[1 * nc + g]);
+    Bh[1 * nc + g] = I * (k[2] * S->A[0 * nc + g] - k[0] * S->A[2 * nc + g]);
+    Bh[2 * nc + g] = I * (k[0] * S->A[1 * nc + g] - k[1] * S->A[0 * nc + g]);
+  }
+  for (int l = 0; l < 3; ++l) {
+    /* E_l: dW/dE = dV E / sigma1 */
+    to_real(G, Eh + l * nc, f);
+    for (int64_t g = 0; g < nc; ++g) f[g] *= G->dV / S->c.sigma1;
+    adj_of_to_real(G, f, t);
+    for (int64_t g = 0; g < nc; ++g) {
+      double k[3];
+      mode_k(G, g, k);
+      lFh[g] += I * k[l] * t[g];         /* E = -i k phi - U */
+      lFh[(5 + l) * nc + g] -= t[g];
+    }
+    /* B_l: dW/dB = dV B / sigma2; B_l = i (k_p A_q - k_q A_p), (l, p, q) cyclic */
+    to_real(G, Bh + l * nc, f);
+    for (int64_t g = 0; g < nc; ++g) f[g] *= G->dV / S->c.sigma2;
+    adj_of_to_real(G, f, t);
+    int p = (l + 1) % 3, qq = (l + 2) % 3;
+    for (int64_t g = 0; g < nc; ++g) {
+      double k[3];
+      mode_k(G, g, k);
+      lFh[(2 + qq) * nc + g] += -I * k[p] * t[g];
+      lFh[(2 + p) * nc + g] += I * k[qq] * t[g];
+    }
+  }
+  for (int fi = 0; fi < 9; ++fi) adj_of_to_fourier(G, lFh + fi * nc, lF + fi * nc);
+  free(Eh); free(Bh); free(lFh); free(f); free(t);
+  return 0;
+}
