@@ -192,6 +192,54 @@ typedef struct {
 ecpic_status ecpic_set_profiling(ecpic_sim* sim, int32_t enable);
 ecpic_status ecpic_get_profile(ecpic_sim* sim, ecpic_profile* out);
 
+/* ---- Differentiation: adjoint of one converged step --------------------
+   The converged step of Algorithm 1 maps the level-n state (x, v, fields) to
+   the level-(n+1) state through the solution w = v^{n+1} of the implicit
+   push (eq. orbit-push with P^n rebuilt by eq. discrete-canonical-relation,
+   the orbit current of eq. orbit-current, and eqs. cn-continuity and
+   cn-field-update).  ecpic_adjoint_step() applies the transpose of that
+   map's Jacobian (implicit-function form, solved by the transposed Picard
+   iteration xi = b + (dG/dw)^T xi, which contracts like the forward one):
+   given the adjoints of x^{n+1}, v^{n+1} and the level-(n+1) fields it
+   returns those of x^n, v^n and the level-n fields.  v^{n-1} only sets the
+   first guess of the iteration, so the converged step does not depend on it.
+   Requirements: precision ECPIC_FP64, spline_degree 2 (with degree 1 the
+   derivative of the piecewise-constant shape gradient jumps at knots),
+   split_orbit_at_knots 1.
+
+   Device pointers, FP64, particles in the caller's order, on the simulation's
+   stream (the call returns after the stream is synchronised):
+     x, v, w      3*np component-major: x^n (inside the box), v^n, and the
+                  converged v^{n+1} of the step from this state
+     fields       9*ncell: level-n fields (layout of ecpic_get_state)
+     lx1, lv1     3*np adjoints of x^{n+1} and v^{n+1}; NULL = zero
+     lF1          9*ncell adjoint of the level-(n+1) fields; NULL = zero
+     lx0, lv0     3*np outputs: adjoints of x^n and v^n
+     lF0          9*ncell output: adjoint of the level-n fields
+     tol          stop when max|xi^{k+1} - xi^k| <= tol max|xi^{k+1}|
+     max_iters    iteration bound (ECPIC_ENOCONV if reached; outputs still set)
+   workspace: caller-owned device buffer of ecpic_adjoint_workspace_bytes()
+   bytes (256-byte aligned).  The simulation's own state is not changed; its
+   scratch is reused. */
+typedef struct {
+  int32_t iters;     /* transposed Picard iterations */
+  int32_t converged; /* 1 if tol was reached */
+  double err;        /* last max|xi^{k+1} - xi^k| / max|xi^{k+1}| */
+} ecpic_adjoint_info;
+
+ecpic_status ecpic_adjoint_workspace_bytes(const ecpic_config* cfg, int64_t n_particles,
+                                           size_t* bytes);
+ecpic_status ecpic_adjoint_step(ecpic_sim* sim, void* workspace, size_t workspace_bytes,
+                                const double* x, const double* v, const double* w,
+                                const double* fields, const double* lx1, const double* lv1,
+                                const double* lF1, double* lx0, double* lv0, double* lF0,
+                                double tol, int32_t max_iters, ecpic_adjoint_info* info);
+
+/* Gradient of the field energy W (eq. field-energy) of the present state with
+   respect to its real-space fields: device output, 9*ncell (layout of
+   ecpic_get_state; the psi and rho rows are zero). */
+ecpic_status ecpic_field_energy_grad(ecpic_sim* sim, double* lF);
+
 /* Message for the last non-OK status of this thread ("" if none). */
 const char* ecpic_last_error(void);
 

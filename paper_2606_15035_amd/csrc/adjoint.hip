@@ -1,0 +1,264 @@
+// Particle side of the adjoint of a converged step (degree 2, split orbits).
+//
+// The converged step solves w = G(w; x, v, F) with vbar = (w + v)/2,
+// d = dt vbar and (P^n rebuilt from eq. discrete-canonical-relation)
+//   G = v + (q/m) [A0_h(x) - A1_h(x + d)] + (q dt/m) [-gphibar + (D A)^T vbar],
+//   gphibar = sum_g gphi_g Sbar_g,
+//   ((D A)^T vbar)_j = sum_g int b_g(s) d_j S_g(x(s)) ds,  b_g(s) = vbar.((1-s) A0_g + s A1_g),
+// (eqs. orbit-push, split-Sbar, split-DA), and the current
+//   J_g = (q/dV) sum_i vbar_i Sbar_ig   (eq. orbit-current).
+// For a particle with push adjoint eta = (q/m) xi and current adjoint
+// mu = (q/dV) lambda_J, this kernel adds the derivatives with respect to
+// x, d and vbar, and scatters the push's mesh adjoints of gphi, A0 and A1.
+// Inside each split piece the integrands are polynomials of degree <= 6 in s
+// (4-point Gauss-Legendre is exact); the piece ends move with x and d, but
+// the integrands b_g d_j S_g and S_g are continuous across knots for degree
+// 2, so no end-point terms arise.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "orbit.hpp"
+#include "reduce.hpp"
+
+namespace ecpic {
+
+namespace {
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// weights, first and second derivatives (physical units) of the three
+// degree-2 stencil nodes along one axis
+struct Axis2 {
+  double w[3], dw[3], ddw[3];
+  __device__ __forceinline__ void at(double t, double invH) {
+    Spline<2>::wd(t, w, dw);
+    const double i2 = invH * invH;
+#pragma unroll
+    for (int o = 0; o < 3; ++o) dw[o] *= invH;
+    ddw[0] = i2;
+    ddw[1] = -2.0 * i2;
+    ddw[2] = i2;
+  }
+};
+
+template <bool ETA, bool MU>
+__global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= P.np) return;
+  const Grid& G = P.G;
+  const int64_t np = P.np, nc = G.ncell;
+  double x0[3], vb[3], d[3], eta[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    x0[a] = P.x[a * np + i];
+    vb[a] = P.vb[a * np + i];
+    d[a] = P.dt * vb[a];
+    if constexpr (ETA) eta[a] = P.qm * P.xi[a * np + i];
+  }
+  double lx[3] = {0.0, 0.0, 0.0}, ld[3] = {0.0, 0.0, 0.0}, lvb[3] = {0.0, 0.0, 0.0};
+  const bool ok = for_each_piece<2>(x0, d, G, [&](double s0, double s1) {
+    const double h = s1 - s0;
+    double base[3];
+    piece_base<2>(x0, d, 0.5 * (s0 + s1), G, base);
+    int first[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) first[a] = to_int_clamped(base[a]) + Spline<2>::first_off;
+    for (int q = 0; q < 4; ++q) {
+      const double s = s0 + 0.5 * h * (1.0 + Gauss<4>::x(q));
+      const double wt = 0.5 * h * Gauss<4>::w(q);
+      Axis2 X, Y, Z;
+      X.at((x0[0] + s * d[0]) * G.invH[0] - base[0], G.invH[0]);
+      Y.at((x0[1] + s * d[1]) * G.invH[1] - base[1], G.invH[1]);
+      Z.at((x0[2] + s * d[2]) * G.invH[2] - base[2], G.invH[2]);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          for (int c = 0; c < 3; ++c) {
+            const int64_t g = node_index(G, first[0] + a, first[1] + b, first[2] + c);
+            const double S = X.w[a] * Y.w[b] * Z.w[c];
+            const double dS[3] = {X.dw[a] * Y.w[b] * Z.w[c], X.w[a] * Y.dw[b] * Z.w[c],
+                                  X.w[a] * Y.w[b] * Z.dw[c]};
+            if constexpr (ETA) {
+              const double Hs[3][3] = {
+                  {X.ddw[a] * Y.w[b] * Z.w[c], X.dw[a] * Y.dw[b] * Z.w[c], X.dw[a] * Y.w[b] * Z.dw[c]},
+                  {X.dw[a] * Y.dw[b] * Z.w[c], X.w[a] * Y.ddw[b] * Z.w[c], X.w[a] * Y.dw[b] * Z.dw[c]},
+                  {X.dw[a] * Y.w[b] * Z.dw[c], X.w[a] * Y.dw[b] * Z.dw[c], X.w[a] * Y.w[b] * Z.ddw[c]}};
+              double Ag[3], bg = 0.0, edS = 0.0, eg = 0.0;
+#pragma unroll
+              for (int l = 0; l < 3; ++l) {
+                Ag[l] = (1.0 - s) * P.A0[l * nc + g] + s * P.A1[l * nc + g];
+                bg += vb[l] * Ag[l];
+                edS += eta[l] * dS[l];
+                eg += eta[l] * P.gphi[l * nc + g];
+              }
+              const double c1 = P.dt * wt;
+#pragma unroll
+              for (int kk = 0; kk < 3; ++kk) {
+                const double eH = eta[0] * Hs[0][kk] + eta[1] * Hs[1][kk] + eta[2] * Hs[2][kk];
+                lx[kk] += c1 * (bg * eH - eg * dS[kk]);        // (D A)^T vbar, -gphibar
+                ld[kk] += c1 * s * (bg * eH - eg * dS[kk]);
+                lvb[kk] += c1 * Ag[kk] * edS;
+              }
+#pragma unroll
+              for (int l = 0; l < 3; ++l) {
+                unsafeAtomicAdd(P.lgphi + l * nc + g, -c1 * eta[l] * S);
+                unsafeAtomicAdd(P.lA0 + l * nc + g, c1 * (1.0 - s) * vb[l] * edS);
+                unsafeAtomicAdd(P.lA1 + l * nc + g, c1 * s * vb[l] * edS);
+              }
+            }
+            if constexpr (MU) {
+              double vm = 0.0;
+#pragma unroll
+              for (int l = 0; l < 3; ++l) {
+                const double m = P.mu[l * nc + g];
+                lvb[l] += wt * m * S;
+                vm += vb[l] * m;
+              }
+#pragma unroll
+              for (int kk = 0; kk < 3; ++kk) {
+                lx[kk] += wt * vm * dS[kk];
+                ld[kk] += wt * s * vm * dS[kk];
+              }
+            }
+          }
+    }
+  });
+  if constexpr (ETA) {  // + A0_h(x0) - A1_h(x0 + d), end point wrapped
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const double sgn = e == 0 ? 1.0 : -1.0;
+      const double* F = e == 0 ? P.A0 : P.A1;
+      double* lF = e == 0 ? P.lA0 : P.lA1;
+      double base[3];
+      int first[3];
+      Axis2 ax[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double xp = e == 0 ? x0[a] : wrap_pos(x0[a] + d[a], G.L[a], G.invL[a]);
+        const double u = xp * G.invH[a];
+        base[a] = floor(u + Spline<2>::base_off);
+        first[a] = to_int_clamped(base[a]) + Spline<2>::first_off;
+        ax[a].at(u - base[a], G.invH[a]);
+      }
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          for (int c = 0; c < 3; ++c) {
+            const int64_t g = node_index(G, first[0] + a, first[1] + b, first[2] + c);
+            const double S = ax[0].w[a] * ax[1].w[b] * ax[2].w[c];
+            const double dS[3] = {ax[0].dw[a] * ax[1].w[b] * ax[2].w[c],
+                                  ax[0].w[a] * ax[1].dw[b] * ax[2].w[c],
+                                  ax[0].w[a] * ax[1].w[b] * ax[2].dw[c]};
+            double eF = 0.0;
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+              eF += eta[l] * F[l * nc + g];
+              unsafeAtomicAdd(lF + l * nc + g, sgn * eta[l] * S);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) {
+              lx[kk] += sgn * eF * dS[kk];
+              if (e == 1) ld[kk] += sgn * eF * dS[kk];
+            }
+          }
+    }
+  }
+  if (!ok) P.bad[0] = 1.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    P.lx[a * np + i] += lx[a];
+    P.ld[a * np + i] += ld[a];
+    P.lvb[a * np + i] += lvb[a];
+  }
+}
+
+// vbar = (w + v)/2
+__global__ __launch_bounds__(kBlock) void k_vbar(int64_t n3, const double* __restrict__ w,
+                                                const double* __restrict__ v,
+                                                double* __restrict__ vb) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n3) vb[i] = 0.5 * (w[i] + v[i]);
+}
+
+// b = lv1 + (lvb + dt (ld + lx1)) / 2, lxacc = lx1 + lx
+__global__ __launch_bounds__(kBlock) void k_adjoint_rhs(int64_t n3, double dt,
+                                                       const double* __restrict__ lx1,
+                                                       const double* __restrict__ lv1,
+                                                       const double* __restrict__ lx,
+                                                       const double* __restrict__ ld,
+                                                       const double* __restrict__ lvb,
+                                                       double* __restrict__ b,
+                                                       double* __restrict__ lxacc) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n3) return;
+  const double x1 = lx1 ? lx1[i] : 0.0;
+  b[i] = (lv1 ? lv1[i] : 0.0) + 0.5 * (lvb[i] + dt * (ld[i] + x1));
+  lxacc[i] = x1 + lx[i];
+}
+
+// xn = b + (lvb + dt ld)/2; max|xn - xi| and max|xn| into red[0], red[1]
+__global__ __launch_bounds__(kBlock) void k_adjoint_update(int64_t n3, double dt,
+                                                          const double* __restrict__ b,
+                                                          const double* __restrict__ lvb,
+                                                          const double* __restrict__ ld,
+                                                          const double* __restrict__ xi,
+                                                          double* __restrict__ xn,
+                                                          double* __restrict__ red) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double dm = 0.0, xm = 0.0;
+  if (i < n3) {
+    const double x = b[i] + 0.5 * (lvb[i] + dt * ld[i]);
+    xn[i] = x;
+    dm = fabs(x - xi[i]);
+    xm = fabs(x);
+    if (!isfinite(x)) dm = INFINITY;
+  }
+  block_max_to(dm, red);
+  block_max_to(xm, red + 1);
+}
+
+// lx0 = lxacc + lx, lv0 = 2 xi - lv1
+__global__ __launch_bounds__(kBlock) void k_adjoint_out(int64_t n3, const double* __restrict__ lxacc,
+                                                       const double* __restrict__ lx,
+                                                       const double* __restrict__ xi,
+                                                       const double* __restrict__ lv1,
+                                                       double* __restrict__ lx0,
+                                                       double* __restrict__ lv0) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n3) return;
+  lx0[i] = lxacc[i] + lx[i];
+  lv0[i] = 2.0 * xi[i] - (lv1 ? lv1[i] : 0.0);
+}
+
+}  // namespace
+
+void launch_particle_adjoint(hipStream_t s, const AdjParticleArgs& P, bool eta, bool mu) {
+  if (P.np <= 0) return;
+  if (eta && mu)
+    k_particle_adjoint<true, true><<<blocks_for(P.np), kBlock, 0, s>>>(P);
+  else if (eta)
+    k_particle_adjoint<true, false><<<blocks_for(P.np), kBlock, 0, s>>>(P);
+  else if (mu)
+    k_particle_adjoint<false, true><<<blocks_for(P.np), kBlock, 0, s>>>(P);
+}
+
+void launch_vbar(hipStream_t s, int64_t n3, const double* w, const double* v, double* vb) {
+  if (n3 > 0) k_vbar<<<blocks_for(n3), kBlock, 0, s>>>(n3, w, v, vb);
+}
+
+void launch_adjoint_rhs(hipStream_t s, int64_t n3, double dt, const double* lx1, const double* lv1,
+                        const double* lx, const double* ld, const double* lvb, double* b,
+                        double* lxacc) {
+  if (n3 > 0) k_adjoint_rhs<<<blocks_for(n3), kBlock, 0, s>>>(n3, dt, lx1, lv1, lx, ld, lvb, b, lxacc);
+}
+
+void launch_adjoint_update(hipStream_t s, int64_t n3, double dt, const double* b,
+                           const double* lvb, const double* ld, const double* xi, double* xn,
+                           double* red) {
+  if (n3 > 0) k_adjoint_update<<<blocks_for(n3), kBlock, 0, s>>>(n3, dt, b, lvb, ld, xi, xn, red);
+}
+
+void launch_adjoint_out(hipStream_t s, int64_t n3, const double* lxacc, const double* lx,
+                        const double* xi, const double* lv1, double* lx0, double* lv0) {
+  if (n3 > 0) k_adjoint_out<<<blocks_for(n3), kBlock, 0, s>>>(n3, lxacc, lx, xi, lv1, lx0, lv0);
+}
+
+}  // namespace ecpic

@@ -271,6 +271,55 @@ ecpic_status update_level_energies(ecpic_sim* S) {
 
 }  // namespace
 
+namespace {
+
+// Device workspace of the adjoint step (caller-owned).
+struct AdjWs {
+  double *vb, *xi, *xn, *b, *lxacc, *lx, *ld, *lvb;  // 3 x np each
+  double *J, *gfield, *lg_r, *mu;                     // 3, 6, 9, 3 x ncell (real)
+  double2 *Fh, *F1h, *Jh, *inv, *l1, *lg, *lcur, *lJh;  // 9, 9, 3, 6, 9, 9, 9, 3 x ncell
+  double* red;                                        // [max|dxi|, max|xi|, bad]
+};
+
+size_t carve_adjoint(const Grid& G, int64_t np, char* base, AdjWs* A) {
+  const size_t n3 = (size_t)3 * (np > 0 ? np : 1);
+  const int64_t nc = G.ncell;
+  Carver c{base};
+  double** pv[8] = {&A->vb, &A->xi, &A->xn, &A->b, &A->lxacc, &A->lx, &A->ld, &A->lvb};
+  for (double** q : pv) *q = c.take<double>(n3);
+  A->J = c.take<double>(3 * nc);
+  A->gfield = c.take<double>(6 * nc);
+  A->lg_r = c.take<double>(9 * nc);
+  A->mu = c.take<double>(3 * nc);
+  A->Fh = c.take<double2>(9 * nc);
+  A->F1h = c.take<double2>(9 * nc);
+  A->Jh = c.take<double2>(3 * nc);
+  A->inv = c.take<double2>(6 * nc);
+  A->l1 = c.take<double2>(9 * nc);
+  A->lg = c.take<double2>(9 * nc);
+  A->lcur = c.take<double2>(9 * nc);
+  A->lJh = c.take<double2>(3 * nc);
+  A->red = c.take<double>(4);
+  return c.off + 256;
+}
+
+ecpic_status check_adjoint_config(const ecpic_config* cfg) {
+  if (cfg->precision != ECPIC_FP64) return fail(ECPIC_EINVAL, "adjoint: FP64 precision only");
+  if (cfg->spline_degree != 2) return fail(ECPIC_EINVAL, "adjoint: spline_degree 2 only");
+  return ECPIC_OK;
+}
+
+// mu = (q/dV) x real part of the unnormalised inverse transform of lJh
+// (the adjoint of J given the adjoint of its forward transform); lJh is used up
+void current_adjoint(ecpic_sim* S, const AdjWs& A) {
+  const int64_t nc = S->G.ncell;
+  launch_spec_copy(S->stream, 3 * nc, A.lJh, A.lJh, S->q / S->G.dV);
+  RealIO o = soa_io(A.mu, nc, 3);
+  fft3_inverse(S->stream, S->G, 3, A.lJh, &o, twp(S));
+}
+
+}  // namespace
+
 extern "C" {
 
 ecpic_status ecpic_state_bytes(const ecpic_config* cfg, int64_t n_particles, size_t* state_bytes,
@@ -728,6 +777,150 @@ ecpic_status ecpic_get_profile(ecpic_sim* S, ecpic_profile* out) {
 
 const char* ecpic_last_error(void) { return g_err.c_str(); }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.3"; }
+ecpic_status ecpic_adjoint_workspace_bytes(const ecpic_config* cfg, int64_t n_particles,
+                                           size_t* bytes) {
+  if (!bytes) return fail(ECPIC_EINVAL, "null output");
+  ecpic_status st = check_config(cfg, n_particles);
+  if (st != ECPIC_OK) return st;
+  st = check_adjoint_config(cfg);
+  if (st != ECPIC_OK) return st;
+  AdjWs A;
+  *bytes = carve_adjoint(make_grid(cfg), n_particles, nullptr, &A);
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_adjoint_step(ecpic_sim* S, void* workspace, size_t workspace_bytes,
+                                const double* x, const double* v, const double* w,
+                                const double* fields, const double* lx1, const double* lv1,
+                                const double* lF1, double* lx0, double* lv0, double* lF0,
+                                double tol, int32_t max_iters, ecpic_adjoint_info* info) {
+  if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  ecpic_status st = check_adjoint_config(&S->cfg);
+  if (st != ECPIC_OK) return st;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(ECPIC_EINVAL, "adjoint workspace must be non-null and 256-byte aligned");
+  const int64_t np = S->np, nc = S->G.ncell, n3 = 3 * np;
+  AdjWs A;
+  if (carve_adjoint(S->G, np, nullptr, &A) > workspace_bytes)
+    return fail(ECPIC_ENOMEM, "adjoint workspace too small");
+  if (!fields || !lx0 || !lv0 || !lF0 || (np > 0 && (!x || !v || !w)))
+    return fail(ECPIC_EINVAL, "null state or output pointer");
+  if (!(tol >= 0.0) || max_iters < 0) return fail(ECPIC_EINVAL, "tol >= 0 and max_iters >= 0");
+  carve_adjoint(S->G, np, static_cast<char*>(workspace), &A);
+  hipStream_t s = S->stream;
+  const Grid& G = S->G;
+  const FieldParams FP = S->fp();
+  StepParams P = S->pp();
+  const double dt = S->cfg.dt;
+
+  // forward quantities of the converged iterate: J, the level n+1 spectra,
+  // grad_h phi^{n+1/2} and A^{n+1} (A^n is the fields' A rows)
+  launch_vbar(s, n3, w, v, A.vb);
+  launch_fill(s, 3 * nc, A.J, 0.0);
+  launch_reset_slots(s, S->sc.red, S_BAD, 1);
+  {
+    Fp64Store view{const_cast<double*>(x), const_cast<double*>(v), nullptr};
+    launch_scatter(s, 2, P, view, w, CurrentOut{A.J, nullptr, 0.0}, S->sc);
+  }
+  RealIO jin = soa_io(A.J, nc, 3);
+  fft3_forward(s, G, 3, A.Jh, &jin, nullptr, twp(S), S->sc);
+  RealIO fin = soa_io(const_cast<double*>(fields), nc, 9);
+  fft3_forward(s, G, 9, A.Fh, &fin, nullptr, twp(S), S->sc);
+  launch_cn_update(s, FP, A.Fh, A.Jh, A.F1h, A.inv, S->sc);
+  RealIO gout = soa_io(A.gfield, nc, 6);
+  fft3_inverse(s, G, 6, A.inv, &gout, twp(S));
+  const double* gphi = A.gfield;
+  const double* A1r = A.gfield + 3 * nc;
+  const double* A0r = fields + 2 * nc;
+
+  AdjParticleArgs PA{G, dt, S->q / S->m, np, x, A.vb, A.xi, A.mu, gphi, A0r, A1r,
+                     A.lx, A.ld, A.lvb, A.lg_r, A.lg_r + 6 * nc, A.lg_r + 3 * nc, A.red + 2};
+  launch_fill(s, 4, A.red, 0.0);
+
+  // adjoints reaching w straight from the outputs
+  launch_fill(s, 2 * 9 * nc, reinterpret_cast<double*>(A.lcur), 0.0);
+  if (lF1) {
+    RealIO l1in = soa_io(const_cast<double*>(lF1), nc, 9);
+    fft3_forward(s, G, 9, A.l1, &l1in, nullptr, twp(S), S->sc);
+    launch_spec_copy(s, 9 * nc, A.l1, A.l1, 1.0 / (double)nc);
+  }
+  launch_cn_adjoint(s, FP, lF1 ? A.l1 : nullptr, nullptr, A.lcur, A.lJh);
+  current_adjoint(S, A);
+  for (double* p : {A.lx, A.ld, A.lvb}) launch_fill(s, n3, p, 0.0);
+  launch_particle_adjoint(s, PA, false, true);
+  launch_adjoint_rhs(s, n3, dt, lx1, lv1, A.lx, A.ld, A.lvb, A.b, A.lxacc);
+  if (n3 > 0)
+    HIPCHK(hipMemcpyAsync(A.xi, A.b, sizeof(double) * n3, hipMemcpyDeviceToDevice, s));
+
+  // transposed Picard iteration
+  int it = 0;
+  bool conv = false;
+  double err = 0.0;
+  for (it = 1; it <= max_iters + 1; ++it) {
+    for (double* p : {A.lx, A.ld, A.lvb}) launch_fill(s, n3, p, 0.0);
+    launch_fill(s, 9 * nc, A.lg_r, 0.0);
+    PA.xi = A.xi;
+    launch_particle_adjoint(s, PA, true, false);
+    RealIO lgin = soa_io(A.lg_r, nc, 9);  // [grad phi, A^{n+1}, A^n]
+    fft3_forward(s, G, 9, A.lg, &lgin, nullptr, twp(S), S->sc);
+    launch_spec_copy(s, 9 * nc, A.lg, A.lg, 1.0 / (double)nc);
+    launch_cn_adjoint(s, FP, nullptr, A.lg, nullptr, A.lJh);
+    current_adjoint(S, A);
+    launch_particle_adjoint(s, PA, false, true);
+    launch_fill(s, 2, A.red, 0.0);
+    launch_adjoint_update(s, n3, dt, A.b, A.lvb, A.ld, A.xi, A.xn, A.red);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(S->host, A.red, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double dm = S->host[0], xm = S->host[1];
+    if (S->host[2] != 0.0)
+      return fail(ECPIC_EINVAL, "adjoint: an orbit crossed more than %d knots", kMaxPieces - 1);
+    if (!std::isfinite(dm) || !std::isfinite(xm))
+      return fail(ECPIC_ENONFINITE, "adjoint: non-finite iterate at iteration %d", it);
+    err = xm > 0.0 ? dm / xm : dm;
+    conv = dm <= tol * xm;
+    if (conv || it == max_iters + 1) {
+      // the inputs' adjoints from this xi: the push's mesh share of level n
+      launch_cn_adjoint(s, FP, nullptr, A.lg, A.lcur, A.lJh);
+      launch_adjoint_out(s, n3, A.lxacc, A.lx, A.xi, lv1, lx0, lv0);
+      RealIO fo = soa_io(lF0, nc, 9);
+      fft3_inverse(s, G, 9, A.lcur, &fo, twp(S));
+      break;
+    }
+    std::swap(A.xi, A.xn);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = it;
+    info->converged = conv ? 1 : 0;
+    info->err = err;
+  }
+  return conv ? ECPIC_OK : ECPIC_ENOCONV;
+}
+
+ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
+  if (!S || !lF) return fail(ECPIC_EINVAL, "null argument");
+  if (!S->initialized) return fail(ECPIC_ESTATE, "field energy gradient before a state is set");
+  const int64_t nc = S->G.ncell;
+  hipStream_t s = S->stream;
+  // E, B as real fields scaled by dV / sigma (dW/dE, dW/dB), via the batch buffers
+  launch_fields_EB(s, S->G, S->spec[S->cur], S->batch);
+  launch_spec_copy(s, 3 * nc, S->batch, S->batch, S->G.dV / S->cfg.sigma1);
+  launch_spec_copy(s, 3 * nc, S->batch + 3 * nc, S->batch + 3 * nc, S->G.dV / S->cfg.sigma2);
+  RealIO eb = soa_io(S->realbuf, nc, 6);
+  fft3_inverse(s, S->G, 6, S->batch, &eb, twp(S));
+  fft3_forward(s, S->G, 6, S->batch, &eb, nullptr, twp(S), S->sc);
+  launch_spec_copy(s, 6 * nc, S->batch, S->batch, 1.0 / (double)nc);
+  launch_energy_adjoint(s, S->G, S->batch, S->batch);  // 6 -> 9 spectra in place
+  RealIO out = soa_io(S->realbuf, nc, 9);
+  fft3_inverse(s, S->G, 9, S->batch, &out, twp(S));
+  HIPCHK(hipMemcpyAsync(lF, S->realbuf, sizeof(double) * 9 * nc, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return ECPIC_OK;
+}
+
+const char* ecpic_version(void) { return "ecpic-gfx950 0.4"; }
 
 }  // extern "C"

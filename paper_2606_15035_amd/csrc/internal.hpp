@@ -175,6 +175,47 @@ void launch_set_A0(hipStream_t s, int64_t ncell, const double* A, double* gbuf);
 void launch_fill(hipStream_t s, int64_t count, double* p, double value);
 void launch_reset_slots(hipStream_t s, double* red, int first, int count);
 
+// ---- adjoint (adjoint.hip, mesh.hip) ----
+struct AdjParticleArgs {
+  Grid G;
+  double dt, qm;       // time step, q/m
+  int64_t np;
+  const double* x;     // x^n, 3 x np
+  const double* vb;    // vbar of the converged iterate, 3 x np
+  const double* xi;    // adjoint of the push output (eta = qm xi), 3 x np
+  const double* mu;    // (q/dV) x adjoint of J, 3 x ncell
+  const double* gphi;  // grad_h phi^{n+1/2}, A^n, A^{n+1}: 3 x ncell each
+  const double* A0;
+  const double* A1;
+  double* lx;          // accumulated per-particle adjoints of x, d, vbar (3 x np)
+  double* ld;
+  double* lvb;
+  double* lgphi;       // push-side mesh adjoints (3 x ncell each), atomics
+  double* lA0;
+  double* lA1;
+  double* bad;         // set to 1 if an orbit had too many pieces
+};
+// eta: push terms with xi; mu: current terms
+void launch_particle_adjoint(hipStream_t s, const AdjParticleArgs& P, bool eta, bool mu);
+void launch_vbar(hipStream_t s, int64_t n3, const double* w, const double* v, double* vb);
+void launch_adjoint_rhs(hipStream_t s, int64_t n3, double dt, const double* lx1, const double* lv1,
+                        const double* lx, const double* ld, const double* lvb, double* b,
+                        double* lxacc);
+void launch_adjoint_update(hipStream_t s, int64_t n3, double dt, const double* b,
+                           const double* lvb, const double* ld, const double* xi, double* xn,
+                           double* red);
+void launch_adjoint_out(hipStream_t s, int64_t n3, const double* lxacc, const double* lx,
+                        const double* xi, const double* lv1, double* lx0, double* lv0);
+// adjoint of k_cn; l1: next level's adjoint spectra (9, nullable); lg: gather
+// fields' adjoint spectra [grad phi (3), A^{n+1} (3), A^n (3)] (nullable);
+// lcur: current level's adjoint spectra, accumulated (nullable); lJh written
+void launch_cn_adjoint(hipStream_t s, const FieldParams& F, const double2* l1, const double2* lg,
+                       double2* lcur, double2* lJh);
+// E, B spectra / ncell of a level (6 fields) and the energy adjoint from
+// their scaled transforms (9 fields)
+void launch_fields_EB(hipStream_t s, const Grid& G, const double2* cur, double2* EB);
+void launch_energy_adjoint(hipStream_t s, const Grid& G, const double2* lEB, double2* lF);
+
 constexpr int kGbufStride = 10;  // [gphi x,y,z | A^n x,y,z | A^{n+1} x,y,z | pad]
 
 }  // namespace ecpic

@@ -457,6 +457,124 @@ void fft_pass(hipStream_t s, const Grid& G, int nb, double2* data, int axis, dou
   k_fft<MODE><<<nblk, kBlock, 0, s>>>(A);
 }
 
+// ---- adjoint of the field update ----------------------------------------
+// Complex spectra carry adjoints in the convention dL = Re sum conj(lambda) dz;
+// every coefficient of k_cn is real except -dt i k of the continuity update,
+// whose adjoint is +dt i k.  Given the adjoints l1 of the next level (9
+// fields, may be null) and the gather-side adjoints lg = [grad phi^{n+1/2}
+// (3), A^{n+1} (3), A^n (3)] as spectra (may be null; A^n only when lcur is
+// set), writes the adjoint of J^ to lJh and adds the current level's share to
+// lcur (may be null).  Transposes k_cn's arithmetic step by step.
+__global__ __launch_bounds__(kBlock) void k_cn_adjoint(FieldParams F, const double2* l1,
+                                                      const double2* lg, double2* lcur,
+                                                      double2* lJh) {
+  const Grid& G = F.G;
+  const int64_t nc = G.ncell;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= nc) return;
+  double k[3];
+  mode_k(G, g, k);
+  const double dt = F.dt, a = 0.5 * dt, kap2 = F.kappa * F.kappa;
+  const double w2 = kap2 * (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  const double inv_den = 1.0 / (1.0 + a * a * w2);
+  const double c_old = 1.0 - a * a * w2, c_x = 2.0 * a * w2;
+  const double src1 = dt * kap2 * F.sigma1, src2 = dt * kap2 * F.sigma2;
+  const double2 z = make_double2(0.0, 0.0);
+  auto at = [&](const double2* p, int f) { return p ? p[f * nc + g] : z; };
+  // gather side: grad phi^{n+1/2} = i k (phi0 + phi1)/2 -> (-i k / 2) per component
+  double2 lphi_g = z;
+  if (lg)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) lphi_g = cadd(lphi_g, ik(-0.5 * k[l], lg[l * nc + g]));
+  const double2 lphi1 = cadd(at(l1, F_PHI), lphi_g);
+  // phi1 = phi0 + a psi0 + a psi1; psi1 = (c_old psi0 - c_x phi0 + src1 rho_h) inv_den
+  const double2 lpsi1 = cadd(at(l1, F_PSI), cscale(lphi1, a));
+  const double2 lphi0 = csub(cadd(lphi1, lphi_g), cscale(lpsi1, c_x * inv_den));
+  const double2 lpsi0 = cadd(cscale(lphi1, a), cscale(lpsi1, c_old * inv_den));
+  const double2 lrhoh = cscale(lpsi1, src1 * inv_den);
+  // rho_h = (rho0 + rho1)/2, rho1 = rho0 - dt i k.J
+  const double2 lrho1 = cadd(at(l1, F_RHO), cscale(lrhoh, 0.5));
+  const double2 lrho0 = cadd(lrho1, cscale(lrhoh, 0.5));
+  double2 lJ[3], lA0[3], lU0[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double2 lA1 = cadd(at(l1, F_A + l), lg ? lg[(3 + l) * nc + g] : z);
+    const double2 lU1 = cadd(at(l1, F_U + l), cscale(lA1, a));
+    lA0[l] = csub(lA1, cscale(lU1, c_x * inv_den));
+    if (lg && lcur) lA0[l] = cadd(lA0[l], lg[(6 + l) * nc + g]);
+    lU0[l] = cadd(cscale(lA1, a), cscale(lU1, c_old * inv_den));
+    lJ[l] = cadd(cscale(lU1, src2 * inv_den), ik(dt * k[l], lrho1));
+    lJh[l * nc + g] = lJ[l];
+  }
+  if (lcur) {
+    lcur[F_PHI * nc + g] = cadd(lcur[F_PHI * nc + g], lphi0);
+    lcur[F_PSI * nc + g] = cadd(lcur[F_PSI * nc + g], lpsi0);
+    lcur[F_RHO * nc + g] = cadd(lcur[F_RHO * nc + g], lrho0);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      lcur[(F_A + l) * nc + g] = cadd(lcur[(F_A + l) * nc + g], lA0[l]);
+      lcur[(F_U + l) * nc + g] = cadd(lcur[(F_U + l) * nc + g], lU0[l]);
+    }
+  }
+}
+
+// Adjoint of W (eq. field-energy) with respect to the spectra of the
+// present level, before the inverse transforms: with E = -i k phi - U and
+// B = i k x A evaluated as real fields and scaled by dV/sigma, lE and lB are
+// their forward transforms / ncell; writes the 9-field adjoint spectrum (lF
+// may be the same buffer as lEB).
+__global__ __launch_bounds__(kBlock) void k_energy_adjoint(Grid G, const double2* lEB,
+                                                          double2* lF) {
+  const int64_t nc = G.ncell;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= nc) return;
+  double k[3];
+  mode_k(G, g, k);
+  const double2 z = make_double2(0.0, 0.0);
+  double2 lE[3], lB[3];  // all inputs first: lF may alias lEB (same mode, other rows)
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    lE[l] = lEB[l * nc + g];
+    lB[l] = lEB[(3 + l) * nc + g];
+  }
+  double2 lphi = z, lA[3] = {z, z, z};
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    lphi = cadd(lphi, ik(k[l], lE[l]));          // E_l = -i k_l phi - U_l
+    const int p = (l + 1) % 3, q = (l + 2) % 3;  // B_l = i (k_p A_q - k_q A_p)
+    lA[q] = cadd(lA[q], ik(-k[p], lB[l]));
+    lA[p] = cadd(lA[p], ik(k[q], lB[l]));
+  }
+#pragma unroll
+  for (int l = 0; l < 3; ++l) lF[(F_U + l) * nc + g] = cscale(lE[l], -1.0);
+  lF[F_PHI * nc + g] = lphi;
+  lF[F_PSI * nc + g] = z;
+  lF[F_RHO * nc + g] = z;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) lF[(F_A + l) * nc + g] = lA[l];
+}
+
+// E = -i k phi - U and B = i k x A of the present level, / ncell (inverse
+// transform inputs of the energy adjoint)
+__global__ __launch_bounds__(kBlock) void k_fields_EB(Grid G, const double2* cur, double2* EB) {
+  const int64_t nc = G.ncell;
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= nc) return;
+  double k[3];
+  mode_k(G, g, k);
+  const double sc = 1.0 / (double)nc;
+  const double2 phi = cur[F_PHI * nc + g];
+  double2 A[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    A[l] = cur[(F_A + l) * nc + g];
+    EB[l * nc + g] = cscale(csub(ik(-k[l], phi), cur[(F_U + l) * nc + g]), sc);
+  }
+  EB[3 * nc + g] = cscale(csub(ik(k[1], A[2]), ik(k[2], A[1])), sc);
+  EB[4 * nc + g] = cscale(csub(ik(k[2], A[0]), ik(k[0], A[2])), sc);
+  EB[5 * nc + g] = cscale(csub(ik(k[0], A[1]), ik(k[1], A[0])), sc);
+}
+
 }  // namespace
 
 void fft3_forward(hipStream_t s, const Grid& G, int nb, double2* data, const RealIO* in,
@@ -540,6 +658,23 @@ void launch_fill(hipStream_t s, int64_t count, double* p, double value) {
 
 void launch_reset_slots(hipStream_t s, double* red, int first, int count) {
   launch_fill(s, count, red + first, 0.0);
+}
+
+}  // namespace ecpic
+
+namespace ecpic {
+
+void launch_cn_adjoint(hipStream_t s, const FieldParams& F, const double2* l1, const double2* lg,
+                       double2* lcur, double2* lJh) {
+  k_cn_adjoint<<<blocks_for(F.G.ncell), kBlock, 0, s>>>(F, l1, lg, lcur, lJh);
+}
+
+void launch_energy_adjoint(hipStream_t s, const Grid& G, const double2* lEB, double2* lF) {
+  k_energy_adjoint<<<blocks_for(G.ncell), kBlock, 0, s>>>(G, lEB, lF);
+}
+
+void launch_fields_EB(hipStream_t s, const Grid& G, const double2* cur, double2* EB) {
+  k_fields_EB<<<blocks_for(G.ncell), kBlock, 0, s>>>(G, cur, EB);
 }
 
 }  // namespace ecpic

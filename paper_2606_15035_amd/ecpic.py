@@ -66,6 +66,10 @@ class Profile(C.Structure):
                 for i, name in enumerate(self.PHASES)} | {"pieces": self.pieces}
 
 
+class AdjointInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("err", C.c_double)]
+
+
 _lib = None
 
 
@@ -93,13 +97,18 @@ def lib():
         L.ecpic_orbit_deposit.argtypes = [cfgp, I64, D, D, D, D, P]
         L.ecpic_set_profiling.argtypes = [P, C.c_int32]
         L.ecpic_get_profile.argtypes = [P, C.POINTER(Profile)]
+        L.ecpic_adjoint_workspace_bytes.argtypes = [cfgp, I64, C.POINTER(C.c_size_t)]
+        L.ecpic_adjoint_step.argtypes = [P, P, C.c_size_t, D, D, D, D, D, D, D, D, D, D,
+                                         C.c_double, C.c_int32, C.POINTER(AdjointInfo)]
+        L.ecpic_field_energy_grad.argtypes = [P, D]
         L.ecpic_last_error.restype = C.c_char_p
         L.ecpic_version.restype = C.c_char_p
         for name in ("ecpic_state_bytes", "ecpic_create", "ecpic_init_particles",
                      "ecpic_picard_step", "ecpic_field_solve", "ecpic_energy_diagnostics",
                      "ecpic_get_state", "ecpic_set_state", "ecpic_get_current",
                      "ecpic_orbit_gather", "ecpic_orbit_deposit", "ecpic_set_profiling",
-                     "ecpic_get_profile"):
+                     "ecpic_get_profile", "ecpic_adjoint_workspace_bytes",
+                     "ecpic_adjoint_step", "ecpic_field_energy_grad"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -235,6 +244,47 @@ class Sim:
         J = np.zeros((3,) + self.n)
         _check(lib().ecpic_get_current(self._h, _hp(J)))
         return J
+
+    # -- adjoint ----------------------------------------------------------
+    def _dev(self, a, shape):
+        """float64 contiguous device tensor of the given shape (or None)."""
+        if a is None:
+            return None
+        torch = self.torch
+        t = torch.as_tensor(a, dtype=torch.float64, device=self.state.device)
+        return t.reshape(shape).contiguous()
+
+    def field_energy_grad(self):
+        """dW/dF of the present fields: device tensor (9,) + n."""
+        torch = self.torch
+        g = torch.empty((9,) + self.n, dtype=torch.float64, device=self.state.device)
+        _check(lib().ecpic_field_energy_grad(self._h, C.c_void_p(g.data_ptr())))
+        return g
+
+    def adjoint_step(self, x, v, w, F, lx1=None, lv1=None, lF1=None, tol=1e-13, max_iters=100):
+        """Adjoint of the converged step from (x, v, F) whose solution is w
+        (arrays or tensors; particles in the caller's order).  Returns device
+        tensors (lx0, lv0, lF0) and the iteration info."""
+        torch = self.torch
+        if getattr(self, "_adj_ws", None) is None:
+            nb = C.c_size_t()
+            _check(lib().ecpic_adjoint_workspace_bytes(C.byref(self.cfg), self.np, C.byref(nb)))
+            self._adj_ws = torch.empty(nb.value, dtype=torch.uint8, device=self.state.device)
+        p3, pf = (3, self.np), (9,) + self.n
+        x, v, w, lx1, lv1 = (self._dev(a, p3) for a in (x, v, w, lx1, lv1))
+        F, lF1 = self._dev(F, pf), self._dev(lF1, pf)
+        lx0 = torch.empty(p3, dtype=torch.float64, device=self.state.device)
+        lv0 = torch.empty(p3, dtype=torch.float64, device=self.state.device)
+        lF0 = torch.empty(pf, dtype=torch.float64, device=self.state.device)
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        info = AdjointInfo()
+        st = lib().ecpic_adjoint_step(self._h, C.c_void_p(self._adj_ws.data_ptr()),
+                                      self._adj_ws.numel(), ptr(x), ptr(v), ptr(w), ptr(F),
+                                      ptr(lx1), ptr(lv1), ptr(lF1), ptr(lx0), ptr(lv0), ptr(lF0),
+                                      float(tol), int(max_iters), C.byref(info))
+        _check(st, allow=(OK, ENOCONV))
+        return lx0, lv0, lF0, {"iters": info.iters, "converged": bool(info.converged),
+                               "err": info.err}
 
 
 def orbit_gather(cfg: Config, x0, d, gphi, U, A0, A1, device="cuda"):
