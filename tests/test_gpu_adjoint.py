@@ -105,3 +105,118 @@ def test_adjoint_rejects_unsupported_configurations():
     g = gpu_sim(wl, r=1)
     with pytest.raises(E.EcpicError):
         g.adjoint_step(wl.x, wl.v, wl.v, F)
+
+
+# --------------------------------------------------------------------------
+# multi-step gradients through torch.autograd
+# --------------------------------------------------------------------------
+def two_stream_params(name, amps, v0):
+    """Positions of workload `name` and velocities v_x = +-v0 + sum_m a_m sin(m k1 x)."""
+    base = W.two_stream(name)
+    x = base.x
+    sign = np.sign(base.v[0])
+    basis = np.stack([np.sin((m + 1) * W.K1 * x[0]) for m in range(len(amps))])
+    return base, x, sign, basis
+
+
+def torch_v0(torch, sign, basis, theta):
+    """v^0(theta) with theta = (a_1..a_M, v0), built in torch so that autograd
+    carries dW/dv^0 to theta."""
+    M = basis.shape[0]
+    b = torch.as_tensor(basis, dtype=torch.float64, device=theta.device)
+    sg = torch.as_tensor(sign, dtype=torch.float64, device=theta.device)
+    vx = sg * theta[M] + (theta[:M, None] * b).sum(0)
+    z = torch.zeros_like(vx)
+    return torch.stack([vx, z, z])
+
+
+def gpu_gradient(torch, name, amps, v0, steps, every, r=2, tol=1e-13):
+    from paper_2606_15035_amd import adjoint as AD
+    base, x, sign, basis = two_stream_params(name, amps, v0)
+    cfg = E.make_config(base.n, base.L, base.dt, r=r, tol=tol, pmax=40)
+    run = AD.Run(cfg=cfg, x0=x, q=base.q, m=base.m, steps=steps, checkpoint_every=every)
+    theta = torch.tensor(list(amps) + [v0], dtype=torch.float64, device="cuda",
+                         requires_grad=True)
+    Wk = AD.field_energy_after(torch_v0(torch, sign, basis, theta), run)
+    Wk.backward()
+    return float(Wk.detach()), theta.grad.cpu().numpy(), run
+
+
+def gpu_energy(torch, name, amps, v0, steps, r=2, tol=1e-13):
+    from paper_2606_15035_amd import adjoint as AD
+    base, x, sign, basis = two_stream_params(name, amps, v0)
+    cfg = E.make_config(base.n, base.L, base.dt, r=r, tol=tol, pmax=40)
+    run = AD.Run(cfg=cfg, x0=x, q=base.q, m=base.m, steps=steps, checkpoint_every=steps)
+    theta = torch.tensor(list(amps) + [v0], dtype=torch.float64, device="cuda")
+    return float(AD.field_energy_after(torch_v0(torch, sign, basis, theta), run))
+
+
+def oracle_gradient(name, amps, v0, steps, r=2):
+    base, x, sign, basis = two_stream_params(name, amps, v0)
+    v = np.zeros_like(x)
+    v[0] = sign * v0 + (np.asarray(amps)[:, None] * basis).sum(0)
+    o = O.OracleSim(O.make_cfg(base.n, base.L, base.dt, r=r, tol=0.0, pmax=30), x.shape[1])
+    o.init_particles(x, v, base.q, base.m, 1.0)
+    states = []
+    for _ in range(steps):
+        s = o.get_state()
+        states.append((s["x"], s["v"], s["fields"]))
+        o.step()
+    lF = o.field_energy_grad()
+    lx = lv = None
+    for k in range(steps - 1, -1, -1):
+        xk, vk, Fk = states[k]
+        w = states[k + 1][1] if k + 1 < steps else o.get_state()["v"]
+        lx, lv, lF, _ = o.adjoint_step(xk, vk, w, Fk, lx, lv, lF)
+    grad = [float(np.sum(lv[0] * b)) for b in basis] + [float(np.sum(lv[0] * sign))]
+    return o.energy()["W"], np.asarray(grad)
+
+
+def test_multi_step_gradient_matches_oracle_and_finite_differences(gpu):
+    """16x4x4 two-stream geometry with the quadratic shape, 6 steps,
+    checkpoints every 4 (a full and a partial segment): the GPU gradient of W^6
+    with respect to three mode amplitudes and the drift equals the oracle's
+    multi-step adjoint, and central finite differences of GPU runs."""
+    torch = gpu
+    amps, v0, steps = [1e-3, 5e-4, 2e-4], 0.1, 6
+    Wg, gg, run = gpu_gradient(torch, "c1", amps, v0, steps, every=4)
+    Wo, go = oracle_gradient("c1", amps, v0, steps)
+    log(f"W: GPU {Wg:.15e} oracle {Wo:.15e}; grad GPU {gg} oracle {go}")
+    assert abs(Wg - Wo) <= 1e-12 * abs(Wo)
+    assert np.abs(gg - go).max() <= 1e-10 * np.abs(go).max()
+    assert sum(1 for e in run.log if e[0] == "adj") == steps
+    h = 1e-7
+    for j in (0, 3):
+        tp, tm = list(amps) + [v0], list(amps) + [v0]
+        tp[j] += h
+        tm[j] -= h
+        fd = (gpu_energy(torch, "c1", tp[:3], tp[3], steps)
+              - gpu_energy(torch, "c1", tm[:3], tm[3], steps)) / (2 * h)
+        log(f"param {j}: adjoint {gg[j]:.10e} FD {fd:.10e}")
+        assert abs(fd - gg[j]) <= 1e-5 * abs(fd)
+
+
+@pytest.mark.slow
+def test_adjoint_workload_32cubed_gradient_vs_finite_differences(gpu):
+    """The adjoint workload: 32^3 mesh, 2,097,152 particles, quadratic shape,
+    50 steps (checkpoints every 10), Picard tolerance 1e-13; gradient of W^50
+    with respect to the 8 mode amplitudes and the drift, checked by central
+    finite differences (h = 1e-6) for the unstable mode's amplitude, a stable
+    one and the drift."""
+    torch = gpu
+    amps, v0, steps = [1e-3] * 8, 0.1, 50
+    import time
+    t = time.time()
+    Wg, gg, run = gpu_gradient(torch, "c5", amps, v0, steps, every=10)
+    log(f"W^50 = {Wg:.12e}; gradient {gg}; {time.time() - t:.1f} s; "
+        f"forward passes {sum(e[2] for e in run.log if e[0] == 'fwd')}, "
+        f"adjoint iterations {sum(e[2] for e in run.log if e[0] == 'adj')}")
+    h = 1e-6
+    for j in (0, 3, 8):
+        tp, tm = list(amps) + [v0], list(amps) + [v0]
+        tp[j] += h
+        tm[j] -= h
+        fd = (gpu_energy(torch, "c5", tp[:8], tp[8], steps)
+              - gpu_energy(torch, "c5", tm[:8], tm[8], steps)) / (2 * h)
+        log(f"param {j}: adjoint {gg[j]:.10e} FD {fd:.10e} rel {abs(fd - gg[j]) / abs(fd):.2e}")
+        assert abs(fd - gg[j]) <= 1e-5 * abs(fd)
