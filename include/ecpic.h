@@ -67,9 +67,14 @@ typedef struct {
   double picard_tol;            /* tau: stop when both fixed-point errors are below it (p >= 1) */
   int32_t picard_max;           /* p_max: iterations p = 0..p_max (at most p_max+1 passes) */
   int32_t split_orbit_at_knots; /* 1: split orbit integrals at every crossed knot (Sec. 4.7);
-                                   0: one Gauss rule over the whole orbit (comparison runs) */
-  int32_t quad_points;          /* Gauss points per piece; 0 = smallest exact rule
-                                   (2 n_q - 1 >= 3 r): 2 for r = 1, 4 for r = 2 */
+                                   0: one Gauss rule over the whole orbit, each point with the
+                                   stencil of its own cell (the paper's unsplit comparison
+                                   runs; FP64 only, no adjoint) */
+  int32_t quad_points;          /* Gauss-Legendre points, 0..16; 0 = smallest exact rule
+                                   (2 n_q - 1 >= 3 r): 2 for r = 1, 4 for r = 2.  Split pieces
+                                   are polynomial, so every rule with at least that many
+                                   points gives the same integrals and the smallest one is
+                                   used; without splitting the given rule is used as is */
   int32_t precision;            /* ecpic_precision */
   double fixed_point_scale;     /* mixed precision: current quantum is 1/fixed_point_scale of
                                    the per-particle charge unit (0 = 2^40) */

@@ -63,15 +63,52 @@ ecpic_status check_config(const ecpic_config* c, int64_t np) {
   if (c->picard_max < 0 || c->picard_max > 1000) return fail(ECPIC_EINVAL, "picard_max out of range");
   if (!(c->picard_tol >= 0.0)) return fail(ECPIC_EINVAL, "picard_tol must be >= 0");
   const int nq_min = c->spline_degree == 1 ? 2 : 4;
-  if (c->quad_points != 0 && c->quad_points != nq_min)
-    return fail(ECPIC_EINVAL, "quad_points: only the minimal exact rule (%d) is built", nq_min);
-  if (c->split_orbit_at_knots != 1)
-    return fail(ECPIC_EINVAL, "only split orbit integrals (split_orbit_at_knots = 1) are built");
+  if (c->split_orbit_at_knots != 0 && c->split_orbit_at_knots != 1)
+    return fail(ECPIC_EINVAL, "split_orbit_at_knots must be 0 or 1");
+  if (c->quad_points < 0 || c->quad_points > kMaxRule)
+    return fail(ECPIC_EINVAL, "quad_points must be in [0, %d]", kMaxRule);
+  if (c->split_orbit_at_knots == 1 && c->quad_points != 0 && c->quad_points < nq_min)
+    return fail(ECPIC_EINVAL, "quad_points: split pieces need at least %d points (2 n_q - 1 >= 3 r)",
+                nq_min);
+  if (c->split_orbit_at_knots == 0 && c->precision != ECPIC_FP64)
+    return fail(ECPIC_EINVAL, "unsplit orbit integrals are built for FP64 precision only");
   if (c->precision != ECPIC_FP64 && c->precision != ECPIC_MIXED)
     return fail(ECPIC_EINVAL, "precision must be ECPIC_FP64 or ECPIC_MIXED");
   if (!(c->fixed_point_scale >= 0.0) || c->fixed_point_scale > 0x1p52)
     return fail(ECPIC_EINVAL, "fixed_point_scale must be in [0, 2^52] (0 = 2^40)");
   return ECPIC_OK;
+}
+
+// Gauss-Legendre nodes and weights on [0, 1]: Newton iteration on the
+// Legendre polynomial P_n (three-term recurrence) from the Chebyshev-like
+// starting guesses cos(pi (i + 3/4) / (n + 1/2)).
+QuadRule gauss_rule01(int n) {
+  QuadRule R{};
+  R.n = n;
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) p1 = z, p0 = 1.0;
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    // node z on [-1, 1] with weight 2 / ((1 - z^2) P_n'(z)^2), mapped to [0, 1]
+    R.s[n - 1 - i] = 0.5 * (1.0 + z);
+    R.w[n - 1 - i] = 0.5 * 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  return R;
+}
+
+int quad_rule_points(const ecpic_config* c) {
+  return c->quad_points > 0 ? c->quad_points : (c->spline_degree == 1 ? 2 : 4);
 }
 
 int ilog2i(int n) {
@@ -154,7 +191,8 @@ struct ecpic_sim {
   double K = 0.0, W = 0.0;
   ecpic_energy en{};
   FieldParams fp() const { return FieldParams{G, cfg.dt, cfg.kappa, cfg.sigma1, cfg.sigma2}; }
-  StepParams pp() const { return StepParams{G, cfg.dt, q, m, np}; }
+  QuadRule rule{};  // rule of the unsplit comparison path
+  StepParams pp() const { return StepParams{G, cfg.dt, q, m, np, cfg.split_orbit_at_knots, rule}; }
 };
 
 namespace {
@@ -306,6 +344,7 @@ size_t carve_adjoint(const Grid& G, int64_t np, char* base, AdjWs* A) {
 ecpic_status check_adjoint_config(const ecpic_config* cfg) {
   if (cfg->precision != ECPIC_FP64) return fail(ECPIC_EINVAL, "adjoint: FP64 precision only");
   if (cfg->spline_degree != 2) return fail(ECPIC_EINVAL, "adjoint: spline_degree 2 only");
+  if (cfg->split_orbit_at_knots != 1) return fail(ECPIC_EINVAL, "adjoint: split orbits only");
   return ECPIC_OK;
 }
 
@@ -354,6 +393,7 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
   S->np = n_particles;
   S->stream = reinterpret_cast<hipStream_t>(hip_stream);
   S->fix_scale = cfg->fixed_point_scale > 0.0 ? cfg->fixed_point_scale : 0x1p40;
+  S->rule = gauss_rule01(quad_rule_points(cfg));
   carve(S, static_cast<char*>(state_dev), static_cast<char*>(workspace_dev), nullptr, nullptr);
   if (hipHostMalloc(reinterpret_cast<void**>(&S->host), sizeof(double) * S_NSLOTS,
                     hipHostMallocDefault) != hipSuccess) {
@@ -743,7 +783,9 @@ ecpic_status ecpic_orbit_gather(const ecpic_config* cfg, int64_t n, const double
   if (n > 0 && (!x0 || !d || !gphi || !U || !A0 || !A1 || !out))
     return fail(ECPIC_EINVAL, "null device pointer");
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  launch_orbit_gather_soa(s, cfg->spline_degree, make_grid(cfg), n, x0, d, gphi, U, A0, A1, out);
+  const QuadRule rule = gauss_rule01(quad_rule_points(cfg));
+  launch_orbit_gather_soa(s, cfg->spline_degree, cfg->split_orbit_at_knots ? nullptr : &rule,
+                          make_grid(cfg), n, x0, d, gphi, U, A0, A1, out);
   HIPCHK(hipGetLastError());
   return ECPIC_OK;
 }
@@ -754,7 +796,9 @@ ecpic_status ecpic_orbit_deposit(const ecpic_config* cfg, int64_t n, const doubl
   if (st != ECPIC_OK) return st;
   if (n > 0 && (!x0 || !d || !qv || !J)) return fail(ECPIC_EINVAL, "null device pointer");
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  launch_orbit_deposit_soa(s, cfg->spline_degree, make_grid(cfg), n, x0, d, qv, J);
+  const QuadRule rule = gauss_rule01(quad_rule_points(cfg));
+  launch_orbit_deposit_soa(s, cfg->spline_degree, cfg->split_orbit_at_knots ? nullptr : &rule,
+                           make_grid(cfg), n, x0, d, qv, J);
   HIPCHK(hipGetLastError());
   return ECPIC_OK;
 }

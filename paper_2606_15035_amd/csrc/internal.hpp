@@ -37,10 +37,21 @@ enum Slot : int {
 enum Site : int { P_JS = 0, P_CN, P_SWEEP, P_K, P_W, P_NORM, P_NSITES };
 constexpr int kMaxSumValues = 4;
 
+// Gauss-Legendre rule on [0, 1] for orbits integrated without splitting at
+// knots (comparison runs): n points s[q] with weights w[q] (sum 1).
+constexpr int kMaxRule = 16;
+struct QuadRule {
+  int n;
+  double s[kMaxRule];
+  double w[kMaxRule];
+};
+
 struct StepParams {
   Grid G;
   double dt, q, m;
   int64_t np;
+  int split;      // 1: split orbit integrals at knots; 0: one rule over the orbit
+  QuadRule rule;  // the rule of split = 0
 };
 
 struct Scratch {
@@ -104,11 +115,13 @@ void launch_export(hipStream_t s, const StepParams& P, const PS& st, int which, 
 // J = unit * Jfix (as signed integers), then Jfix = 0
 void launch_fixed_current(hipStream_t s, int64_t n, unsigned long long* Jfix, double* J,
                           double unit);
-void launch_orbit_gather_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
-                             const double* d, const double* gphi, const double* U,
-                             const double* A0, const double* A1, double* out);
-void launch_orbit_deposit_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
-                              const double* d, const double* qv, double* J);
+// kernel-level checks; rule = nullptr: split orbits, else that rule over [0, 1]
+void launch_orbit_gather_soa(hipStream_t s, int r, const QuadRule* rule, const Grid& G,
+                             int64_t n, const double* x0, const double* d, const double* gphi,
+                             const double* U, const double* A0, const double* A1, double* out);
+void launch_orbit_deposit_soa(hipStream_t s, int r, const QuadRule* rule, const Grid& G,
+                              int64_t n, const double* x0, const double* d, const double* qv,
+                              double* J);
 
 // ---- particle sort (sort.hip) ----
 struct SortScratch {

@@ -91,14 +91,13 @@ __device__ __forceinline__ int64_t node_of(const Grid& G, int ix, int iy, int iz
 // ---- one orbit piece: current scatter -------------------------------------
 // Iw[a][b][c] = int_{s0}^{s1} S_g(x(s)) ds for the stencil node first + (a, b, c)
 // (eq. split-Sbar); first is the unwrapped index of the piece's first stencil node.
-template <int R>
-__device__ __forceinline__ void piece_sbar(const Grid& G, const double* x0, const double* d,
-                                           double s0, double s1, double (&Iw)[R + 1][R + 1][R + 1],
-                                           int* first) {
-  constexpr int W = R + 1, NQ = Quad<R>::NQ;
-  const double h = s1 - s0;
-  double base[3];
-  piece_base<R>(x0, d, 0.5 * (s0 + s1), G, base);
+// NP quadrature points sq[] with weights wq[] against the stencil of base
+template <int R, int NP>
+__device__ __forceinline__ void sbar_points(const Grid& G, const double* x0, const double* d,
+                                            const double* base, const double* sq,
+                                            const double* wq,
+                                            double (&Iw)[R + 1][R + 1][R + 1], int* first) {
+  constexpr int W = R + 1;
 #pragma unroll
   for (int a = 0; a < W; ++a)
 #pragma unroll
@@ -106,9 +105,9 @@ __device__ __forceinline__ void piece_sbar(const Grid& G, const double* x0, cons
 #pragma unroll
       for (int c = 0; c < W; ++c) Iw[a][b][c] = 0.0;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const double s = s0 + 0.5 * h * (1.0 + Gauss<NQ>::x(q));
-    const double wt = 0.5 * h * Gauss<NQ>::w(q);
+  for (int q = 0; q < NP; ++q) {
+    const double s = sq[q];
+    const double wt = wq[q];
     double wx[W], wy[W], wz[W];
     Spline<R>::w((x0[0] + s * d[0]) * G.invH[0] - base[0], wx);
     Spline<R>::w((x0[1] + s * d[1]) * G.invH[1] - base[1], wy);
@@ -126,6 +125,42 @@ __device__ __forceinline__ void piece_sbar(const Grid& G, const double* x0, cons
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) first[a] = to_int_clamped(base[a]) + Spline<R>::first_off;
+}
+
+// the n_q-point rule of a piece [s0, s1] and the stencil of its midpoint
+template <int R>
+__device__ __forceinline__ void piece_rule(const Grid& G, const double* x0, const double* d,
+                                           double s0, double s1, double* base, double* sq,
+                                           double* wq) {
+  constexpr int NQ = Quad<R>::NQ;
+  const double h = s1 - s0;
+  piece_base<R>(x0, d, 0.5 * (s0 + s1), G, base);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    sq[q] = s0 + 0.5 * h * (1.0 + Gauss<NQ>::x(q));
+    wq[q] = 0.5 * h * Gauss<NQ>::w(q);
+  }
+}
+
+// point q of the rule over the whole orbit (no splitting): the stencil is
+// the one of x(s_q) itself (comparison runs)
+template <int R>
+__device__ __forceinline__ void unsplit_point(const Grid& G, const QuadRule& rule, int q,
+                                              const double* x0, const double* d, double* base,
+                                              double& s, double& w) {
+  s = rule.s[q];
+  w = rule.w[q];
+  piece_base<R>(x0, d, s, G, base);
+}
+
+template <int R>
+__device__ __forceinline__ void piece_sbar(const Grid& G, const double* x0, const double* d,
+                                           double s0, double s1, double (&Iw)[R + 1][R + 1][R + 1],
+                                           int* first) {
+  constexpr int NQ = Quad<R>::NQ;
+  double base[3], sq[NQ], wq[NQ];
+  piece_rule<R>(G, x0, d, s0, s1, base, sq, wq);
+  sbar_points<R, NQ>(G, x0, d, base, sq, wq, Iw, first);
 }
 
 // J_g += (q vbar / dV) int_{s0}^{s1} S_g(x(s)) ds straight into global memory
@@ -164,21 +199,19 @@ __device__ __forceinline__ void scatter_piece(const Grid& G, const double* x0, c
 // The n_q-point rule is evaluated once per piece; each stencil node then
 // accumulates its weight integrals over the quadrature points and is
 // contracted with the node's field values.
-template <int R, bool WITH_U, class Acc>
-__device__ __forceinline__ void gather_piece(const Grid& G, const double* x0, const double* d,
-                                             double s0, double s1, const Acc& acc,
-                                             const double* __restrict__ Uh, double* gp,
-                                             double (*D)[3], double* Ub, double& pou) {
-  constexpr int W = R + 1, NQ = Quad<R>::NQ;
-  const double h = s1 - s0;
-  double base[3];
-  piece_base<R>(x0, d, 0.5 * (s0 + s1), G, base);
+template <int R, int NQ, bool WITH_U, class Acc>
+__device__ __forceinline__ void gather_points(const Grid& G, const double* x0, const double* d,
+                                              const double* base, const double* sqs,
+                                              const double* wqs, const Acc& acc,
+                                              const double* __restrict__ Uh, double* gp,
+                                              double (*D)[3], double* Ub, double& pou) {
+  constexpr int W = R + 1;
   double X[NQ][W], dX[NQ][W], Y[NQ][W], dY[NQ][W];
   double Zw[NQ][W], Z0[NQ][W], Z1[NQ][W], dZ0[NQ][W], dZ1[NQ][W];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const double s = s0 + 0.5 * h * (1.0 + Gauss<NQ>::x(q));
-    const double wt = 0.5 * h * Gauss<NQ>::w(q);
+    const double s = sqs[q];
+    const double wt = wqs[q];
     const double w0 = wt * (1.0 - s), w1 = wt * s;
     double wz[W], dz[W];
     Spline<R>::wd((x0[0] + s * d[0]) * G.invH[0] - base[0], X[q], dX[q]);
@@ -245,6 +278,17 @@ __device__ __forceinline__ void gather_piece(const Grid& G, const double* x0, co
   }
 }
 
+template <int R, bool WITH_U, class Acc>
+__device__ __forceinline__ void gather_piece(const Grid& G, const double* x0, const double* d,
+                                             double s0, double s1, const Acc& acc,
+                                             const double* __restrict__ Uh, double* gp,
+                                             double (*D)[3], double* Ub, double& pou) {
+  constexpr int NQ = Quad<R>::NQ;
+  double base[3], sq[NQ], wq[NQ];
+  piece_rule<R>(G, x0, d, s0, s1, base, sq, wq);
+  gather_points<R, NQ, WITH_U>(G, x0, d, base, sq, wq, acc, Uh, gp, D, Ub, pou);
+}
+
 // ---- one orbit piece: gather for the push ----------------------------------
 // The push needs grad phi-bar and (D A)^T vbar only.  With b_g(s) = vbar . A_g(s),
 //   ((D A)^T vbar)_j = sum_g int b_g(s) d_j S_g(x(s)) ds,
@@ -254,20 +298,16 @@ __device__ __forceinline__ void gather_piece(const Grid& G, const double* x0, co
 // stencil the quadrature-point sums B_q = sum_c b_c(s_q) Z_c(q) and
 // B'_q = sum_c b_c(s_q) Z'_c(q) are formed first, and the x and y factors
 // multiply those column sums, not every node.
-template <int R, class Acc>
-__device__ __forceinline__ void push_piece(const Grid& G, const double* x0, const double* d,
-                                           double s0, double s1, const double* vb,
-                                           const Acc& acc, double* gp, double* dtv) {
-  constexpr int W = R + 1, NQ = Quad<R>::NQ;
-  const double h = s1 - s0;
-  double base[3];
-  piece_base<R>(x0, d, 0.5 * (s0 + s1), G, base);
-  double tx[NQ], ty[NQ], sq[NQ], wq[NQ], Z[NQ][W], dZ[NQ][W];
+template <int R, int NQ, class Acc>
+__device__ __forceinline__ void push_points(const Grid& G, const double* x0, const double* d,
+                                            const double* base, const double* sq,
+                                            const double* wq, const double* vb, const Acc& acc,
+                                            double* gp, double* dtv) {
+  constexpr int W = R + 1;
+  double tx[NQ], ty[NQ], Z[NQ][W], dZ[NQ][W];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const double s = s0 + 0.5 * h * (1.0 + Gauss<NQ>::x(q));
-    sq[q] = s;
-    wq[q] = 0.5 * h * Gauss<NQ>::w(q);
+    const double s = sq[q];
     tx[q] = (x0[0] + s * d[0]) * G.invH[0] - base[0];
     ty[q] = (x0[1] + s * d[1]) * G.invH[1] - base[1];
     Spline<R>::wd((x0[2] + s * d[2]) * G.invH[2] - base[2], Z[q], dZ[q]);
@@ -328,6 +368,16 @@ __device__ __forceinline__ void push_piece(const Grid& G, const double* x0, cons
       }
     }
   }
+}
+
+template <int R, class Acc>
+__device__ __forceinline__ void push_piece(const Grid& G, const double* x0, const double* d,
+                                           double s0, double s1, const double* vb,
+                                           const Acc& acc, double* gp, double* dtv) {
+  constexpr int NQ = Quad<R>::NQ;
+  double base[3], sq[NQ], wq[NQ];
+  piece_rule<R>(G, x0, d, s0, s1, base, sq, wq);
+  push_points<R, NQ>(G, x0, d, base, sq, wq, vb, acc, gp, dtv);
 }
 
 // point interpolant of A^n (which = 0) or A^{n+1} (which = 1) at x, whose
@@ -477,7 +527,7 @@ __device__ __forceinline__ unsigned long long quantize(double w, double scale) {
   return (unsigned long long)(long long)round(w * scale);
 }
 
-template <int R, class PS>
+template <int R, class PS, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
                                                    const double* __restrict__ vit,
                                                    CurrentOut out, Scratch sc) {
@@ -545,10 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
       const int raw = lo - s_ref[a];
       shift[a] = min_image(raw, P.G.n[a]) - raw;  // particle frame -> chunk frame
     }
-    const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
-      double Iw[W][W][W];
-      int f[3];
-      piece_sbar<R>(P.G, x0, d, s0, s1, Iw, f);
+    auto deposit = [&](const double (&Iw)[W][W][W], const int* f) {
       const int ox = f[0] - s_ref[0] + shift[0] - tlo[0];
       const int oy = f[1] - s_ref[1] + shift[1] - tlo[1];
       const int oz = f[2] - s_ref[2] + shift[2] - tlo[2];
@@ -589,7 +636,24 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
               }
             }
       }
-    });
+    };
+    bool ok = true;
+    if constexpr (SPLIT) {
+      ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
+        double Iw[W][W][W];
+        int f[3];
+        piece_sbar<R>(P.G, x0, d, s0, s1, Iw, f);
+        deposit(Iw, f);
+      });
+    } else {
+      for (int q = 0; q < P.rule.n; ++q) {
+        double base[3], sq, wq, Iw[W][W][W];
+        int f[3];
+        unsplit_point<R>(P.G, P.rule, q, x0, d, base, sq, wq);
+        sbar_points<R, 1>(P.G, x0, d, base, &sq, &wq, Iw, f);
+        deposit(Iw, f);
+      }
+    }
     if (!ok) bad = 1.0;
   }
   __syncthreads();
@@ -614,18 +678,27 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
 
 // Gather + push of one particle through accessor acc: grad phi-bar and
 // (D A)^T vbar over the orbit pieces, then P^{n+1,p} and v^{n+1,p+1}.
-template <int R, class Acc>
+template <int R, bool SPLIT, class Acc>
 __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& acc,
                                                 const double* x0, const double* d,
                                                 const double* vb, const double* va,
                                                 double* vn, double& npieces, double& bad) {
   double gp[3] = {0.0, 0.0, 0.0};
   double dtv[3] = {0.0, 0.0, 0.0};  // (D A)^T vbar
-  const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
-    push_piece<R>(P.G, x0, d, s0, s1, vb, acc, gp, dtv);
+  if constexpr (SPLIT) {
+    const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
+      push_piece<R>(P.G, x0, d, s0, s1, vb, acc, gp, dtv);
+      npieces += 1.0;
+    });
+    if (!ok) bad = 1.0;
+  } else {
+    for (int q = 0; q < P.rule.n; ++q) {
+      double base[3], sq, wq;
+      unsplit_point<R>(P.G, P.rule, q, x0, d, base, sq, wq);
+      push_points<R, 1>(P.G, x0, d, base, &sq, &wq, vb, acc, gp, dtv);
+    }
     npieces += 1.0;
-  });
-  if (!ok) bad = 1.0;
+  }
   // A_h^n(x^n) rebuilds P^n = m v^n + q A_h^n(x^n) (eq. discrete-canonical-relation);
   // A_h^{n+1}(x^{n+1}) at the wrapped end point closes the velocity (eq. orbit-v-update).
   double x1[3], A0s[3], A1e[3];
@@ -654,7 +727,7 @@ __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& 
 // buffer in global memory.  Two kernels keep each one's register budget.
 constexpr int kGatherTileNodes = 512;
 
-template <int R, bool TILED, class PS>
+template <int R, bool TILED, class PS, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
                                                        const double* __restrict__ vit,
                                                        double* __restrict__ vnew, AosFields F,
@@ -734,12 +807,12 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
       acc.oz = shift[2] - s_ref[2] - tlo[2];
       acc.dy = dim[1];
       acc.dz = dim[2];
-      gather_push_one<R>(P, acc, x0, d, vb, va, vn, npieces[0], bad);
+      gather_push_one<R, SPLIT>(P, acc, x0, d, vb, va, vn, npieces[0], bad);
     }
   } else {
     if (active) {
       GlobalGather acc{F.g, P.G.mask[0], P.G.mask[1], P.G.mask[2], P.G.shx, P.G.shy};
-      gather_push_one<R>(P, acc, x0, d, vb, va, vn, npieces[0], bad);
+      gather_push_one<R, SPLIT>(P, acc, x0, d, vb, va, vn, npieces[0], bad);
     }
   }
   if (active) {
@@ -761,7 +834,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
 // Consistency sweep of the accepted iterate: Ubar, Ebar = -gphibar - Ubar,
 // sum_i q vbar . Ebar, R_A = A_h^{n+1}(x^{n+1}) - A_h^n(x^n) - dt (Ubar + D vbar)
 // (eq. RA-test) and the partition of unity sum_g Sbar_g.
-template <int R, class PS>
+template <int R, class PS, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, PS st,
                                                  const double* __restrict__ vit, AosFields F,
                                                  const double* __restrict__ Uh, Scratch sc) {
@@ -781,9 +854,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, PS st,
     double gp[3] = {0.0, 0.0, 0.0}, Ub[3] = {0.0, 0.0, 0.0};
     double D[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     double pou = 0.0;
-    for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
-      gather_piece<R, true>(P.G, x0, d, s0, s1, F, Uh, gp, D, Ub, pou);
-    });
+    if constexpr (SPLIT) {
+      for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
+        gather_piece<R, true>(P.G, x0, d, s0, s1, F, Uh, gp, D, Ub, pou);
+      });
+    } else {
+      for (int q = 0; q < P.rule.n; ++q) {
+        double base[3], sq, wq;
+        unsplit_point<R>(P.G, P.rule, q, x0, d, base, sq, wq);
+        gather_points<R, 1, true>(P.G, x0, d, base, &sq, &wq, F, Uh, gp, D, Ub, pou);
+      }
+    }
     double x1[3], A0s[3], A1e[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], P.G.L[a], P.G.invL[a]);
@@ -925,8 +1006,8 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rho(StepParams P, PS st, Cur
 }
 
 // Orbit integrals of independent particles against SoA fields (kernel-level check).
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_orbit_gather_soa(Grid G, int64_t n,
+template <int R, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_orbit_gather_soa(QuadRule rule, Grid G, int64_t n,
                                                             const double* __restrict__ x0s,
                                                             const double* __restrict__ ds,
                                                             SoaFields F,
@@ -941,10 +1022,20 @@ __global__ __launch_bounds__(kBlock) void k_orbit_gather_soa(Grid G, int64_t n,
   double D[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   double pou = 0.0;
   int pieces = 0;
-  const bool ok = for_each_piece<R>(x0, d, G, [&](double s0, double s1) {
-    gather_piece<R, true>(G, x0, d, s0, s1, F, Uh, gp, D, Ub, pou);
-    ++pieces;
-  });
+  bool ok = true;
+  if constexpr (SPLIT) {
+    ok = for_each_piece<R>(x0, d, G, [&](double s0, double s1) {
+      gather_piece<R, true>(G, x0, d, s0, s1, F, Uh, gp, D, Ub, pou);
+      ++pieces;
+    });
+  } else {
+    for (int q = 0; q < rule.n; ++q) {
+      double base[3], sq, wq;
+      unsplit_point<R>(G, rule, q, x0, d, base, sq, wq);
+      gather_points<R, 1, true>(G, x0, d, base, &sq, &wq, F, Uh, gp, D, Ub, pou);
+    }
+    pieces = rule.n;
+  }
   double x1[3], A0s[3], A1e[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) x1[a] = wrap_pos(x0[a] + d[a], G.L[a], G.invL[a]);
@@ -965,8 +1056,8 @@ __global__ __launch_bounds__(kBlock) void k_orbit_gather_soa(Grid G, int64_t n,
   o[23] = 0.0;
 }
 
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_orbit_deposit_soa(Grid G, int64_t n,
+template <int R, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_orbit_deposit_soa(QuadRule rule, Grid G, int64_t n,
                                                              const double* __restrict__ x0s,
                                                              const double* __restrict__ ds,
                                                              const double* __restrict__ qv,
@@ -979,9 +1070,26 @@ __global__ __launch_bounds__(kBlock) void k_orbit_deposit_soa(Grid G, int64_t n,
   load3(qv, n, i, c3);
 #pragma unroll
   for (int a = 0; a < 3; ++a) c3[a] /= G.dV;
-  for_each_piece<R>(x0, d, G, [&](double s0, double s1) {
-    scatter_piece<R>(G, x0, d, s0, s1, c3, J);
-  });
+  if constexpr (SPLIT) {
+    for_each_piece<R>(x0, d, G, [&](double s0, double s1) {
+      scatter_piece<R>(G, x0, d, s0, s1, c3, J);
+    });
+  } else {
+    constexpr int W = R + 1;
+    for (int q = 0; q < rule.n; ++q) {
+      double base[3], sq, wq, Iw[W][W][W];
+      int f[3];
+      unsplit_point<R>(G, rule, q, x0, d, base, sq, wq);
+      sbar_points<R, 1>(G, x0, d, base, &sq, &wq, Iw, f);
+      for (int a = 0; a < W; ++a)
+        for (int b = 0; b < W; ++b)
+          for (int c = 0; c < W; ++c) {
+            const int64_t g = node_index(G, f[0] + a, f[1] + b, f[2] + c);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) unsafeAtomicAdd(J + l * G.ncell + g, Iw[a][b][c] * c3[l]);
+          }
+    }
+  }
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -1004,10 +1112,19 @@ void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, con
                     CurrentOut out, Scratch sc) {
   if (P.np <= 0) return;
   const unsigned nblk = (unsigned)((P.np + kChunk - 1) / kChunk);
+  if constexpr (!PS::kMixed) {
+    if (!P.split) {
+      if (r == 1)
+        k_scatter<1, PS, false><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+      else
+        k_scatter<2, PS, false><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+      return;
+    }
+  }
   if (r == 1)
-    k_scatter<1, PS><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+    k_scatter<1, PS, true><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
   else
-    k_scatter<2, PS><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+    k_scatter<2, PS, true><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
 }
 
 template <class PS>
@@ -1017,12 +1134,24 @@ void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
   if (P.np <= 0) return;
   AosFields F{gbuf};
   const unsigned nb = blocks_for(P.np);
+  if constexpr (!PS::kMixed) {
+    if (!P.split) {
+      if (r == 1) {
+        k_gather_push<1, true, PS, false><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+        k_gather_push<1, false, PS, false><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+      } else {
+        k_gather_push<2, true, PS, false><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+        k_gather_push<2, false, PS, false><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+      }
+      return;
+    }
+  }
   if (r == 1) {
-    k_gather_push<1, true, PS><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
-    k_gather_push<1, false, PS><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+    k_gather_push<1, true, PS, true><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+    k_gather_push<1, false, PS, true><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
   } else {
-    k_gather_push<2, true, PS><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
-    k_gather_push<2, false, PS><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+    k_gather_push<2, true, PS, true><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+    k_gather_push<2, false, PS, true><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
   }
 }
 
@@ -1031,10 +1160,19 @@ void launch_sweep(hipStream_t s, int r, const StepParams& P, const PS& st, const
                   const double* gbuf, const double* Uhalf, Scratch sc) {
   if (P.np <= 0) return;
   AosFields F{gbuf};
+  if constexpr (!PS::kMixed) {
+    if (!P.split) {
+      if (r == 1)
+        k_sweep<1, PS, false><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
+      else
+        k_sweep<2, PS, false><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
+      return;
+    }
+  }
   if (r == 1)
-    k_sweep<1, PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
+    k_sweep<1, PS, true><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
   else
-    k_sweep<2, PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
+    k_sweep<2, PS, true><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
 }
 
 template <class PS>
@@ -1097,24 +1235,43 @@ ECPIC_INSTANTIATE_STORE(Fp64Store)
 ECPIC_INSTANTIATE_STORE(MixedStore)
 #undef ECPIC_INSTANTIATE_STORE
 
-void launch_orbit_gather_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
-                             const double* d, const double* gphi, const double* U,
-                             const double* A0, const double* A1, double* out) {
+void launch_orbit_gather_soa(hipStream_t s, int r, const QuadRule* rule, const Grid& G,
+                             int64_t n, const double* x0, const double* d, const double* gphi,
+                             const double* U, const double* A0, const double* A1, double* out) {
   if (n <= 0) return;
   SoaFields F{gphi, A0, A1, G.ncell};
-  if (r == 1)
-    k_orbit_gather_soa<1><<<blocks_for(n), kBlock, 0, s>>>(G, n, x0, d, F, U, out);
-  else
-    k_orbit_gather_soa<2><<<blocks_for(n), kBlock, 0, s>>>(G, n, x0, d, F, U, out);
+  const QuadRule ru = rule ? *rule : QuadRule{};
+  const unsigned nb = blocks_for(n);
+  if (rule) {
+    if (r == 1)
+      k_orbit_gather_soa<1, false><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, F, U, out);
+    else
+      k_orbit_gather_soa<2, false><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, F, U, out);
+  } else {
+    if (r == 1)
+      k_orbit_gather_soa<1, true><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, F, U, out);
+    else
+      k_orbit_gather_soa<2, true><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, F, U, out);
+  }
 }
 
-void launch_orbit_deposit_soa(hipStream_t s, int r, const Grid& G, int64_t n, const double* x0,
-                              const double* d, const double* qv, double* J) {
+void launch_orbit_deposit_soa(hipStream_t s, int r, const QuadRule* rule, const Grid& G,
+                              int64_t n, const double* x0, const double* d, const double* qv,
+                              double* J) {
   if (n <= 0) return;
-  if (r == 1)
-    k_orbit_deposit_soa<1><<<blocks_for(n), kBlock, 0, s>>>(G, n, x0, d, qv, J);
-  else
-    k_orbit_deposit_soa<2><<<blocks_for(n), kBlock, 0, s>>>(G, n, x0, d, qv, J);
+  const QuadRule ru = rule ? *rule : QuadRule{};
+  const unsigned nb = blocks_for(n);
+  if (rule) {
+    if (r == 1)
+      k_orbit_deposit_soa<1, false><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, qv, J);
+    else
+      k_orbit_deposit_soa<2, false><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, qv, J);
+  } else {
+    if (r == 1)
+      k_orbit_deposit_soa<1, true><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, qv, J);
+    else
+      k_orbit_deposit_soa<2, true><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, qv, J);
+  }
 }
 
 }  // namespace ecpic

@@ -159,6 +159,30 @@ def two_stream(name: str) -> Workload:
                     precision=prec, x=x, v=v, q=q, m=m, description=desc)
 
 
+def paper_two_stream(steps: int = 1200) -> Workload:
+    """The paper's own demonstration run (Sec. 5.4): 16^3 mesh on
+    [0, 2 pi]^3, 16 particles per cell per beam on the cell-centred x lattice
+    with both beams at identical positions (131,072 particles), drift
+    v0 = 0.3, v_x = +-v0 + 0.02 sin(x) on both beams (k = 2 pi m / L_x, m = 1),
+    v_y = v_z = 0, linear shape, dt = 0.025 for 1200 steps (T = 30), Picard
+    tolerance 1e-11 and p_max = 16.  The paper's Gauss rule has 16 points per
+    piece (identical to the closed forms when the orbit is split)."""
+    n = (16, 16, 16)
+    L = (2.0 * math.pi,) * 3
+    k = 16
+    pos = _quiet_x_lattice(n, L, k)
+    ncell = int(np.prod(n))
+    p3 = np.broadcast_to(pos.reshape(3, ncell, 1, k), (3, ncell, 2, k))
+    x = np.ascontiguousarray(p3.reshape(3, -1))
+    sign = np.broadcast_to(np.array([1.0, -1.0]).reshape(1, 2, 1), (ncell, 2, k)).reshape(-1)
+    v = np.zeros_like(x)
+    v[0] = sign * 0.3 + 0.02 * np.sin(x[0])
+    q, m = _species(1.0, L, x.shape[1])
+    return Workload(name="paper", n=n, L=L, dt=0.025, steps=steps, r=1, tol=1e-11, pmax=16,
+                    precision="fp64", x=x, v=v, q=q, m=m,
+                    description="paper's cold two-stream 16^3, L = 2 pi, v0 = 0.3, 131072 particles")
+
+
 def random_plasma(n, L, np_, r, dt, vth, drift=(0.0, 0.0, 0.0), seed=SEED, tol=1e-12,
                   pmax=16, name="random") -> Workload:
     """Uniform random positions and Maxwellian velocities (for parity cases

@@ -64,6 +64,9 @@ def test_state_bytes_scale_with_particles(lib):
     dict(pmax=-1),
     dict(tol=-1.0),
     dict(precision=2),                    # no such precision
+    dict(quad_points=17),                 # beyond the largest rule
+    dict(quad_points=3),                  # split quadratic pieces need 4 points
+    dict(split=False, precision=1),       # unsplit comparison path is FP64 only
 ])
 def test_invalid_configurations_are_rejected(lib, bad):
     with pytest.raises(E.EcpicError) as ei:
@@ -84,6 +87,12 @@ def test_mixed_precision_state_is_smaller(lib):
 def test_fixed_point_scale_range(lib, scale):
     with pytest.raises(E.EcpicError):
         E.state_bytes(good_cfg(precision=E.MIXED, fixed_point_scale=scale), 10)
+
+
+@pytest.mark.parametrize("ok", [dict(split=False), dict(split=False, quad_points=16),
+                                dict(split=False, quad_points=1), dict(quad_points=16)])
+def test_unsplit_and_larger_rules_accepted(lib, ok):
+    E.state_bytes(good_cfg(**ok), 10)
 
 
 def test_maxwell_scaling_accepted_when_consistent(lib):

@@ -155,6 +155,41 @@ def test_kernel_orbit_deposit_matches_oracle(r):
     assert err <= 1e-13 * scale
 
 
+@pytest.mark.parametrize("r,nq", [(1, 0), (1, 16), (2, 0), (2, 7)])
+def test_kernel_unsplit_orbit_integrals_match_oracle(r, nq):
+    """The unsplit comparison path: one Gauss rule over the whole orbit, each
+    point with the stencil of its own cell."""
+    rng = np.random.default_rng(300 + 10 * r + nq)
+    x0, d = rand_orbits(rng, 2000)
+    A0, A1, gphi, U = (W.random_fields(N, 3, seed=s) for s in (5, 6, 7, 8))
+    qv = rng.normal(size=(2000, 3))
+    cfg = E.make_config(N, LB, 0.1, r=r, split=False, quad_points=nq)
+    o = O.OracleSim(O.make_cfg(n=N, L=LB, dt=0.1, r=r, split=False, nq=nq), 1)
+    got = E.orbit_gather(cfg, x0, d, gphi, U, A0, A1)
+    ref = o.orbit_gather(x0, d, gphi, U, A0, A1)
+    np.testing.assert_array_equal(got["npieces"], ref["npieces"])
+    for k, scale in (("gphibar", np.abs(gphi).max()), ("Ubar", np.abs(U).max()),
+                     ("D", np.abs(ref["D"]).max()), ("pou", 1.0)):
+        err = np.abs(got[k] - ref[k]).max()
+        assert err <= 1e-13 * scale, (k, err, scale)
+    Jg, Jo = E.orbit_deposit(cfg, x0, d, qv), o.orbit_deposit(x0, d, qv)
+    assert np.abs(Jg - Jo).max() <= 1e-13 * np.abs(Jo).max()
+
+
+@pytest.mark.parametrize("r,nq", [(1, 16), (2, 0)])
+def test_unsplit_step_parity_fixed_iterations(r, nq):
+    wl = small_random(r)
+    g = E.Sim(gpu_cfg(wl, tol=0.0, pmax=3, split=False, quad_points=nq), wl.np)
+    g.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
+    args = wl.cfg_kwargs()
+    args.update(tol=0.0, pmax=3, split=False, nq=nq)
+    o = O.OracleSim(O.make_cfg(**args), wl.np)
+    o.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
+    for step in range(2):
+        assert g.picard_step()["iters"] == o.step()["iters"] == 4
+        compare_states(wl, g, o, f"unsplit r={r} nq={nq} step {step}")
+
+
 # --------------------------------------------------------------------------
 # whole steps
 # --------------------------------------------------------------------------
