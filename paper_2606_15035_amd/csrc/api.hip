@@ -244,6 +244,7 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->gflags = w.take<int>(particle_blocks(np) > 0 ? particle_blocks(np) : 1);
   if (S->mixed()) S->Jfix = w.take<unsigned long long>(3 * nc);
   S->sc.red = w.take<double>(S_NSLOTS);
+  S->sc.spread = w.take<double>((size_t)S_NSLOTS * kSpread * kSpreadStride);
   const int64_t maxblk = std::max<int64_t>(
       std::max<int64_t>(particle_blocks(np), scatter_blocks(np)), mesh_blocks(nc));
   S->sc.part_stride = (int64_t)kMaxSumValues * (maxblk > 0 ? maxblk : 1);
@@ -417,6 +418,8 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
     }
   }
   if (hipMemsetAsync(S->sc.red, 0, sizeof(double) * S_NSLOTS, S->stream) != hipSuccess ||
+      hipMemsetAsync(S->sc.spread, 0, sizeof(double) * S_NSLOTS * kSpread * kSpreadStride,
+                     S->stream) != hipSuccess ||
       hipMemsetAsync(S->gflags, 0, sizeof(int) * std::max<int64_t>(particle_blocks(n_particles), 1),
                      S->stream) != hipSuccess ||
       (S->Jfix && hipMemsetAsync(S->Jfix, 0, sizeof(unsigned long long) * 3 * S->G.ncell,
@@ -504,14 +507,14 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   on_store(S, [&](auto& st, auto&) { launch_extrapolate(s, S->np, st, S->vit); });
   const CurrentOut cout{nullptr, S->Jfix, S->fix_scale};
   const double fix_unit = S->q / S->G.dV / S->fix_scale;
-  launch_reset_slots(s, S->sc.red, S_PIECES, 1);
+  launch_reset_slots(s, S->sc, S_PIECES, 1);
   int p = 0, jcur = 1 - S->jlast;
   bool converged = false;
   double err_v = 0.0, err_J = INFINITY;
   for (p = 0; p <= S->cfg.picard_max; ++p) {
     double* J = S->Jb[jcur];
     double* Jprev = S->Jb[1 - jcur];
-    launch_reset_slots(s, S->sc.red, S_DVMAX, 5);  // DVMAX, VMAX, DJMAX, JS, BAD
+    launch_reset_slots(s, S->sc, S_DVMAX, 5);  // DVMAX, VMAX, DJMAX, JS, BAD
     if (!S->mixed()) launch_fill(s, 3 * nc, J, 0.0);
     if (prof) HIPCHK(hipEventRecord(S->ev[0], s));
     on_store(S, [&](auto& st, auto&) {  // J^{n+1/2,p}
@@ -531,9 +534,12 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     });
     if (prof) HIPCHK(hipEventRecord(S->ev[3], s));
     {
-      const FinishJob jobs[2] = {{P_JS, (int)scatter_blocks(S->np), 1, S_JS},
-                                 {P_CN, (int)mesh_blocks(nc), 3, S_JE}};
-      launch_finish(s, S->sc, S->np > 0 ? jobs : jobs + 1, S->np > 0 ? 2 : 1);
+      const FinishJob jobs[5] = {{P_CN, (int)mesh_blocks(nc), 3, S_JE},
+                                 {P_JS, (int)scatter_blocks(S->np), 1, S_JS},
+                                 {0, 0, 2, S_DVMAX, F_SPREAD_MAX},
+                                 {0, 0, 1, S_BAD, F_SPREAD_MAX},
+                                 {0, 0, 1, S_PIECES, F_SPREAD_SUM}};
+      launch_finish(s, S->sc, jobs, S->np > 0 ? 5 : 1);
     }
     HIPCHK(hipGetLastError());
     ecpic_status st = sync_read(S, S_DVMAX, 5);
@@ -573,7 +579,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   // consistency sweep of the accepted iterate (its orbit, current and fields)
   if (prof) HIPCHK(hipEventRecord(S->ev[0], s));
   if (S->cfg.diagnostics) {
-    launch_reset_slots(s, S->sc.red, S_RAMAX, 2);
+    launch_reset_slots(s, S->sc, S_RAMAX, 2);
     launch_half_U(s, S->G, cur, nxt, S->batch);
     RealIO uo = soa_io(S->Uhalf, nc, 3);
     fft3_inverse(s, S->G, 3, S->batch, &uo, twp(S));
@@ -585,8 +591,8 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   // accept: x^{n+1} = x^n + dt vbar^p, v^{n-1} <- v^n, v^n <- v^{n+1,p+1}; fields of pass p
   on_store(S, [&](auto& st, auto&) { launch_finalize(s, P, st, S->vit, S->vnew, S->sc); });
   if (S->np <= 0) {
-    launch_reset_slots(s, S->sc.red, S_K, 2);
-    launch_reset_slots(s, S->sc.red, S_WORK, 2);
+    launch_reset_slots(s, S->sc, S_K, 2);
+    launch_reset_slots(s, S->sc, S_WORK, 2);
   }
   launch_accept_A(s, nc, S->gbuf);
   if (S->np > 0) {
@@ -677,7 +683,7 @@ ecpic_status ecpic_energy_diagnostics(ecpic_sim* S, ecpic_energy* out) {
   if (!S->initialized) return fail(ECPIC_ESTATE, "diagnostics before init_particles/set_state");
   const int64_t nc = S->G.ncell;
   hipStream_t s = S->stream;
-  launch_reset_slots(s, S->sc.red, S_GMAX, 2);
+  launch_reset_slots(s, S->sc, S_GMAX, 2);
   launch_constraint_spectra(s, S->fp(), S->spec[S->cur], S->batch, S->sc);
   RealIO o = soa_io(S->realbuf, nc, 2);
   fft3_inverse(s, S->G, 2, S->batch, &o, twp(S));
@@ -861,7 +867,7 @@ ecpic_status ecpic_adjoint_step(ecpic_sim* S, void* workspace, size_t workspace_
   // grad_h phi^{n+1/2} and A^{n+1} (A^n is the fields' A rows)
   launch_vbar(s, n3, w, v, A.vb);
   launch_fill(s, 3 * nc, A.J, 0.0);
-  launch_reset_slots(s, S->sc.red, S_BAD, 1);
+  launch_reset_slots(s, S->sc, S_BAD, 1);
   {
     Fp64Store view{const_cast<double*>(x), const_cast<double*>(v), nullptr};
     launch_scatter(s, 2, P, view, w, CurrentOut{A.J, nullptr, 0.0}, S->sc);
@@ -965,6 +971,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.4"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.5"; }
 
 }  // extern "C"

@@ -54,18 +54,35 @@ struct StepParams {
   QuadRule rule;  // the rule of split = 0
 };
 
+// Slots that many blocks of a kernel update with atomics (maxima, exact
+// integer counts) get kSpread copies, one 128-byte line apart, so that the
+// atomics of different blocks rarely meet on one address; a block uses copy
+// blockIdx.x % kSpread and k_finish folds the copies into the slot.
+constexpr int kSpread = 64;
+constexpr int kSpreadStride = 16;
+
 struct Scratch {
   double* red;          // S_NSLOTS
   double* part;         // P_NSITES regions of part_stride doubles
   int64_t part_stride;  // kMaxSumValues * (largest grid of a producing kernel)
+  double* spread;       // S_NSLOTS x kSpread copies, kSpreadStride doubles apart
   __host__ __device__ double* region(int site) const { return part + site * part_stride; }
+  __device__ double* spread_copy(int slot) const {
+    return spread + ((size_t)slot * kSpread + blockIdx.x % kSpread) * kSpreadStride;
+  }
 };
 
-// One row reduction for the finishing kernel: M values of site `site`, each
-// over nb block partials, into red[slot .. slot + M).
+// One row reduction for the finishing kernel: rows row0 .. row0 + M - 1 of
+// site `site`, each over nb partials, into red[slot .. slot + M).
+// F_SUM: set the slot to the sum of the partial row; F_SPREAD_MAX / F_SPREAD_SUM:
+// set the slot to the max / sum of its kSpread copies (site, nb, row0 unused)
+enum FinishOp : int { F_SUM = 0, F_SPREAD_MAX = 1, F_SPREAD_SUM = 2 };
 struct FinishJob {
   int site, nb, M, slot;
+  int op = F_SUM;
+  int row0 = 0;
 };
+constexpr int kMaxFinishJobs = 8;
 void launch_finish(hipStream_t s, Scratch sc, const FinishJob* jobs, int njobs);
 // grid sizes of the producing kernels
 int64_t scatter_blocks(int64_t np);
@@ -186,7 +203,8 @@ void launch_accept_A(hipStream_t s, int64_t ncell, double* gbuf);
 // gbuf A0 slots <- real A (3 x ncell)
 void launch_set_A0(hipStream_t s, int64_t ncell, const double* A, double* gbuf);
 void launch_fill(hipStream_t s, int64_t count, double* p, double value);
-void launch_reset_slots(hipStream_t s, double* red, int first, int count);
+// zero slots first .. first + count - 1 and their spread copies
+void launch_reset_slots(hipStream_t s, const Scratch& sc, int first, int count);
 
 // ---- adjoint (adjoint.hip, mesh.hip) ----
 struct AdjParticleArgs {

@@ -373,23 +373,48 @@ __global__ __launch_bounds__(kBlock) void k_norms(int64_t nc, const double* gf, 
 
 struct FinishArgs {
   Scratch sc;
-  FinishJob job[4];
+  FinishJob job[kMaxFinishJobs];
   int njobs;
 };
 
-// One block: each requested row of block partials summed in a fixed order.
+// One block: each requested row of block partials summed in a fixed order,
+// or a spread slot's copies folded by max or sum.
 __global__ __launch_bounds__(kBlock) void k_finish(FinishArgs F) {
   for (int j = 0; j < F.njobs; ++j) {
     const FinishJob jb = F.job[j];
-    const double* region = F.sc.region(jb.site);
     for (int m = 0; m < jb.M; ++m) {
-      double acc[1] = {0.0};
+      double* slot = F.sc.red + jb.slot + m;
+      if (jb.op == F_SUM) {
+        const double* row = F.sc.region(jb.site) + (size_t)(jb.row0 + m) * jb.nb;
+        double acc[1] = {0.0};
 #pragma unroll 8
-      for (int b = threadIdx.x; b < jb.nb; b += kBlock) acc[0] += region[(size_t)m * jb.nb + b];
-      block_sum<1>(acc);
-      if (threadIdx.x == 0) F.sc.red[jb.slot + m] = acc[0];
+        for (int b = threadIdx.x; b < jb.nb; b += kBlock) acc[0] += row[b];
+        block_sum<1>(acc);
+        if (threadIdx.x == 0) *slot = acc[0];
+      } else {
+        const double* cp = F.sc.spread + (size_t)(jb.slot + m) * kSpread * kSpreadStride;
+        const double c = threadIdx.x < kSpread ? cp[(size_t)threadIdx.x * kSpreadStride] : 0.0;
+        if (jb.op == F_SPREAD_MAX) {
+          const double r = block_max(c);
+          if (threadIdx.x == 0) *slot = r;
+        } else {
+          double acc[1] = {c};
+          block_sum<1>(acc);
+          if (threadIdx.x == 0) *slot = acc[0];
+        }
+      }
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reset_slots(Scratch sc, int first, int count) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= count * (kSpread + 1)) return;
+  const int j = i / (kSpread + 1), c = i % (kSpread + 1);
+  if (c == kSpread)
+    sc.red[first + j] = 0.0;
+  else
+    sc.spread[((size_t)(first + j) * kSpread + c) * kSpreadStride] = 0.0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_spec_copy(int64_t n, const double2* src, double2* dst,
@@ -644,7 +669,7 @@ void launch_set_A0(hipStream_t s, int64_t ncell, const double* A, double* gbuf) 
 void launch_finish(hipStream_t s, Scratch sc, const FinishJob* jobs, int njobs) {
   FinishArgs F;
   F.sc = sc;
-  F.njobs = njobs < 4 ? njobs : 4;
+  F.njobs = njobs < kMaxFinishJobs ? njobs : kMaxFinishJobs;
   for (int j = 0; j < F.njobs; ++j) F.job[j] = jobs[j];
   if (F.njobs > 0) k_finish<<<1, kBlock, 0, s>>>(F);
 }
@@ -656,8 +681,9 @@ void launch_fill(hipStream_t s, int64_t count, double* p, double value) {
   k_fill<<<blocks_for(count), kBlock, 0, s>>>(count, p, value);
 }
 
-void launch_reset_slots(hipStream_t s, double* red, int first, int count) {
-  launch_fill(s, count, red + first, 0.0);
+void launch_reset_slots(hipStream_t s, const Scratch& sc, int first, int count) {
+  if (count <= 0) return;
+  k_reset_slots<<<blocks_for((int64_t)count * (kSpread + 1)), kBlock, 0, s>>>(sc, first, count);
 }
 
 }  // namespace ecpic

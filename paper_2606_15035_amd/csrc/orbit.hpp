@@ -150,40 +150,30 @@ struct Gauss<4> {
 };
 
 // Streaming merge of the three per-axis knot-crossing sequences of an orbit.
+// Along axis a the crossings are equally spaced in s, H_a / |d_a| apart: the
+// first one is found from its knot, the later ones by adding that spacing
+// (a few ulp from the quotient of each knot; pieces only need their midpoint
+// inside the right cell, so the ends may move by that much).
 template <int R>
 struct Crossings {
-  double sn[3];   // next crossing parameter per axis (>= 2 when exhausted)
-  double knot[3]; // cell coordinate of that knot
-  double dir[3];
-  double x0[3], d[3], H[3];
+  double sn[3];    // next crossing parameter per axis (>= 2 when exhausted)
+  double step[3];  // spacing of the crossings of that axis
 
-  __device__ __forceinline__ double s_of(int a) const { return (knot[a] * H[a] - x0[a]) / d[a]; }
-
-  __device__ __forceinline__ void init(const double* x0_, const double* d_, const Grid& G) {
+  __device__ __forceinline__ void init(const double* x0, const double* d, const Grid& G) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      x0[a] = x0_[a];
-      d[a] = d_[a];
-      H[a] = G.H[a];
       sn[a] = 2.0;
-      knot[a] = 0.0;
-      dir[a] = 0.0;
+      step[a] = 2.0;
       if (d[a] != 0.0) {
+        const double inv = 1.0 / d[a];
         const double u0 = x0[a] * G.invH[a];
         const double off = Spline<R>::knot_off;
-        if (d[a] > 0.0) {
-          dir[a] = 1.0;
-          knot[a] = floor(u0 - off) - 1.0 + off;
-        } else {
-          dir[a] = -1.0;
-          knot[a] = floor(u0 - off) + 1.0 + off;
-        }
-        double s = s_of(a);
-        for (int it = 0; it < 4 && !(s > 0.0); ++it) {
-          knot[a] += dir[a];
-          s = s_of(a);
-        }
+        const double knot = d[a] > 0.0 ? floor(u0 - off) - 1.0 + off : floor(u0 - off) + 1.0 + off;
+        const double st = G.H[a] * fabs(inv);
+        double s = (knot * G.H[a] - x0[a]) * inv;
+        for (int it = 0; it < 4 && !(s > 0.0); ++it) s += st;
         sn[a] = (s > 0.0 && s < 1.0) ? s : 2.0;
+        step[a] = st;
       }
     }
   }
@@ -196,8 +186,7 @@ struct Crossings {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (sn[a] == s1) {
-        knot[a] += dir[a];
-        const double s = s_of(a);
+        const double s = sn[a] + step[a];
         sn[a] = (s > sn[a] && s < 1.0) ? s : 2.0;
       }
     }

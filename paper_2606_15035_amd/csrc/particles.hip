@@ -486,18 +486,33 @@ __device__ __forceinline__ int min_image(int raw, int n) {
   return r;
 }
 
-__device__ __forceinline__ int block_min_int(int v) {
-  __shared__ int lds_i[kBlock / kWave];
+// t / d for 0 <= t < 2^22 and d >= 1, with inv_d = 1.0f / d: (t + 1/2) / d
+// lies at least 1/(2d) away from an integer, further than the float rounding
+// error (t + 1/2) 2^-23 / d, so the truncation is exact (no integer division)
+__device__ __forceinline__ int div_small(int t, float inv_d) {
+  return (int)(((float)t + 0.5f) * inv_d);
+}
+
+// block-wide minimum of M ints at once (one barrier pair for all of them)
+template <int M>
+__device__ __forceinline__ void block_min_ints(int (&v)[M]) {
+  __shared__ int lds_i[M][kBlock / kWave];
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
 #pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
-  if (lane == 0) lds_i[wid] = v;
-  __syncthreads();
-  int r = lds_i[0];
+  for (int m = 0; m < M; ++m) {
 #pragma unroll
-  for (int w = 1; w < kBlock / kWave; ++w) r = min(r, lds_i[w]);
+    for (int o = kWave / 2; o > 0; o >>= 1) v[m] = min(v[m], __shfl_xor(v[m], o, kWave));
+    if (lane == 0) lds_i[m][wid] = v[m];
+  }
   __syncthreads();
-  return r;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    int r = lds_i[m][0];
+#pragma unroll
+    for (int w = 1; w < kBlock / kWave; ++w) r = min(r, lds_i[m][w]);
+    v[m] = r;
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ int64_t chunk_particle(int64_t base, int k) {
@@ -539,6 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   double js[1] = {0.0};
   double bad = 0.0;
+  late_reduce_init<2>();
   if (threadIdx.x == 0) {  // the chunk's first particle is the reference cell
     double x0[3];
     st.x_of(P.G, P.np, base, x0);
@@ -566,10 +582,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
     }
   }
   int tlo[3], dim[3];
+  {
+    int mv[6] = {rmin[0], rmin[1], rmin[2], -rmax[0], -rmax[1], -rmax[2]};
+    block_min_ints<6>(mv);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    tlo[a] = block_min_int(rmin[a]);
-    dim[a] = -block_min_int(-rmax[a]) - tlo[a] + 1;
+    for (int a = 0; a < 3; ++a) {
+      tlo[a] = mv[a];
+      dim[a] = -mv[3 + a] - tlo[a] + 1;
+    }
   }
   // block-uniform; each extent is bounded first so that the product cannot overflow
   const bool use_tile = dim[0] > 0 && dim[0] <= kTileNodes && dim[1] <= kTileNodes &&
@@ -657,8 +677,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
     if (!ok) bad = 1.0;
   }
   __syncthreads();
+  const float inv_d1 = 1.0f / (float)max(dim[1], 1), inv_d2 = 1.0f / (float)max(dim[2], 1);
   for (int t = threadIdx.x; t < nt; t += kBlock) {
-    const int cz = t % dim[2], cy = (t / dim[2]) % dim[1], cx = t / (dim[2] * dim[1]);
+    const int q = div_small(t, inv_d2), cx = div_small(q, inv_d1);
+    const int cz = t - q * dim[2], cy = q - cx * dim[1];
     const int64_t g = node_index(P.G, s_ref[0] + tlo[0] + cx, s_ref[1] + tlo[1] + cy,
                                  s_ref[2] + tlo[2] + cz);
 #pragma unroll
@@ -672,8 +694,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
       }
     }
   }
-  block_max_to(bad, sc.red + S_BAD);
-  block_partials<1>(js, sc.region(P_JS));
+  const double part[2] = {js[0], bad};
+  const bool ismax[2] = {false, true};
+  double blk[2];
+  if (late_reduce<2>(part, ismax, blk)) {
+    sc.region(P_JS)[blockIdx.x] = blk[0];  // J_s partials, summed in order by k_finish
+    atomic_max_nonneg(sc.spread_copy(S_BAD), blk[1]);
+  }
 }
 
 // Gather + push of one particle through accessor acc: grad phi-bar and
@@ -733,10 +760,11 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
                                                        double* __restrict__ vnew, AosFields F,
                                                        int* __restrict__ flags, Scratch sc) {
   constexpr int W = R + 1;
-  if (!TILED && flags) {
-    if (flags[blockIdx.x] == 0) return;  // done by the tiled kernel
+  late_reduce_init<4>();
+  if (!TILED) {
+    if (flags && flags[blockIdx.x] == 0) return;  // done by the tiled kernel
     __syncthreads();
-    if (threadIdx.x == 0) flags[blockIdx.x] = 0;
+    if (threadIdx.x == 0 && flags) flags[blockIdx.x] = 0;
   }
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < P.np;
@@ -772,14 +800,20 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
 #pragma unroll
       for (int a = 0; a < 3; ++a) s_ref[a] = lo[a];
     __syncthreads();
-    int shift[3], tlo[3], dim[3];
+    int shift[3], tlo[3], dim[3], mv[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int raw = lo[a] - s_ref[a];
       const int rel = min_image(raw, P.G.n[a]);
       shift[a] = rel - raw;
-      tlo[a] = block_min_int(active ? rel : 0x3fffffff);
-      dim[a] = -block_min_int(active ? -(rel + span[a]) : 0x3fffffff) - tlo[a] + 1;
+      mv[a] = active ? rel : 0x3fffffff;
+      mv[3 + a] = active ? -(rel + span[a]) : 0x3fffffff;
+    }
+    block_min_ints<6>(mv);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      tlo[a] = mv[a];
+      dim[a] = -mv[3 + a] - tlo[a] + 1;
     }
     // block-uniform; each extent is bounded first so that the product cannot overflow
     const bool fits = dim[0] <= kGatherTileNodes && dim[1] <= kGatherTileNodes &&
@@ -791,9 +825,11 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
     }
     const int nt2 = (int)vol * (kGbufStride / 2);
     const double2* g2 = reinterpret_cast<const double2*>(F.g);
+    const float inv_d1 = 1.0f / (float)dim[1], inv_d2 = 1.0f / (float)dim[2];
     for (int t = threadIdx.x; t < nt2; t += kBlock) {
       const int nd = t / (kGbufStride / 2), part = t % (kGbufStride / 2);
-      const int cz = nd % dim[2], cy = (nd / dim[2]) % dim[1], cx = nd / (dim[2] * dim[1]);
+      const int q = div_small(nd, inv_d2), cx = div_small(q, inv_d1);
+      const int cz = nd - q * dim[2], cy = q - cx * dim[1];
       const int64_t g = node_index(P.G, s_ref[0] + tlo[0] + cx, s_ref[1] + tlo[1] + cy,
                                    s_ref[2] + tlo[2] + cz);
       tile2[t] = g2[g * (kGbufStride / 2) + part];
@@ -824,11 +860,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
       if (!isfinite(vn[j])) bad = 2.0;  // max-reductions drop NaN: flag it explicitly
     }
   }
-  block_max_to(dvm, sc.red + S_DVMAX);
-  block_max_to(vm, sc.red + S_VMAX);
-  block_max_to(bad, sc.red + S_BAD);
-  block_sum<1>(npieces);  // integer counts: the atomic sum is exact and order-free
-  if (threadIdx.x == 0 && npieces[0] > 0.0) unsafeAtomicAdd(sc.red + S_PIECES, npieces[0]);
+  // no block barrier after the orbit loops: a wavefront with fewer pieces
+  // does not wait for the block's slowest one
+  const double part[4] = {dvm, vm, bad, npieces[0]};
+  const bool ismax[4] = {true, true, true, false};
+  double blk[4];
+  if (late_reduce<4>(part, ismax, blk)) {
+    atomic_max_nonneg(sc.spread_copy(S_DVMAX), blk[0]);
+    atomic_max_nonneg(sc.spread_copy(S_VMAX), blk[1]);
+    atomic_max_nonneg(sc.spread_copy(S_BAD), blk[2]);
+    // integer counts: the atomic sum is exact and order-free
+    if (blk[3] > 0.0) unsafeAtomicAdd(sc.spread_copy(S_PIECES), blk[3]);
+  }
 }
 
 // Consistency sweep of the accepted iterate: Ubar, Ebar = -gphibar - Ubar,

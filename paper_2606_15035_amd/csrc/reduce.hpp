@@ -60,6 +60,58 @@ __device__ __forceinline__ double block_max(double v) {
   return r;
 }
 
+// Block reductions without a barrier after the producing loops, so that a
+// wavefront that finishes early does not wait for its block's slowest one:
+// every wavefront reduces its lanes (sum, or max where ismax[m]) and leaves
+// its M values in LDS; the last wavefront of the block to arrive (an LDS
+// counter) combines the block's wavefronts in a fixed order.  Returns true
+// in exactly one thread of the block (lane 0 of that wavefront), with the
+// block's values in out.  Thread 0 must run late_reduce_init<M>() before a
+// barrier that precedes the call.
+template <int M>
+__device__ __forceinline__ unsigned int* late_counter() {
+  __shared__ unsigned int c;
+  return &c;
+}
+template <int M>
+__device__ __forceinline__ double* late_values() {
+  __shared__ double v[M * (kBlock / kWave)];
+  return v;
+}
+template <int M>
+__device__ __forceinline__ void late_reduce_init() {
+  if (threadIdx.x == 0) *late_counter<M>() = 0u;
+}
+template <int M>
+__device__ __forceinline__ bool late_reduce(const double (&v)[M], const bool (&ismax)[M],
+                                            double (&out)[M]) {
+  constexpr int NW = kBlock / kWave;
+  const int wid = threadIdx.x / kWave;
+  double r[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) r[m] = ismax[m] ? wave_max(v[m]) : wave_sum(v[m]);
+  if (threadIdx.x % kWave != 0) return false;
+  double* vals = late_values<M>();
+#pragma unroll
+  for (int m = 0; m < M; ++m) vals[m * NW + wid] = r[m];
+  __threadfence_block();  // the values before the arrival count
+  if (atomicAdd(late_counter<M>(), 1u) != NW - 1) return false;
+  __threadfence_block();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double a = vals[m * NW];
+    for (int w = 1; w < NW; ++w) a = ismax[m] ? fmax(a, vals[m * NW + w]) : a + vals[m * NW + w];
+    out[m] = a;
+  }
+  return true;
+}
+
+// bit-pattern atomicMax of a non-negative double (order-independent)
+__device__ __forceinline__ void atomic_max_nonneg(double* slot, double v) {
+  if (v > 0.0)
+    atomicMax(reinterpret_cast<unsigned long long*>(slot), (unsigned long long)__double_as_longlong(v));
+}
+
 // Block max of a non-negative value, folded into *slot (bit-pattern atomicMax).
 // fmax drops NaN operands, so callers flag non-finite values separately.
 __device__ __forceinline__ void block_max_to(double v, double* slot) {
