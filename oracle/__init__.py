@@ -43,7 +43,8 @@ class Cfg(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("L", C.c_double * 3), ("kappa", C.c_double),
                 ("sigma1", C.c_double), ("sigma2", C.c_double), ("dt", C.c_double),
                 ("r", C.c_int32), ("split", C.c_int32), ("nq", C.c_int32),
-                ("analytic", C.c_int32), ("tol", C.c_double), ("pmax", C.c_int32)]
+                ("analytic", C.c_int32), ("tol", C.c_double), ("pmax", C.c_int32),
+                ("anderson", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -97,6 +98,8 @@ def lib():
                                        C.POINTER(C.c_int)]
         L.orc_rebuild_P.argtypes = [P]
         L.orc_field_energy_grad.argtypes = [P, D]
+        L.orc_set_trace.argtypes = [P, D, D, C.c_int]
+        L.orc_anderson_mix.argtypes = [C.c_int, C.c_int64, C.POINTER(D), C.POINTER(D), D, D]
         _lib = L
     return _lib
 
@@ -113,7 +116,7 @@ def _f64(a):
 
 
 def make_cfg(n, L, dt, r=1, kappa=1.0, sigma1=1.0, sigma2=1.0, split=True, nq=0,
-             analytic=True, tol=1e-12, pmax=16) -> Cfg:
+             analytic=True, tol=1e-12, pmax=16, anderson=0) -> Cfg:
     c = Cfg()
     for a in range(3):
         c.n[a] = int(n[a])
@@ -121,7 +124,25 @@ def make_cfg(n, L, dt, r=1, kappa=1.0, sigma1=1.0, sigma2=1.0, split=True, nq=0,
     c.kappa, c.sigma1, c.sigma2, c.dt = kappa, sigma1, sigma2, dt
     c.r, c.split, c.nq, c.analytic = int(r), int(bool(split)), int(nq), int(bool(analytic))
     c.tol, c.pmax = float(tol), int(pmax)
+    c.anderson = int(anderson)
     return c
+
+
+def anderson_mix(w_hist, g_hist):
+    """One Anderson update from iterates w_hist[j] and images g_hist[j]
+    (j = 0 newest; len = mk + 1).  Returns (w_next, gamma)."""
+    mk = len(w_hist) - 1
+    w = [_f64(a).ravel() for a in w_hist]
+    g = [_f64(a).ravel() for a in g_hist]
+    n = w[0].size
+    PD = C.POINTER(C.c_double)
+    wa = (PD * (mk + 1))(*[_p(a) for a in w])
+    ga = (PD * (mk + 1))(*[_p(a) for a in g])
+    out = np.zeros(n)
+    gamma = np.zeros(max(mk, 1))
+    if lib().orc_anderson_mix(mk, n, wa, ga, _p(out), _p(gamma)) != 0:
+        raise ValueError("bad Anderson arguments")
+    return out, gamma[:mk]
 
 
 def gauss_legendre(n):
@@ -188,6 +209,17 @@ class OracleSim:
         args = [None if a is None else _f64(a) for a in (x, v, vprev, P, fields)]
         self.q, self.m = float(q), float(m)
         lib().orc_set_state(self._h, *[_p(a) for a in args], q, m)
+
+    def trace_next_step(self, max_passes):
+        """Record the iterates and images of the passes of the next step.
+        Returns (w, g) arrays of shape (max_passes, 3, np), filled by step()."""
+        self._trace = (np.zeros((max_passes, 3, self.np)), np.zeros((max_passes, 3, self.np)))
+        lib().orc_set_trace(self._h, _p(self._trace[0]), _p(self._trace[1]), int(max_passes))
+        return self._trace
+
+    def stop_trace(self):
+        lib().orc_set_trace(self._h, None, None, 0)
+        self._trace = None
 
     def current(self):
         J = np.zeros((3,) + self.n)

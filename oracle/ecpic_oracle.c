@@ -22,7 +22,12 @@
  *               potential update (eq. cn-field-update) with Fourier symbols
  *               (Sec. 3.3), evaluated with a plain separable DFT
  *   push        orbit-discrete-gradient canonical-momentum push (eq. orbit-push)
- *   step        Picard iteration of Algorithm 1
+ *   step        Picard iteration of Algorithm 1, optionally with Anderson
+ *               mixing of the iterates (an extension: the conservation
+ *               statement concerns the converged discrete equations, not the
+ *               nonlinear solver, Sec. 4 "Picard iteration used in the
+ *               numerical experiments"; Anderson acceleration is the paper's
+ *               named future work, Sec. 6)
  *   diagnostics K, W (eqs. particle-energy, field-energy), R_field, R_particle,
  *               R_total (Sec. 5.3), gauge/Gauss residuals (Sec. 5.1),
  *               chain-rule residual R_A (Sec. 5.2)
@@ -53,6 +58,8 @@
 
 typedef double complex cplx;
 
+#define ORC_MAX_ANDERSON 4
+
 /* ------------------------------------------------------------------------- */
 /* configuration and state                                                   */
 /* ------------------------------------------------------------------------- */
@@ -70,6 +77,7 @@ typedef struct {
   int32_t analytic;  /* degree 1 with splitting: 1 = App. A/B closed forms, 0 = Gauss */
   double tol;        /* Picard tolerance */
   int32_t pmax;      /* Picard iterations p = 0..pmax */
+  int32_t anderson;  /* Anderson depth m (0: the plain Picard iteration of Algorithm 1) */
 } orc_cfg;
 
 typedef struct {
@@ -107,6 +115,10 @@ typedef struct {
   orc_energy en;
   double K0, W0;
   int have_energy;
+  /* optional record of the Picard passes of the next steps (tests): iterate
+     w_p and image G(w_p) of pass p at trace_w/g + 3 np p, passes < trace_max */
+  double *trace_w, *trace_g;
+  int trace_max;
 } orc_sim;
 
 /* ------------------------------------------------------------------------- */
@@ -712,6 +724,94 @@ static void constraints(const orc_sim* S, double* gmax, double* gl2, double* rma
 /* public API                                                                */
 /* ------------------------------------------------------------------------- */
 
+/* ------------------------------------------------------------------------- */
+/* Anderson mixing of a fixed-point iteration w = G(w)                       */
+/* ------------------------------------------------------------------------- */
+/*
+ * Anderson acceleration (D. G. Anderson, J. ACM 12, 1965; the form of
+ * H. F. Walker and P. Ni, SIAM J. Numer. Anal. 49, 2011, with mixing
+ * parameter 1).  Given the last mk + 1 iterates w_{p-j} and their images
+ * g_{p-j} = G(w_{p-j}), j = 0..mk (index 0 the newest), with residuals
+ * f = g - w:
+ *   dF_j = f_{p-j+1} - f_{p-j},  dG_j = g_{p-j+1} - g_{p-j},  j = 1..mk
+ *   gamma = argmin_gamma || f_p - sum_j gamma_j dF_j ||_2
+ *   w_{p+1} = g_p - sum_j gamma_j dG_j
+ * The least-squares problem is solved by modified Gram-Schmidt QR of the
+ * columns dF_1..dF_mk (newest first, each orthogonalised twice); a column
+ * whose norm after orthogonalisation is at most 1e-6 of its own norm, or is
+ * zero, is dropped (gamma_j = 0), so that nearly dependent differences do
+ * not amplify rounding.  mk = 0 gives the Picard step w_{p+1} = g_p.
+ *
+ * w[j], g[j]: n doubles each; out: n doubles (may alias none of the inputs);
+ * gamma: mk doubles.  Returns 0, or -1 on a bad argument.
+ */
+int orc_anderson_mix(int mk, int64_t n, const double* const* w, const double* const* g,
+                     double* out, double* gamma) {
+  if (mk < 0 || mk > ORC_MAX_ANDERSON || n < 0) return -1;
+  double* q[ORC_MAX_ANDERSON];
+  double R[ORC_MAX_ANDERSON][ORC_MAX_ANDERSON];
+  int kept[ORC_MAX_ANDERSON];
+  int nk = 0;
+  for (int j = 0; j < mk; ++j) gamma[j] = 0.0;
+  for (int j = 1; j <= mk; ++j) {
+    double* v = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double norm0 = 0.0;
+    for (int64_t e = 0; e < n; ++e) {
+      v[e] = (g[j - 1][e] - w[j - 1][e]) - (g[j][e] - w[j][e]);
+      norm0 += v[e] * v[e];
+    }
+    norm0 = sqrt(norm0);
+    double rcol[ORC_MAX_ANDERSON] = {0.0};
+    for (int pass = 0; pass < 2; ++pass)
+      for (int k = 0; k < nk; ++k) {
+        double r = 0.0;
+        for (int64_t e = 0; e < n; ++e) r += q[k][e] * v[e];
+        for (int64_t e = 0; e < n; ++e) v[e] -= r * q[k][e];
+        rcol[k] += r;
+      }
+    double norm = 0.0;
+    for (int64_t e = 0; e < n; ++e) norm += v[e] * v[e];
+    norm = sqrt(norm);
+    if (norm0 == 0.0 || norm <= 1e-6 * norm0) {
+      free(v);
+      continue;
+    }
+    for (int64_t e = 0; e < n; ++e) v[e] /= norm;
+    for (int k = 0; k < nk; ++k) R[k][nk] = rcol[k];
+    R[nk][nk] = norm;
+    q[nk] = v;
+    kept[nk] = j;
+    ++nk;
+  }
+  /* gamma_kept = R^{-1} Q^T f_p */
+  double c[ORC_MAX_ANDERSON], gk[ORC_MAX_ANDERSON];
+  for (int k = 0; k < nk; ++k) {
+    c[k] = 0.0;
+    for (int64_t e = 0; e < n; ++e) c[k] += q[k][e] * (g[0][e] - w[0][e]);
+  }
+  for (int k = nk - 1; k >= 0; --k) {
+    double t = c[k];
+    for (int l = k + 1; l < nk; ++l) t -= R[k][l] * gk[l];
+    gk[k] = t / R[k][k];
+  }
+  for (int k = 0; k < nk; ++k) gamma[kept[k] - 1] = gk[k];
+  for (int64_t e = 0; e < n; ++e) {
+    double u = g[0][e];
+    for (int j = 1; j <= mk; ++j) u -= gamma[j - 1] * (g[j - 1][e] - g[j][e]);
+    out[e] = u;
+  }
+  for (int k = 0; k < nk; ++k) free(q[k]);
+  return 0;
+}
+
+/* Record the passes of later steps into caller buffers of 3 np max_passes
+   doubles each (NULL stops recording). */
+void orc_set_trace(orc_sim* S, double* w, double* g, int max_passes) {
+  S->trace_w = w;
+  S->trace_g = g;
+  S->trace_max = w && g ? max_passes : 0;
+}
+
 int orc_check_config(const orc_cfg* c) {
   for (int a = 0; a < 3; ++a)
     if (c->n[a] < 2 || !(c->L[a] > 0.0)) return -1;
@@ -721,6 +821,7 @@ int orc_check_config(const orc_cfg* c) {
   double lhs = c->sigma1, rhs = c->kappa * c->kappa * c->sigma2;
   if (fabs(lhs - rhs) > 1e-13 * fmax(fabs(lhs), fabs(rhs))) return -1;
   if (c->nq < 0 || c->nq > 64 || c->pmax < 0) return -1;
+  if (c->anderson < 0 || c->anderson > ORC_MAX_ANDERSON) return -1;
   return 0;
 }
 
@@ -873,6 +974,14 @@ int orc_picard_step(orc_sim* S, orc_step_info* info) {
   double err_v = 0.0, err_J = 0.0;
   int p = 0;
   double work = 0.0, JE = 0.0, RA2 = 0.0, RAmax = 0.0, poumax = 0.0;
+  /* Anderson history: iterates and images of the last m + 1 passes (pass k in slot k % (m + 1)) */
+  const int M = S->c.anderson;
+  double* hist_w[ORC_MAX_ANDERSON + 1] = {NULL};
+  double* hist_g[ORC_MAX_ANDERSON + 1] = {NULL};
+  for (int k = 0; M > 0 && k <= M; ++k) {
+    hist_w[k] = (double*)malloc(sizeof(double) * 3 * np + 8);
+    hist_g[k] = (double*)malloc(sizeof(double) * 3 * np + 8);
+  }
 
   /* extrapolated initial guess v^{n+1,0} = 2 v^n - v^{n-1} */
   for (int64_t i = 0; i < 3 * np; ++i) vit[i] = 2.0 * S->v[i] - S->vprev[i];
@@ -962,6 +1071,11 @@ int orc_picard_step(orc_sim* S, orc_step_info* info) {
       for (int64_t g = 0; g < nc; ++g)
         JE += J[l * nc + g] * (-gphi[l * nc + g] - Uhalf[l * nc + g]) * G->dV;
 
+    if (S->trace_w && p < S->trace_max) {
+      memcpy(S->trace_w + (size_t)3 * np * p, vit, sizeof(double) * 3 * np);
+      memcpy(S->trace_g + (size_t)3 * np * p, vnew, sizeof(double) * 3 * np);
+    }
+
     /* fixed-point errors */
     err_v = vmaxall > 0.0 ? dvmax / vmaxall : dvmax;
     if (p >= 1) {
@@ -978,7 +1092,21 @@ int orc_picard_step(orc_sim* S, orc_step_info* info) {
       break;
     }
     if (p == S->c.pmax) break;
-    memcpy(vit, vnew, sizeof(double) * 3 * np);
+    if (M == 0) {
+      memcpy(vit, vnew, sizeof(double) * 3 * np); /* Picard: v^{n+1,p+1} is the next iterate */
+    } else {
+      memcpy(hist_w[p % (M + 1)], vit, sizeof(double) * 3 * np);
+      memcpy(hist_g[p % (M + 1)], vnew, sizeof(double) * 3 * np);
+      const int mk = p < M ? p : M;
+      const double* wv[ORC_MAX_ANDERSON + 1];
+      const double* gv[ORC_MAX_ANDERSON + 1];
+      for (int j = 0; j <= mk; ++j) {
+        wv[j] = hist_w[(p - j) % (M + 1)];
+        gv[j] = hist_g[(p - j) % (M + 1)];
+      }
+      double gamma[ORC_MAX_ANDERSON];
+      orc_anderson_mix(mk, 3 * np, wv, gv, vit, gamma);
+    }
   }
   if (p > S->c.pmax) p = S->c.pmax;
 
@@ -1018,6 +1146,10 @@ done:
     info->converged = status == 0;
     info->err_v = err_v;
     info->err_J = err_J;
+  }
+  for (int k = 0; k <= ORC_MAX_ANDERSON; ++k) {
+    free(hist_w[k]);
+    free(hist_g[k]);
   }
   free(A0r);
   free(vit);
