@@ -65,13 +65,14 @@ def gather_bytes_per_push() -> float:
 MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.5", "workload": "c2", "bytes": 209.6e6}
 
 
-def time_workload(E, wl, precision, steps, warmup):
+def time_workload(E, wl, precision, steps, warmup, anderson=0):
     """Particle-pushes/s of `steps` timed steps of workload wl after `warmup`
-    steps, in the given precision; returns (value, ms/step, mean passes,
-    max |R_total|/E per step, |E - E0|/E0, profile)."""
+    steps, in the given precision and Anderson depth; returns (value, ms/step,
+    mean passes, |R_total|/E of the last step, |E - E0|/E0, profile)."""
     import torch
     cfg = E.make_config(wl.n, wl.L, wl.dt, r=wl.r, kappa=wl.kappa, sigma1=wl.sigma1,
-                        sigma2=wl.sigma2, tol=wl.tol, pmax=wl.pmax, precision=precision)
+                        sigma2=wl.sigma2, tol=wl.tol, pmax=wl.pmax, precision=precision,
+                        anderson=anderson)
     sim = E.Sim(cfg, wl.np)
     sim.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
     E0 = sim.energy_diagnostics()["E_total"]
@@ -120,6 +121,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision lines (32^3 and 64^3 workloads)")
+    ap.add_argument("--no-anderson", action="store_true",
+                    help="skip the line with Anderson mixing of the Picard iterates")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -207,11 +210,23 @@ def main():
                                for k in ("scatter", "field_solve", "gather_push")},
         "roofline": roofline,
     }
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_anderson:
+        # the same FP64 workload with Anderson mixing (depth 1): fewer passes
+        # per step, each pass a little longer (two streaming kernels)
+        steps = max(5, args.steps // 2)
+        print("anderson depth 1 ...", flush=True)
+        v_, ms_, it_, rel_, drift_, pr_ = time_workload(E, wl, E.FP64, steps, args.warmup,
+                                                        anderson=1)
+        out["anderson"] = {"depth": 1, "value": v_, "unit": "particle-pushes/s",
+                           "ms_per_step": ms_, "steps": steps, "warmup": args.warmup,
+                           "picard_passes_mean": it_, "dE_over_E_step": rel_,
+                           "dE_over_E_run": drift_,
+                           "step_speedup_vs_picard": out["ms_per_step"] / ms_}
     if not args.no_mixed:
         # the same workload in the mixed form, and the 64^3 / 33.5M-particle
         # workload (mixed by definition), a few steps each
-        del sim
-        torch.cuda.empty_cache()
         mixed = {}
         for name, steps in ((args.workload, max(5, args.steps // 2)), ("c4", 3)):
             wlm = W.two_stream(name)

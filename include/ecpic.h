@@ -83,6 +83,22 @@ typedef struct {
   int32_t sort_interval;        /* particles are re-sorted by mesh cell at the start of every
                                    k-th step: 0 or 1 = every step, k > 1 = every k steps,
                                    -1 = never (results are the same up to rounding) */
+  int32_t anderson_depth;       /* 0: the Picard iteration of Algorithm 1.  m = 1..4: Anderson
+                                   mixing of the iterates over the last m passes (Walker and
+                                   Ni 2011, mixing parameter 1): with w_p the iterate
+                                   v^{n+1,p}, g_p = G(w_p) the velocity the pass returns and
+                                   f = g - w, the next iterate is g_p - sum_j gamma_j
+                                   (g_{p-j+1} - g_{p-j}), gamma minimising
+                                   |f_p - sum_j gamma_j (f_{p-j+1} - f_{p-j})|_2 over
+                                   j = 1..min(m, p).  The stopping test, the accepted
+                                   iterate and the converged equations are those of
+                                   Algorithm 1; energy conservation holds at convergence
+                                   whatever the solver (Sec. 4, Picard iteration of the
+                                   experiments; Anderson acceleration is the paper's future
+                                   work, Sec. 6).  Costs 2 m more 3 x np FP64 arrays of state.
+                                   In mixed precision the mixing coefficients are FP64 sums
+                                   over the particles, so with m > 0 the step is no longer
+                                   bitwise independent of the particle order. */
 } ecpic_config;
 
 typedef struct {

@@ -76,6 +76,8 @@ ecpic_status check_config(const ecpic_config* c, int64_t np) {
     return fail(ECPIC_EINVAL, "precision must be ECPIC_FP64 or ECPIC_MIXED");
   if (!(c->fixed_point_scale >= 0.0) || c->fixed_point_scale > 0x1p52)
     return fail(ECPIC_EINVAL, "fixed_point_scale must be in [0, 2^52] (0 = 2^40)");
+  if (c->anderson_depth < 0 || c->anderson_depth > kMaxAnderson)
+    return fail(ECPIC_EINVAL, "anderson_depth must be in [0, %d]", kMaxAnderson);
   return ECPIC_OK;
 }
 
@@ -162,7 +164,11 @@ struct ecpic_sim {
   // One of the two stores is live (cfg.precision); [1] is the sort's alternate.
   Fp64Store f64[2];
   MixedStore mx[2];
-  double *vit, *vnew;  // Picard iterates (FP64 in both forms)
+  double *vit, *vnew;  // Picard iterate w_p and image g_p of the current pass (FP64)
+  // 2 (m + 1) buffers of 3 np doubles for the iterates and images that the
+  // Anderson mixing of depth m still needs (m = 0: the two of the plain iteration)
+  double* apool[2 * (kMaxAnderson + 1)] = {};
+  int npool = 0;
   int *id, *id2;
   SortScratch sb;
   unsigned long long* Jfix = nullptr;  // mixed: fixed-point current quanta
@@ -221,8 +227,10 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
       S->f64[k].vp = st.take<double>(n3);
     }
   }
-  S->vit = st.take<double>(n3);
-  S->vnew = st.take<double>(n3);
+  S->npool = 2 * (S->cfg.anderson_depth + 1);
+  for (int k = 0; k < S->npool; ++k) S->apool[k] = st.take<double>(n3);
+  S->vit = S->apool[0];
+  S->vnew = S->apool[1];
   S->id = st.take<int>(n1);
   S->id2 = st.take<int>(n1);
   S->sb.key = st.take<int>(n1);
@@ -247,7 +255,8 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->sc.spread = w.take<double>((size_t)S_NSLOTS * kSpread * kSpreadStride);
   const int64_t maxblk = std::max<int64_t>(
       std::max<int64_t>(particle_blocks(np), scatter_blocks(np)), mesh_blocks(nc));
-  S->sc.part_stride = (int64_t)kMaxSumValues * (maxblk > 0 ? maxblk : 1);
+  S->sc.part_stride = std::max<int64_t>((int64_t)kMaxSumValues * (maxblk > 0 ? maxblk : 1),
+                                        (int64_t)kAndersonSums * anderson_dot_blocks(3 * np));
   S->sc.part = w.take<double>((size_t)P_NSITES * S->sc.part_stride);
   if (state_bytes) *state_bytes = st.off + 256;
   if (ws_bytes) *ws_bytes = w.off + 256;
@@ -484,6 +493,29 @@ ecpic_status ecpic_init_particles(ecpic_sim* S, const double* x, const double* v
   return ECPIC_OK;
 }
 
+namespace {
+
+// a pool buffer that none of a[0..na) and b[0..nb) refers to
+double* pool_free(const ecpic_sim* S, double* const* a, int na, double* const* b, int nb) {
+  for (int k = 0; k < S->npool; ++k) {
+    double* c = S->apool[k];
+    bool used = false;
+    for (int i = 0; i < na; ++i) used = used || a[i] == c;
+    for (int i = 0; i < nb; ++i) used = used || b[i] == c;
+    if (!used) return c;
+  }
+  return nullptr;
+}
+
+// put v in front of list (n entries), keeping at most cap of them
+void push_front(double** list, int& n, int cap, double* v) {
+  n = std::min(n + 1, cap);
+  for (int j = n - 1; j > 0; --j) list[j] = list[j - 1];
+  list[0] = v;
+}
+
+}  // namespace
+
 ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   if (!S) return fail(ECPIC_EINVAL, "null simulation");
   if (!S->initialized) return fail(ECPIC_ESTATE, "step before init_particles/set_state");
@@ -504,6 +536,16 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
       launch_sort(s, S->G, S->np, st, alt, S->id, S->id2, S->sb);
     });
   // v^{n+1,0} = 2 v^n - v^{n-1}
+  // Iterates w_{p-j} (wl[j]) and images g_{p-j} (gl[j]) of the passes the
+  // Anderson mixing still needs, newest first (the plain iteration keeps one
+  // of each and takes w_{p+1} = g_p without a copy).
+  const int am = S->cfg.anderson_depth;
+  const int64_t n3 = 3 * S->np;
+  double* wl[kMaxAnderson + 1] = {};
+  double* gl[kMaxAnderson + 1] = {};
+  int nw = 0, ng = 0;
+  push_front(wl, nw, am + 1, S->apool[0]);
+  S->vit = wl[0];
   on_store(S, [&](auto& st, auto&) { launch_extrapolate(s, S->np, st, S->vit); });
   const CurrentOut cout{nullptr, S->Jfix, S->fix_scale};
   const double fix_unit = S->q / S->G.dV / S->fix_scale;
@@ -512,6 +554,18 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   bool converged = false;
   double err_v = 0.0, err_J = INFINITY;
   for (p = 0; p <= S->cfg.picard_max; ++p) {
+    S->vit = wl[0];
+    S->vnew = pool_free(S, wl, nw, gl, std::min(ng, am));
+    if (!S->vnew) return fail(ECPIC_EDEVICE, "internal: no free iterate buffer");
+    push_front(gl, ng, am + 1, S->vnew);
+    // Anderson: differences over mk = min(m, p) passes; one difference is
+    // summed by the gather itself, more by a streaming kernel after it
+    const int mk = am > 0 && S->np > 0 ? std::min(am, p) : 0;
+    AndersonPrev prev{};
+    if (mk == 1) {
+      prev.w = wl[1];
+      prev.g = gl[1];
+    }
     double* J = S->Jb[jcur];
     double* Jprev = S->Jb[1 - jcur];
     launch_reset_slots(s, S->sc, S_DVMAX, 5);  // DVMAX, VMAX, DJMAX, JS, BAD
@@ -530,19 +584,28 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));         // grad phi^{n+1/2}, A^{n+1}
     if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
     on_store(S, [&](auto& st, auto&) {  // v^{n+1,p+1}
-      launch_gather_push(s, r, P, st, S->vit, S->vnew, S->gbuf, S->gflags, S->sc);
+      launch_gather_push(s, r, P, st, S->vit, S->vnew, S->gbuf, S->gflags, S->sc, prev);
     });
     if (prof) HIPCHK(hipEventRecord(S->ev[3], s));
+    AndersonVecs av{};
+    for (int j = 0; j <= mk; ++j) {
+      av.w[j] = wl[j];
+      av.g[j] = gl[j];
+    }
+    if (mk >= 2) launch_anderson_dots(s, mk, n3, av, S->sc);
     {
-      const FinishJob jobs[5] = {{P_CN, (int)mesh_blocks(nc), 3, S_JE},
+      const FinishJob jobs[6] = {{P_CN, (int)mesh_blocks(nc), 3, S_JE},
                                  {P_JS, (int)scatter_blocks(S->np), 1, S_JS},
                                  {0, 0, 2, S_DVMAX, F_SPREAD_MAX},
                                  {0, 0, 1, S_BAD, F_SPREAD_MAX},
-                                 {0, 0, 1, S_PIECES, F_SPREAD_SUM}};
-      launch_finish(s, S->sc, jobs, S->np > 0 ? 5 : 1);
+                                 {0, 0, 1, S_PIECES, F_SPREAD_SUM},
+                                 {P_AA,
+                                  mk == 1 ? (int)particle_blocks(S->np) : anderson_dot_blocks(n3),
+                                  anderson_sums(mk), S_AA}};
+      launch_finish(s, S->sc, jobs, S->np > 0 ? (mk > 0 ? 6 : 5) : 1);
     }
     HIPCHK(hipGetLastError());
-    ecpic_status st = sync_read(S, S_DVMAX, 5);
+    ecpic_status st = sync_read(S, S_DVMAX, (S_AA - S_DVMAX) + anderson_sums(mk));
     if (st != ECPIC_OK) return st;
     if (prof) {
       float t01 = 0.f, t12 = 0.f, t23 = 0.f;
@@ -572,7 +635,15 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
       break;
     }
     if (p == S->cfg.picard_max) break;
-    std::swap(S->vit, S->vnew);  // next iterate
+    double* wnext = gl[0];  // w_{p+1} = g_p
+    if (mk > 0) {           // w_{p+1} = g_p - sum_j gamma_j (g_{p-j+1} - g_{p-j})
+      AndersonCoef c{};
+      anderson_gamma(mk, S->host + (S_AA - S_DVMAX), c.gamma);
+      wnext = pool_free(S, wl, am, gl, am + 1);
+      if (!wnext) return fail(ECPIC_EDEVICE, "internal: no free iterate buffer");
+      launch_anderson_update(s, mk, n3, av, c, wnext);
+    }
+    push_front(wl, nw, am + 1, wnext);
   }
   if (p > S->cfg.picard_max) p = S->cfg.picard_max;
 
@@ -971,6 +1042,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.5"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.6"; }
 
 }  // extern "C"

@@ -9,6 +9,12 @@
 
 namespace ecpic {
 
+// Anderson mixing: at most this many differences, and the sums its
+// least-squares step needs (upper triangle of the Gram matrix + right side).
+constexpr int kMaxAnderson = 4;
+constexpr int anderson_sums(int mk) { return mk * (mk + 1) / 2 + mk; }
+constexpr int kAndersonSums = anderson_sums(kMaxAnderson);
+
 // Reduction slots (doubles) in the device scratch array.
 enum Slot : int {
   S_DVMAX = 0,  // max_i |v^{p+1} - v^p|_inf            (bit-pattern max)
@@ -16,6 +22,8 @@ enum Slot : int {
   S_DJMAX,      // max_g |J^p - J^{p-1}|                (bit-pattern max)
   S_JS,         // J_s = sum_i |q| |vbar_i|_inf / |Omega| (sum)
   S_BAD,        // 1: an orbit had too many pieces, 2: a non-finite velocity (max)
+  S_AA,         // Anderson sums dF_i . dF_j (i <= j), then dF_i . f_p   (sums)
+  S_AA_END = S_AA + kAndersonSums - 1,
   S_JE,         // sum_g J . E^{n+1/2} dV               (sum)
   S_WNEXT,      // W of the new field level             (sum)
   S_DW,         // W^{n+1} - W^n, per-mode differences  (sum)
@@ -34,7 +42,7 @@ enum Slot : int {
   S_NSLOTS
 };
 // Producer sites of block partial sums (each has its own region).
-enum Site : int { P_JS = 0, P_CN, P_SWEEP, P_K, P_W, P_NORM, P_NSITES };
+enum Site : int { P_JS = 0, P_CN, P_SWEEP, P_K, P_W, P_NORM, P_AA, P_NSITES };
 constexpr int kMaxSumValues = 4;
 
 // Gauss-Legendre rule on [0, 1] for orbits integrated without splitting at
@@ -84,6 +92,26 @@ struct FinishJob {
 };
 constexpr int kMaxFinishJobs = 8;
 void launch_finish(hipStream_t s, Scratch sc, const FinishJob* jobs, int njobs);
+
+// Anderson mixing (anderson.hip): iterates w[j] and images g[j] of passes
+// p - j, j = 0..mk, each 3 x np doubles.
+struct AndersonVecs {
+  const double* w[kMaxAnderson + 1];
+  const double* g[kMaxAnderson + 1];
+};
+struct AndersonCoef {
+  double gamma[kMaxAnderson];
+};
+constexpr int kAndersonBlocks = 2048;  // grid of the dot-product kernel (at most)
+int anderson_dot_blocks(int64_t n);
+// block partial sums of anderson_sums(mk) values into site P_AA (mk = 1..4)
+void launch_anderson_dots(hipStream_t s, int mk, int64_t n, const AndersonVecs& V,
+                          const Scratch& sc);
+// out = g[0] - sum_j gamma_j (g[j-1] - g[j]), j = 1..mk (mk = 0: a copy of g[0])
+void launch_anderson_update(hipStream_t s, int mk, int64_t n, const AndersonVecs& V,
+                            const AndersonCoef& c, double* out);
+// host: gamma (mk values) from the anderson_sums(mk) sums of k_aa_dots
+void anderson_gamma(int mk, const double* sums, double* gamma);
 // grid sizes of the producing kernels
 int64_t scatter_blocks(int64_t np);
 int64_t particle_blocks(int64_t np);
@@ -106,11 +134,18 @@ void launch_extrapolate(hipStream_t s, int64_t np, const PS& st, double* vit);
 template <class PS>
 void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
                     CurrentOut out, Scratch sc);
+// Iterate and image of the previous Picard pass: with w non-null the gather
+// also writes the block partial sums dF . dF and dF . f_p of Anderson mixing
+// over one difference (dF = f_p - f_{p-1}, f = image - iterate) to site P_AA.
+struct AndersonPrev {
+  const double* w = nullptr;
+  const double* g = nullptr;
+};
 // flags: one int per 256-particle block, zero on entry and on exit
 template <class PS>
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
                         const double* vit, double* vnew, const double* gbuf, int* flags,
-                        Scratch sc);
+                        Scratch sc, AndersonPrev prev = AndersonPrev{});
 template <class PS>
 void launch_sweep(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
                   const double* gbuf, const double* Uhalf, Scratch sc);

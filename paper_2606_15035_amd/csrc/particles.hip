@@ -758,9 +758,11 @@ template <int R, bool TILED, class PS, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
                                                        const double* __restrict__ vit,
                                                        double* __restrict__ vnew, AosFields F,
-                                                       int* __restrict__ flags, Scratch sc) {
+                                                       int* __restrict__ flags, Scratch sc,
+                                                       AndersonPrev prev) {
   constexpr int W = R + 1;
   late_reduce_init<4>();
+  late_reduce_init<2>();
   if (!TILED) {
     if (flags && flags[blockIdx.x] == 0) return;  // done by the tiled kernel
     __syncthreads();
@@ -871,6 +873,24 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
     atomic_max_nonneg(sc.spread_copy(S_BAD), blk[2]);
     // integer counts: the atomic sum is exact and order-free
     if (blk[3] > 0.0) unsafeAtomicAdd(sc.spread_copy(S_PIECES), blk[3]);
+  }
+  if (prev.w) {  // Anderson mixing over one difference: dF . dF and dF . f_p
+    double aa[2] = {0.0, 0.0};
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int64_t e = j * P.np + i;
+        const double f0 = vn[j] - vi[j], df = f0 - (prev.g[e] - prev.w[e]);
+        aa[0] += df * df;
+        aa[1] += df * f0;
+      }
+    }
+    const bool sums[2] = {false, false};
+    double ab[2];
+    if (late_reduce<2>(aa, sums, ab)) {
+      sc.region(P_AA)[blockIdx.x] = ab[0];
+      sc.region(P_AA)[gridDim.x + blockIdx.x] = ab[1];
+    }
   }
 }
 
@@ -1173,29 +1193,31 @@ void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, con
 template <class PS>
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
                         const double* vit, double* vnew, const double* gbuf, int* flags,
-                        Scratch sc) {
+                        Scratch sc, AndersonPrev prev) {
   if (P.np <= 0) return;
   AosFields F{gbuf};
   const unsigned nb = blocks_for(P.np);
+#define ECPIC_GATHER_PAIR(R_, SPLIT_)                                                          \
+  k_gather_push<R_, true, PS, SPLIT_><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc,   \
+                                                             prev);                            \
+  k_gather_push<R_, false, PS, SPLIT_><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc,  \
+                                                              prev)
   if constexpr (!PS::kMixed) {
     if (!P.split) {
       if (r == 1) {
-        k_gather_push<1, true, PS, false><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
-        k_gather_push<1, false, PS, false><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+        ECPIC_GATHER_PAIR(1, false);
       } else {
-        k_gather_push<2, true, PS, false><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
-        k_gather_push<2, false, PS, false><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+        ECPIC_GATHER_PAIR(2, false);
       }
       return;
     }
   }
   if (r == 1) {
-    k_gather_push<1, true, PS, true><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
-    k_gather_push<1, false, PS, true><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+    ECPIC_GATHER_PAIR(1, true);
   } else {
-    k_gather_push<2, true, PS, true><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
-    k_gather_push<2, false, PS, true><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc);
+    ECPIC_GATHER_PAIR(2, true);
   }
+#undef ECPIC_GATHER_PAIR
 }
 
 template <class PS>
@@ -1263,7 +1285,8 @@ void launch_fixed_current(hipStream_t s, int64_t n, unsigned long long* Jfix, do
   template void launch_scatter<PS>(hipStream_t, int, const StepParams&, const PS&, const double*, \
                                    CurrentOut, Scratch);                                         \
   template void launch_gather_push<PS>(hipStream_t, int, const StepParams&, const PS&,           \
-                                       const double*, double*, const double*, int*, Scratch);    \
+                                       const double*, double*, const double*, int*, Scratch,     \
+                                       AndersonPrev);                                            \
   template void launch_sweep<PS>(hipStream_t, int, const StepParams&, const PS&, const double*,  \
                                  const double*, const double*, Scratch);                         \
   template void launch_finalize<PS>(hipStream_t, const StepParams&, const PS&, const double*,     \

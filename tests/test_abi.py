@@ -83,6 +83,21 @@ def test_mixed_precision_state_is_smaller(lib):
     assert 60 <= (s64 - smx) / 100000 <= 68
 
 
+@pytest.mark.parametrize("m", [-1, 5])
+def test_anderson_depth_range(lib, m):
+    with pytest.raises(E.EcpicError) as ei:
+        E.state_bytes(good_cfg(anderson=m), 10)
+    assert ei.value.status == E.EINVAL
+
+
+def test_anderson_history_is_state(lib):
+    # depth m keeps the iterates and images of m more passes: 2 m x 24 B per particle
+    s0, _ = E.state_bytes(good_cfg(), 100000)
+    for m in (1, 2, 4):
+        s, _ = E.state_bytes(good_cfg(anderson=m), 100000)
+        assert 48 * m <= (s - s0) / 100000 <= 48 * m + 1
+
+
 @pytest.mark.parametrize("scale", [-1.0, 2.0 ** 53])
 def test_fixed_point_scale_range(lib, scale):
     with pytest.raises(E.EcpicError):
