@@ -37,8 +37,8 @@
  *
  * Readings where the paper leaves a choice open (each listed in the design
  * notes of the repository):
- *   - every field and both spline degrees live on nodes x_g = g H; degree 1
- *     uses the cell floor(x/H), degree 2 the nearest node floor(x/H + 1/2);
+ *   - every field and every spline degree live on nodes x_g = g H; degrees 1
+ *     and 3 use the cell floor(x/H), degree 2 the nearest node floor(x/H + 1/2);
  *   - the first-derivative Fourier symbol is zero on the Nyquist index and the
  *     Laplacian symbol is -|k~|^2 with that same k~ (keeps curl curl =
  *     grad div - Laplacian exact);
@@ -71,7 +71,7 @@ typedef struct {
   double sigma1;     /* source coefficient of the phi equation */
   double sigma2;     /* source coefficient of the A equation */
   double dt;
-  int32_t r;         /* spline degree: 1 or 2 */
+  int32_t r;         /* spline degree: 1, 2 or 3 */
   int32_t split;     /* 1: split every orbit integral at crossed knots; 0: one rule over [0,1] */
   int32_t nq;        /* Gauss points per segment, 0: smallest exact rule (2 nq - 1 >= 3 r) */
   int32_t analytic;  /* degree 1 with splitting: 1 = App. A/B closed forms, 0 = Gauss */
@@ -196,16 +196,30 @@ static void gauss_legendre(int n, double* x, double* w) {
 /* ------------------------------------------------------------------------- */
 
 /* index of the node the local polynomial pieces are written against:
-   degree 1 -> the cell's left node floor(u); degree 2 -> nearest node */
-static long spline_base(int r, double u) { return r == 1 ? (long)floor(u) : (long)floor(u + 0.5); }
+   odd degree (knots on the nodes) -> the cell's left node floor(u);
+   degree 2 (knots between nodes) -> the nearest node */
+static long spline_base(int r, double u) { return r == 2 ? (long)floor(u + 0.5) : (long)floor(u); }
 
 /* first stencil node relative to the base */
 static long spline_first(int r, long base) { return r == 1 ? base : base - 1; }
 
 /* weights w[o] and derivatives dw[o] (per unit of u) of the stencil nodes
    first+o, for local coordinate t = u - base.  Degree 1: M1(xi) = 1 - |xi|.
-   Degree 2: M2(xi) = 3/4 - xi^2 (|xi| <= 1/2), (3/2 - |xi|)^2 / 2 (1/2 <= |xi| <= 3/2). */
+   Degree 2: M2(xi) = 3/4 - xi^2 (|xi| <= 1/2), (3/2 - |xi|)^2 / 2 (1/2 <= |xi| <= 3/2).
+   Degree 3: M3(xi) = 2/3 - xi^2 + |xi|^3 / 2 (|xi| <= 1), (2 - |xi|)^3 / 6 (1 <= |xi| <= 2). */
 static void spline_pieces(int r, double t, double* w, double* dw) {
+  if (r == 3) {
+    double u = 1.0 - t;
+    w[0] = u * u * u / 6.0;                    /* node base-1, xi = t + 1 */
+    w[1] = 2.0 / 3.0 - t * t + 0.5 * t * t * t; /* node base,   xi = t     */
+    w[2] = 2.0 / 3.0 - u * u + 0.5 * u * u * u; /* node base+1, |xi| = 1 - t */
+    w[3] = t * t * t / 6.0;                    /* node base+2, |xi| = 2 - t */
+    dw[0] = -0.5 * u * u;
+    dw[1] = -2.0 * t + 1.5 * t * t;
+    dw[2] = 2.0 * u - 1.5 * u * u;
+    dw[3] = 0.5 * t * t;
+    return;
+  }
   if (r == 1) {
     w[0] = 1.0 - t;  /* node base,   xi = t     */
     w[1] = t;        /* node base+1, xi = t - 1 */
@@ -233,14 +247,14 @@ static int cmp_double(const void* a, const void* b) {
 #define MAX_BREAKS 512
 
 /* sorted, de-duplicated breakpoints 0 = s_0 < ... < s_M = 1 of the orbit
-   x(s) = x0 + s d.  Knots sit at k H (degree 1) and (k + 1/2) H (degree 2).
+   x(s) = x0 + s d.  Knots sit at k H (degrees 1, 3) and (k + 1/2) H (degree 2).
    Returns the number of breakpoints, or -1 if the orbit is absurdly long. */
 static int orbit_breakpoints(const grid* G, int r, const double x0[3], const double d[3],
                              double* s) {
   int ns = 0;
   s[ns++] = 0.0;
   s[ns++] = 1.0;
-  double off = (r == 1) ? 0.0 : 0.5;
+  double off = (r == 2) ? 0.5 : 0.0;
   for (int a = 0; a < 3; ++a) {
     if (d[a] == 0.0) continue; /* no breakpoints from a coordinate that does not move */
     double H = G->H[a];
@@ -263,7 +277,7 @@ static int orbit_breakpoints(const grid* G, int r, const double x0[3], const dou
   return m;
 }
 
-/* Integrals of one orbit piece against its stencil (at most 3x3x3 nodes):
+/* Integrals of one orbit piece against its stencil (at most 4x4x4 nodes):
      Iw[nu]   = int S_nu(x(s)) ds
      X[j][nu] = int d_j S_nu(x(s)) ds
      Y[j][nu] = int (s - s0) d_j S_nu(x(s)) ds
@@ -273,9 +287,9 @@ typedef struct {
   long first[3];
   int w; /* stencil width r + 1 */
   double s0;
-  double Iw[27];
-  double X[3][27];
-  double Y[3][27];
+  double Iw[64];
+  double X[3][64];
+  double Y[3][64];
 } piece;
 
 static int pidx(int w, int i, int j, int k) { return (i * w + j) * w + k; }
@@ -343,7 +357,7 @@ static void piece_add_point(const grid* G, int r, const double x0[3], const doub
                             double wt, const long base[3], piece* o) {
   int w = r + 1;
   double eta = s - o->s0;
-  double wv[3][3], dwv[3][3];
+  double wv[3][4], dwv[3][4];
   for (int a = 0; a < 3; ++a) {
     double u = (x0[a] + s * d[a]) / G->H[a];
     spline_pieces(r, u - (double)base[a], wv[a], dwv[a]);
@@ -423,7 +437,7 @@ static int orbit_pieces(const orc_sim* S, const double x0[3], const double d[3],
 static void interp_point(const grid* G, int r, const double xin[3], const double* F, int ncomp,
                          double* out) {
   int w = r + 1;
-  double wv[3][3], dwv[3][3];
+  double wv[3][4], dwv[3][4];
   long first[3];
   for (int a = 0; a < 3; ++a) {
     double x = wrap_pos(xin[a], G->L[a]);
@@ -509,7 +523,7 @@ static void deposit_point_charge(const grid* G, int r, int64_t np, const double*
                                  double* rho) {
   int w = r + 1;
   for (int64_t i = 0; i < np; ++i) {
-    double wv[3][3], dwv[3][3];
+    double wv[3][4], dwv[3][4];
     long first[3];
     for (int a = 0; a < 3; ++a) {
       double xa = wrap_pos(x[(int64_t)a * np + i], G->L[a]);
@@ -815,7 +829,7 @@ void orc_set_trace(orc_sim* S, double* w, double* g, int max_passes) {
 int orc_check_config(const orc_cfg* c) {
   for (int a = 0; a < 3; ++a)
     if (c->n[a] < 2 || !(c->L[a] > 0.0)) return -1;
-  if (c->r != 1 && c->r != 2) return -1;
+  if (c->r < 1 || c->r > 3) return -1;
   if (!(c->dt > 0.0) || !(c->kappa > 0.0) || !(c->sigma1 > 0.0) || !(c->sigma2 > 0.0)) return -1;
   /* Maxwell scaling sigma1 = kappa^2 sigma2 (eq. Maxwell_scaling), to roundoff */
   double lhs = c->sigma1, rhs = c->kappa * c->kappa * c->sigma2;

@@ -15,7 +15,7 @@ import numpy as np
 
 
 def M(r: int, xi: float) -> float:
-    """Centred cardinal B-spline of degree r (1: hat, 2: quadratic)."""
+    """Centred cardinal B-spline of degree r (1: hat, 2: quadratic, 3: cubic)."""
     a = abs(xi)
     if r == 1:
         return max(0.0, 1.0 - a)
@@ -24,6 +24,12 @@ def M(r: int, xi: float) -> float:
             return 0.75 - a * a
         if a <= 1.5:
             return 0.5 * (1.5 - a) ** 2
+        return 0.0
+    if r == 3:
+        if a <= 1.0:
+            return 2.0 / 3.0 - a * a + 0.5 * a ** 3
+        if a <= 2.0:
+            return (2.0 - a) ** 3 / 6.0
         return 0.0
     raise ValueError(r)
 
@@ -39,6 +45,12 @@ def dM(r: int, xi: float) -> float:
             return -2.0 * xi
         if a <= 1.5:
             return -s * (1.5 - a)
+        return 0.0
+    if r == 3:
+        if a <= 1.0:
+            return s * (-2.0 * a + 1.5 * a * a)
+        if a <= 2.0:
+            return -s * 0.5 * (2.0 - a) ** 2
         return 0.0
     raise ValueError(r)
 
@@ -93,8 +105,8 @@ def shape_weights(r, x, n, L):
 def knot_crossings(r, x0, d, n, L, scan=4000):
     """Orbit parameters s in (0,1) where x0 + s d crosses a spline knot, found by
     bisection on the index of the polynomial piece (knots at integers for the
-    hat, at half-integers for the quadratic spline)."""
-    off = 0.0 if r == 1 else 0.5
+    hat and the cubic spline, at half-integers for the quadratic spline)."""
+    off = 0.5 if r == 2 else 0.0
     out = []
     for a in range(3):
         if d[a] == 0.0:

@@ -39,7 +39,8 @@ def test_ktilde_symbols():
 def test_config_validation():
     bad = O.make_cfg(n=N, L=L, dt=0.1, kappa=2.0, sigma1=1.0, sigma2=1.0)  # sigma1 != kappa^2 sigma2
     assert O.lib().orc_check_config(bad) != 0
-    assert O.lib().orc_check_config(O.make_cfg(n=N, L=L, dt=0.1, r=3)) != 0
+    assert O.lib().orc_check_config(O.make_cfg(n=N, L=L, dt=0.1, r=4)) != 0
+    assert O.lib().orc_check_config(O.make_cfg(n=N, L=L, dt=0.1, r=3)) == 0
     assert O.lib().orc_check_config(O.make_cfg(n=N, L=L, dt=0.1, kappa=2.0, sigma1=4.0, sigma2=1.0)) == 0
 
 

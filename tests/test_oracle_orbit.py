@@ -35,7 +35,7 @@ def rand_orbits(rng, k, scale_cells=1.3, n=N, Lb=L):
 # --------------------------------------------------------------------------
 # shapes
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_point_shape_matches_textbook_bspline(r):
     """S_g(x) from the oracle's interpolant equals prod_a M_r(x_a/H_a - g_a)."""
     S = sim(r)
@@ -58,12 +58,25 @@ def test_point_shape_matches_textbook_bspline(r):
         np.testing.assert_allclose(got, want, rtol=0, atol=2e-15)
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_point_partition_of_unity(r):
     S = sim(r)
     rng = np.random.default_rng(2)
     xs = np.stack([rng.uniform(0, L[a], size=200) for a in range(3)], axis=1)
     np.testing.assert_allclose(S.interp(xs, np.ones((1,) + N))[:, 0], 1.0, atol=1e-15)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_textbook_bspline_matches_scipy(r):
+    """The reference shapes used below equal scipy's cardinal B-spline on the
+    r + 2 uniform knots centred on the node, with its derivative."""
+    from scipy.interpolate import BSpline
+    knots = np.arange(r + 2) - (r + 1) / 2.0
+    b = BSpline.basis_element(knots, extrapolate=False)
+    xs = np.linspace(knots[0], knots[-1], 397)[1:-1]
+    xs = xs[np.min(np.abs(xs[:, None] - knots[None, :]), axis=1) > 1e-6]
+    np.testing.assert_allclose([B.M(r, x) for x in xs], b(xs), rtol=0, atol=1e-14)
+    np.testing.assert_allclose([B.dM(r, x) for x in xs], b.derivative()(xs), rtol=0, atol=1e-13)
 
 
 def test_gauss_legendre_matches_numpy():
@@ -77,7 +90,7 @@ def test_gauss_legendre_matches_numpy():
 # --------------------------------------------------------------------------
 # breakpoints (eq. breakpoint-set)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_breakpoints_match_bisection(r):
     S = sim(r)
     rng = np.random.default_rng(3)
@@ -102,7 +115,7 @@ def test_breakpoints_static_axis_and_exact_knot_start():
 # --------------------------------------------------------------------------
 # orbit weights and D versus brute force
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("r,analytic", [(1, True), (1, False), (2, False)])
+@pytest.mark.parametrize("r,analytic", [(1, True), (1, False), (2, False), (3, False)])
 def test_sbar_matches_bruteforce(r, analytic):
     S = sim(r, analytic=analytic)
     rng = np.random.default_rng(4 + r)
@@ -117,7 +130,7 @@ def test_sbar_matches_bruteforce(r, analytic):
         np.testing.assert_allclose(got, want, atol=2e-15)
 
 
-@pytest.mark.parametrize("r,analytic", [(1, True), (1, False), (2, False)])
+@pytest.mark.parametrize("r,analytic", [(1, True), (1, False), (2, False), (3, False)])
 def test_D_and_gathers_match_bruteforce(r, analytic):
     S = sim(r, analytic=analytic)
     rng = np.random.default_rng(10 + r)
@@ -155,7 +168,7 @@ def test_appendix_closed_forms_equal_16_point_gauss():
 # --------------------------------------------------------------------------
 # exact identities
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_orbit_partition_of_unity(r):
     """sum_g Sbar_ig = 1 for every particle (App. A)."""
     S = sim(r)
@@ -167,7 +180,7 @@ def test_orbit_partition_of_unity(r):
     assert out["npieces"].max() >= 4  # orbits really cross several knots
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_lemma1_exact_orbit_chain_rule(r):
     """A_h^{n+1}(x^{n+1}) - A_h^n(x^n) = dt Ubar + dt (D A) vbar (Lemma 1)
     for arbitrary mesh A^n, A^{n+1} with U^{n+1/2} = (A^{n+1} - A^n)/dt."""
@@ -187,7 +200,7 @@ def test_lemma1_exact_orbit_chain_rule(r):
 
 def test_deposit_gather_identity():
     """sum_i q_i vbar_i . G_i = sum_g J_g . G_g dV (eq. deposit-gather-identity)."""
-    for r in (1, 2):
+    for r in (1, 2, 3):
         S = sim(r)
         rng = np.random.default_rng(11)
         x0s, ds = rand_orbits(rng, 300, scale_cells=1.5)
@@ -205,7 +218,7 @@ def test_deposit_gather_identity():
 # --------------------------------------------------------------------------
 # special cases
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_zero_displacement_reduces_to_point_values(r):
     S = sim(r)
     rng = np.random.default_rng(12)
@@ -217,13 +230,13 @@ def test_zero_displacement_reduces_to_point_values(r):
     out = S.orbit_gather(x0s, ds, F, F, A0, A1)
     for i, x in enumerate(x0s):
         np.testing.assert_allclose(out["gphibar"][i], B.point_values(r, x, N, L, F), atol=1e-14)
-        if r == 2:  # the hat's gradient is discontinuous at the nodes; use quadratic here
+        if r >= 2:  # the hat's gradient is discontinuous at the nodes
             _, g0 = B.point_values(r, x, N, L, A0, deriv=True)
             _, g1 = B.point_values(r, x, N, L, A1, deriv=True)
             np.testing.assert_allclose(out["D"][i], 0.5 * (g0 + g1), atol=1e-12)
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_uniform_A_gives_zero_D(r):
     S = sim(r)
     rng = np.random.default_rng(13)
@@ -234,7 +247,7 @@ def test_uniform_A_gives_zero_D(r):
     assert np.abs(out["D"]).max() < 1e-13
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_static_1d_field_gives_discrete_gradient_quotient(r):
     """Static A varying along x, motion along x only: [D A]_lx is the
     difference quotient (A_h(x1) - A_h(x0)) / (x1 - x0)."""
@@ -271,7 +284,7 @@ def one_d_residual(r, crossing, split):
     A0[0] = (np.sin(2 * math.pi * x) + 0.5 * np.cos(6 * math.pi * x)).reshape(-1, 1, 1)
     A1[0] = (np.sin(2 * math.pi * x + 0.3) + 0.4 * np.cos(4 * math.pi * x)).reshape(-1, 1, 1)
     U = (A1 - A0) / dt
-    knot = 5.0 if r == 1 else 5.5
+    knot = 5.5 if r == 2 else 5.0
     length = 0.5  # path length in cells
     x0 = np.array([(knot - (length - crossing)) * h, 0.1 * Lb[1], 0.2 * Lb[2]])
     d = np.array([length * h, 0.0, 0.0])
@@ -282,7 +295,7 @@ def one_d_residual(r, crossing, split):
 
 
 def test_split_restores_chain_rule_unsplit_does_not():
-    for r in (1, 2):
+    for r in (1, 2, 3):
         for c in (0.01, 0.10):
             assert one_d_residual(r, c, split=True) < 2e-15
     u1 = [one_d_residual(1, c, split=False) for c in (0.01, 0.10)]
@@ -290,3 +303,5 @@ def test_split_restores_chain_rule_unsplit_does_not():
     assert u1[0] > 1e-6 and u1[1] > u1[0]          # grows with crossing size
     assert u2 < u1[1]                               # smoother spline, smaller defect
     assert u2 > 1e-10                               # ... but not removed
+    u3 = one_d_residual(3, 0.10, split=False)
+    assert 1e-12 < u3 < u2                          # smoother still

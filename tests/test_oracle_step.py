@@ -67,7 +67,7 @@ def test_initial_state_poisson_and_gauss():
     np.testing.assert_allclose(st["P"], wl.m * wl.v, rtol=0, atol=0)
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 @pytest.mark.parametrize("p", [0, 2])
 def test_per_particle_work_identity_every_iterate(r, p):
     wl = small_random(r=r)
@@ -108,7 +108,7 @@ def test_per_particle_work_identity_every_iterate(r, p):
                                atol=1e-14 * np.abs(s1["P"]).max())
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_step_energy_error_closed_form(r):
     wl = small_random(r=r)
     S = make(wl)
@@ -132,7 +132,7 @@ def test_step_energy_error_closed_form(r):
     assert abs(e["R_particle"] - closed) < 1e-13 * abs(e0["E_total"]) + 1e-3 * abs(closed)
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_energy_conserved_and_constraints_at_roundoff(r):
     wl = small_random(r=r, np_=800, vth=0.08, dt=0.3)
     S = make(wl, tol=1e-13, pmax=40)
@@ -157,13 +157,15 @@ def analytic_growth_rate(a, wp2):
 
 
 @pytest.mark.slow
-def test_two_stream_linear_growth_rate():
-    """16x4x4 two-stream (k1 v0 / omega_p = 0.6, hat shape, dt = 0.1) seeded
-    with a 1e-6 velocity perturbation; |E_x(k1)| grows at the analytic rate."""
+@pytest.mark.parametrize("r", [1, 3])
+def test_two_stream_linear_growth_rate(r):
+    """16x4x4 two-stream (k1 v0 / omega_p = 0.6, dt = 0.1, hat or cubic shape)
+    seeded with a 1e-6 velocity perturbation; |E_x(k1)| grows at the analytic
+    rate, with omega_p^2 reduced by the shape factor sinc^(2 (r + 1))(k1 H / 2)."""
     wl = W.two_stream("c1")
     v = wl.v.copy()
     v[0] = np.sign(v[0]) * W.V0 + 1e-6 * np.sin(W.K1 * wl.x[0])
-    S = O.OracleSim(O.make_cfg(**wl.cfg_kwargs()), wl.np)
+    S = O.OracleSim(O.make_cfg(**{**wl.cfg_kwargs(), "r": r}), wl.np)
     S.init_particles(wl.x, v, wl.q, wl.m, wl.n0)
     nsteps = 270
     amp, Es = [], []
@@ -181,7 +183,7 @@ def test_two_stream_linear_growth_rate():
     g0 = analytic_growth_rate(a, 1.0)
     H = wl.L[0] / wl.n[0]
     sinc = math.sin(W.K1 * H / 2) / (W.K1 * H / 2)
-    g_shape = analytic_growth_rate(a, sinc ** 4)
+    g_shape = analytic_growth_rate(a, sinc ** (2 * (r + 1)))
     assert abs(g0 - 0.353392) < 1e-5
     assert abs(gamma - g0) < 0.03 * g0, (gamma, g0)
     assert abs(gamma - g_shape) < 0.015 * g_shape, (gamma, g_shape)
