@@ -58,7 +58,8 @@ typedef enum { ECPIC_FP64 = 0, ECPIC_MIXED = 1 } ecpic_precision;
 
 typedef struct {
   int32_t n[3];                 /* mesh points per axis: powers of two, 4 <= n <= 256 */
-  int32_t spline_degree;        /* r = 1 (linear B-spline, App. A/B) or 2 (quadratic) */
+  int32_t spline_degree;        /* r = 1 (linear B-spline, App. A/B), 2 (quadratic) or 3
+                                   (cubic; Table 2's degrees) */
   double L[3];                  /* periodic box lengths; H_a = L_a / n_a */
   double kappa;                 /* nondimensional speed of light (Sec. 2.1) */
   double sigma1, sigma2;        /* source coefficients; must satisfy sigma1 = kappa^2 sigma2
@@ -71,7 +72,7 @@ typedef struct {
                                    stencil of its own cell (the paper's unsplit comparison
                                    runs; FP64 only, no adjoint) */
   int32_t quad_points;          /* Gauss-Legendre points, 0..16; 0 = smallest exact rule
-                                   (2 n_q - 1 >= 3 r): 2 for r = 1, 4 for r = 2.  Split pieces
+                                   (2 n_q - 1 >= 3 r): 2, 4, 5 for r = 1, 2, 3.  Split pieces
                                    are polynomial, so every rule with at least that many
                                    points gives the same integrals and the smallest one is
                                    used; without splitting the given rule is used as is */

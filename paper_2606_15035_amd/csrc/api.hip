@@ -52,8 +52,8 @@ ecpic_status check_config(const ecpic_config* c, int64_t np) {
     if (!(c->L[a] > 0.0) || !std::isfinite(c->L[a]))
       return fail(ECPIC_EINVAL, "L[%d] must be positive", a);
   }
-  if (c->spline_degree != 1 && c->spline_degree != 2)
-    return fail(ECPIC_EINVAL, "spline_degree must be 1 or 2");
+  if (c->spline_degree < 1 || c->spline_degree > 3)
+    return fail(ECPIC_EINVAL, "spline_degree must be 1, 2 or 3");
   if (!(c->dt > 0.0) || !(c->kappa > 0.0) || !(c->sigma1 > 0.0) || !(c->sigma2 > 0.0))
     return fail(ECPIC_EINVAL, "dt, kappa, sigma1, sigma2 must be positive");
   const double lhs = c->sigma1, rhs = c->kappa * c->kappa * c->sigma2;
@@ -62,7 +62,7 @@ ecpic_status check_config(const ecpic_config* c, int64_t np) {
                 rhs);
   if (c->picard_max < 0 || c->picard_max > 1000) return fail(ECPIC_EINVAL, "picard_max out of range");
   if (!(c->picard_tol >= 0.0)) return fail(ECPIC_EINVAL, "picard_tol must be >= 0");
-  const int nq_min = c->spline_degree == 1 ? 2 : 4;
+  const int nq_min = (3 * c->spline_degree + 2) / 2;  // smallest n_q with 2 n_q - 1 >= 3 r
   if (c->split_orbit_at_knots != 0 && c->split_orbit_at_knots != 1)
     return fail(ECPIC_EINVAL, "split_orbit_at_knots must be 0 or 1");
   if (c->quad_points < 0 || c->quad_points > kMaxRule)
@@ -110,7 +110,7 @@ QuadRule gauss_rule01(int n) {
 }
 
 int quad_rule_points(const ecpic_config* c) {
-  return c->quad_points > 0 ? c->quad_points : (c->spline_degree == 1 ? 2 : 4);
+  return c->quad_points > 0 ? c->quad_points : (3 * c->spline_degree + 2) / 2;
 }
 
 int ilog2i(int n) {
@@ -254,7 +254,8 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->sc.red = w.take<double>(S_NSLOTS);
   S->sc.spread = w.take<double>((size_t)S_NSLOTS * kSpread * kSpreadStride);
   const int64_t maxblk = std::max<int64_t>(
-      std::max<int64_t>(particle_blocks(np), scatter_blocks(np)), mesh_blocks(nc));
+      std::max<int64_t>(particle_blocks(np), scatter_blocks(np, S->cfg.spline_degree)),
+      mesh_blocks(nc));
   S->sc.part_stride = std::max<int64_t>((int64_t)kMaxSumValues * (maxblk > 0 ? maxblk : 1),
                                         (int64_t)kAndersonSums * anderson_dot_blocks(3 * np));
   S->sc.part = w.take<double>((size_t)P_NSITES * S->sc.part_stride);
@@ -595,7 +596,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     if (mk >= 2) launch_anderson_dots(s, mk, n3, av, S->sc);
     {
       const FinishJob jobs[6] = {{P_CN, (int)mesh_blocks(nc), 3, S_JE},
-                                 {P_JS, (int)scatter_blocks(S->np), 1, S_JS},
+                                 {P_JS, (int)scatter_blocks(S->np, r), 1, S_JS},
                                  {0, 0, 2, S_DVMAX, F_SPREAD_MAX},
                                  {0, 0, 1, S_BAD, F_SPREAD_MAX},
                                  {0, 0, 1, S_PIECES, F_SPREAD_SUM},

@@ -113,7 +113,7 @@ void launch_anderson_update(hipStream_t s, int mk, int64_t n, const AndersonVecs
 // host: gamma (mk values) from the anderson_sums(mk) sums of k_aa_dots
 void anderson_gamma(int mk, const double* sums, double* gamma);
 // grid sizes of the producing kernels
-int64_t scatter_blocks(int64_t np);
+int64_t scatter_blocks(int64_t np, int r);
 int64_t particle_blocks(int64_t np);
 int64_t mesh_blocks(int64_t ncell);
 

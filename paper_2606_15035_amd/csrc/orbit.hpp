@@ -3,8 +3,9 @@
 // Shapes: centred cardinal B-splines of degree r on nodes x_g = g H
 // (eq. Ah-mesh).  A point at cell coordinate u = x / H is written against a
 // base node: degree 1 uses floor(u) and the two nodes {base, base+1};
-// degree 2 uses the nearest node floor(u + 1/2) and {base-1, base, base+1}.
-// Knots sit at integer u (degree 1) and half-integer u (degree 2).
+// degree 2 uses the nearest node floor(u + 1/2) and {base-1, base, base+1};
+// degree 3 uses floor(u) and {base-1, ..., base+2}.  Knots sit at integer u
+// (odd degrees) and half-integer u (degree 2).
 //
 // Orbits: x(s) = x0 + s d, 0 <= s <= 1, with unwrapped displacement d
 // (eq. particle-orbit).  The breakpoints are the parameters s in (0, 1) where
@@ -125,6 +126,50 @@ struct Spline<2> {
   }
 };
 
+template <>
+struct Spline<3> {
+  static constexpr int W = 4;
+  static constexpr double knot_off = 0.0;  // knots at u = k
+  static constexpr double base_off = 0.0;  // base = floor(u)
+  static constexpr int first_off = -1;     // stencil = {base - 1, ..., base + 2}
+  // M3(xi) = 2/3 - xi^2 + |xi|^3 / 2 (|xi| <= 1), (2 - |xi|)^3 / 6 (1 <= |xi| <= 2);
+  // node base - 1 + k sits at xi = t + 1 - k
+  __device__ __forceinline__ static void w(double t, double* o) {
+    const double u = 1.0 - t, t2 = t * t, u2 = u * u;
+    o[0] = (1.0 / 6.0) * u2 * u;
+    o[1] = (2.0 / 3.0) - t2 + 0.5 * t2 * t;
+    o[2] = (2.0 / 3.0) - u2 + 0.5 * u2 * u;
+    o[3] = (1.0 / 6.0) * t2 * t;
+  }
+  __device__ __forceinline__ static void wd(double t, double* o, double* d) {
+    const double u = 1.0 - t, t2 = t * t, u2 = u * u;
+    o[0] = (1.0 / 6.0) * u2 * u;
+    o[1] = (2.0 / 3.0) - t2 + 0.5 * t2 * t;
+    o[2] = (2.0 / 3.0) - u2 + 0.5 * u2 * u;
+    o[3] = (1.0 / 6.0) * t2 * t;
+    d[0] = -0.5 * u2;
+    d[1] = -2.0 * t + 1.5 * t2;
+    d[2] = 2.0 * u - 1.5 * u2;
+    d[3] = 0.5 * t2;
+  }
+  __device__ __forceinline__ static void wk(int k, double t, double& w, double& dw) {
+    const double u = 1.0 - t;
+    if (k == 0) {
+      w = (1.0 / 6.0) * u * u * u;
+      dw = -0.5 * u * u;
+    } else if (k == 1) {
+      w = (2.0 / 3.0) - t * t + 0.5 * t * t * t;
+      dw = -2.0 * t + 1.5 * t * t;
+    } else if (k == 2) {
+      w = (2.0 / 3.0) - u * u + 0.5 * u * u * u;
+      dw = 2.0 * u - 1.5 * u * u;
+    } else {
+      w = (1.0 / 6.0) * t * t * t;
+      dw = 0.5 * t * t;
+    }
+  }
+};
+
 // Gauss-Legendre nodes and weights on [-1, 1] (Abramowitz & Stegun, Table 25.4).
 template <int NQ>
 struct Gauss;
@@ -146,6 +191,18 @@ struct Gauss<4> {
   __device__ __forceinline__ static double w(int q) {
     const double wa = 0.34785484513745385737, wb = 0.65214515486254614263;
     return (q == 0 || q == 3) ? wa : wb;
+  }
+};
+
+template <>
+struct Gauss<5> {
+  __device__ __forceinline__ static double x(int q) {
+    const double a = 0.90617984593866399280, b = 0.53846931010568309104;
+    return q == 0 ? -a : (q == 1 ? -b : (q == 2 ? 0.0 : (q == 3 ? b : a)));
+  }
+  __device__ __forceinline__ static double w(int q) {
+    const double wa = 0.23692688505618908751, wb = 0.47862867049936646804;
+    return (q == 0 || q == 4) ? wa : ((q == 1 || q == 3) ? wb : 0.56888888888888888889);
   }
 };
 

@@ -9,6 +9,8 @@
 // run of contiguous loads.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 #include "orbit.hpp"
 #include "reduce.hpp"
@@ -26,6 +28,10 @@ struct Quad<1> {
 template <>
 struct Quad<2> {
   static constexpr int NQ = 4;  // n_q = 4 for r = 2
+};
+template <>
+struct Quad<3> {
+  static constexpr int NQ = 5;  // n_q = 5 for r = 3
 };
 
 // ---- field accessors ------------------------------------------------------
@@ -473,11 +479,16 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const T* __r
 // relative to the chunk's first particle, one node of margin per side);
 // pass 2 accumulates the current in an LDS tile over that box; the tile is
 // then flushed with one global atomic per non-zero node value.  A chunk whose
-// box exceeds the tile adds straight to global memory.
+// box exceeds the tile adds straight to global memory.  Cubic stencils reach
+// two nodes further per axis, so their chunks hold half as many particles
+// (the box of 32 cells plus margins would overflow the tile).
 constexpr int kTileNodes = 2048;
-constexpr int kChunk = 2048;
-constexpr int kPerThread = kChunk / kBlock;  // particles per thread
-constexpr int kSlot = kChunk / kWave;        // sorted particles per lane slot
+template <int R>
+struct ScatterChunk {
+  static constexpr int kChunk = R >= 3 ? 1024 : 2048;
+  static constexpr int kPerThread = kChunk / kBlock;  // particles per thread
+  static constexpr int kSlot = kChunk / kWave;        // sorted particles per lane slot
+};
 
 __device__ __forceinline__ int min_image(int raw, int n) {
   int r = raw % n;
@@ -515,8 +526,9 @@ __device__ __forceinline__ void block_min_ints(int (&v)[M]) {
   __syncthreads();
 }
 
+template <int R>
 __device__ __forceinline__ int64_t chunk_particle(int64_t base, int k) {
-  return base + (int64_t)(threadIdx.x % kWave) * kSlot + threadIdx.x / kWave +
+  return base + (int64_t)(threadIdx.x % kWave) * ScatterChunk<R>::kSlot + threadIdx.x / kWave +
          (int64_t)(kBlock / kWave) * k;
 }
 
@@ -551,6 +563,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
   __shared__ double tile[3 * kTileNodes];  // FIX: int64 quanta in the same bytes
   __shared__ int s_ref[3];
   unsigned long long* tile_q = reinterpret_cast<unsigned long long*>(tile);
+  constexpr int kChunk = ScatterChunk<R>::kChunk, kPerThread = ScatterChunk<R>::kPerThread;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   double js[1] = {0.0};
   double bad = 0.0;
@@ -566,7 +579,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
   // pass 1: node box of the chunk's orbits
   int rmin[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, rmax[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
   for (int k = 0; k < kPerThread; ++k) {
-    const int64_t i = chunk_particle(base, k);
+    const int64_t i = chunk_particle<R>(base, k);
     if (i >= P.np) continue;
     double x0[3], d[3], vb[3];
     orbit_of(P, st, vit, i, x0, d, vb);
@@ -601,7 +614,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
   const double qdv = P.q / P.G.dV;
   const int64_t nc = P.G.ncell;
   for (int k = 0; k < kPerThread; ++k) {
-    const int64_t i = chunk_particle(base, k);
+    const int64_t i = chunk_particle<R>(base, k);
     if (i >= P.np) continue;
     double x0[3], d[3], vb[3], c3[3];
     orbit_of(P, st, vit, i, x0, d, vb);
@@ -657,8 +670,74 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
             }
       }
     };
+    // Cubic stencils (64 nodes): the weights are never held all at once.
+    // Per quadrature point the three 1-D factors are kept (wq folded into the
+    // x factor); each node's weight is summed over the points when it is
+    // deposited.  Same integrals, a quarter of the registers.
+    auto deposit_factored = [&](const double (&X)[Quad<R>::NQ][W],
+                                const double (&Y)[Quad<R>::NQ][W],
+                                const double (&Z)[Quad<R>::NQ][W], const int* f) {
+      constexpr int NQ = Quad<R>::NQ;
+      const int ox = f[0] - s_ref[0] + shift[0] - tlo[0];
+      const int oy = f[1] - s_ref[1] + shift[1] - tlo[1];
+      const int oz = f[2] - s_ref[2] + shift[2] - tlo[2];
+      const bool inside = use_tile && ox >= 0 && oy >= 0 && oz >= 0 && ox + W <= dim[0] &&
+                          oy + W <= dim[1] && oz + W <= dim[2];
+#pragma unroll
+      for (int a = 0; a < W; ++a)
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+          double xy[NQ];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) xy[q] = X[q][a] * Y[q][b];
+#pragma unroll
+          for (int c = 0; c < W; ++c) {
+            double w = 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) w += xy[q] * Z[q][c];
+            if (inside) {
+              const int t = ((ox + a) * dim[1] + (oy + b)) * dim[2] + (oz + c);
+#pragma unroll
+              for (int l = 0; l < 3; ++l) {
+                if constexpr (FIX)
+                  atomicAdd(&tile_q[3 * t + l], quantize(w * c3[l], out.fix_scale));
+                else
+                  atomicAdd(&tile[3 * t + l], w * c3[l]);
+              }
+            } else {
+              const int64_t g = node_index(P.G, f[0] + a, f[1] + b, f[2] + c);
+#pragma unroll
+              for (int l = 0; l < 3; ++l) {
+                if constexpr (FIX)
+                  atomicAdd(out.Jfix + l * nc + g, quantize(w * c3[l], out.fix_scale));
+                else
+                  unsafeAtomicAdd(out.J + l * nc + g, w * c3[l]);
+              }
+            }
+          }
+        }
+    };
     bool ok = true;
-    if constexpr (SPLIT) {
+    if constexpr (SPLIT && R >= 3) {
+      ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
+        constexpr int NQ = Quad<R>::NQ;
+        double base[3], sq[NQ], wq[NQ], X[NQ][W], Y[NQ][W], Z[NQ][W];
+        int f[3];
+        piece_rule<R>(P.G, x0, d, s0, s1, base, sq, wq);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const double sv = sq[q];
+          Spline<R>::w((x0[0] + sv * d[0]) * P.G.invH[0] - base[0], X[q]);
+          Spline<R>::w((x0[1] + sv * d[1]) * P.G.invH[1] - base[1], Y[q]);
+          Spline<R>::w((x0[2] + sv * d[2]) * P.G.invH[2] - base[2], Z[q]);
+#pragma unroll
+          for (int a = 0; a < W; ++a) X[q][a] *= wq[q];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) f[a] = to_int_clamped(base[a]) + Spline<R>::first_off;
+        deposit_factored(X, Y, Z, f);
+      });
+    } else if constexpr (SPLIT) {
       ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
         double Iw[W][W][W];
         int f[3];
@@ -1159,10 +1238,24 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 }  // namespace
 
-int64_t scatter_blocks(int64_t np) { return (np + kChunk - 1) / kChunk; }
+int64_t scatter_blocks(int64_t np, int r) {
+  const int64_t c = r >= 3 ? ScatterChunk<3>::kChunk : ScatterChunk<2>::kChunk;
+  return (np + c - 1) / c;
+}
 int64_t particle_blocks(int64_t np) { return (np + kBlock - 1) / kBlock; }
 
 // ---- launchers ---------------------------------------------------------------
+
+// f(std::integral_constant<int, r>{}) for the spline degree r = 1, 2, 3
+template <class F>
+void by_degree(int r, F&& f) {
+  if (r == 1)
+    f(std::integral_constant<int, 1>{});
+  else if (r == 2)
+    f(std::integral_constant<int, 2>{});
+  else
+    f(std::integral_constant<int, 3>{});
+}
 
 template <class PS>
 void launch_extrapolate(hipStream_t s, int64_t np, const PS& st, double* vit) {
@@ -1174,20 +1267,18 @@ template <class PS>
 void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
                     CurrentOut out, Scratch sc) {
   if (P.np <= 0) return;
-  const unsigned nblk = (unsigned)((P.np + kChunk - 1) / kChunk);
+  const unsigned nblk = (unsigned)scatter_blocks(P.np, r);
   if constexpr (!PS::kMixed) {
     if (!P.split) {
-      if (r == 1)
-        k_scatter<1, PS, false><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
-      else
-        k_scatter<2, PS, false><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+      by_degree(r, [&](auto R) {
+        k_scatter<R.value, PS, false><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+      });
       return;
     }
   }
-  if (r == 1)
-    k_scatter<1, PS, true><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
-  else
-    k_scatter<2, PS, true><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+  by_degree(r, [&](auto R) {
+    k_scatter<R.value, PS, true><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+  });
 }
 
 template <class PS>
@@ -1204,19 +1295,11 @@ void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
                                                               prev)
   if constexpr (!PS::kMixed) {
     if (!P.split) {
-      if (r == 1) {
-        ECPIC_GATHER_PAIR(1, false);
-      } else {
-        ECPIC_GATHER_PAIR(2, false);
-      }
+      by_degree(r, [&](auto R) { ECPIC_GATHER_PAIR(R.value, false); });
       return;
     }
   }
-  if (r == 1) {
-    ECPIC_GATHER_PAIR(1, true);
-  } else {
-    ECPIC_GATHER_PAIR(2, true);
-  }
+  by_degree(r, [&](auto R) { ECPIC_GATHER_PAIR(R.value, true); });
 #undef ECPIC_GATHER_PAIR
 }
 
@@ -1227,17 +1310,15 @@ void launch_sweep(hipStream_t s, int r, const StepParams& P, const PS& st, const
   AosFields F{gbuf};
   if constexpr (!PS::kMixed) {
     if (!P.split) {
-      if (r == 1)
-        k_sweep<1, PS, false><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
-      else
-        k_sweep<2, PS, false><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
+      by_degree(r, [&](auto R) {
+        k_sweep<R.value, PS, false><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
+      });
       return;
     }
   }
-  if (r == 1)
-    k_sweep<1, PS, true><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
-  else
-    k_sweep<2, PS, true><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
+  by_degree(r, [&](auto R) {
+    k_sweep<R.value, PS, true><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, F, Uhalf, sc);
+  });
 }
 
 template <class PS>
@@ -1256,10 +1337,9 @@ void launch_kinetic(hipStream_t s, const StepParams& P, const PS& st, Scratch sc
 template <class PS>
 void launch_deposit_rho(hipStream_t s, int r, const StepParams& P, const PS& st, CurrentOut out) {
   if (P.np <= 0) return;
-  if (r == 1)
-    k_deposit_rho<1, PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, out);
-  else
-    k_deposit_rho<2, PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, out);
+  by_degree(r, [&](auto R) {
+    k_deposit_rho<R.value, PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, out);
+  });
 }
 
 template <class PS>
@@ -1308,17 +1388,12 @@ void launch_orbit_gather_soa(hipStream_t s, int r, const QuadRule* rule, const G
   SoaFields F{gphi, A0, A1, G.ncell};
   const QuadRule ru = rule ? *rule : QuadRule{};
   const unsigned nb = blocks_for(n);
-  if (rule) {
-    if (r == 1)
-      k_orbit_gather_soa<1, false><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, F, U, out);
+  by_degree(r, [&](auto R) {
+    if (rule)
+      k_orbit_gather_soa<R.value, false><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, F, U, out);
     else
-      k_orbit_gather_soa<2, false><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, F, U, out);
-  } else {
-    if (r == 1)
-      k_orbit_gather_soa<1, true><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, F, U, out);
-    else
-      k_orbit_gather_soa<2, true><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, F, U, out);
-  }
+      k_orbit_gather_soa<R.value, true><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, F, U, out);
+  });
 }
 
 void launch_orbit_deposit_soa(hipStream_t s, int r, const QuadRule* rule, const Grid& G,
@@ -1327,17 +1402,12 @@ void launch_orbit_deposit_soa(hipStream_t s, int r, const QuadRule* rule, const 
   if (n <= 0) return;
   const QuadRule ru = rule ? *rule : QuadRule{};
   const unsigned nb = blocks_for(n);
-  if (rule) {
-    if (r == 1)
-      k_orbit_deposit_soa<1, false><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, qv, J);
+  by_degree(r, [&](auto R) {
+    if (rule)
+      k_orbit_deposit_soa<R.value, false><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, qv, J);
     else
-      k_orbit_deposit_soa<2, false><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, qv, J);
-  } else {
-    if (r == 1)
-      k_orbit_deposit_soa<1, true><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, qv, J);
-    else
-      k_orbit_deposit_soa<2, true><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, qv, J);
-  }
+      k_orbit_deposit_soa<R.value, true><<<nb, kBlock, 0, s>>>(ru, G, n, x0, d, qv, J);
+  });
 }
 
 }  // namespace ecpic

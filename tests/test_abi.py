@@ -58,7 +58,8 @@ def test_state_bytes_scale_with_particles(lib):
 @pytest.mark.parametrize("bad", [
     dict(n=(32, 32, 30)),                 # not a power of two
     dict(n=(2, 32, 32)),                  # too small
-    dict(r=3),                            # spline degree
+    dict(r=4),                            # spline degree
+    dict(r=0),
     dict(kappa=2.0),                      # sigma1 != kappa^2 sigma2
     dict(dt=0.0),
     dict(pmax=-1),
@@ -66,6 +67,7 @@ def test_state_bytes_scale_with_particles(lib):
     dict(precision=2),                    # no such precision
     dict(quad_points=17),                 # beyond the largest rule
     dict(quad_points=3),                  # split quadratic pieces need 4 points
+    dict(r=3, quad_points=4),             # split cubic pieces need 5 points
     dict(split=False, precision=1),       # unsplit comparison path is FP64 only
 ])
 def test_invalid_configurations_are_rejected(lib, bad):

@@ -118,7 +118,7 @@ def rand_orbits(rng, k, cells=1.8):
     return x0, d
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_kernel_orbit_gather_matches_oracle(r):
     rng = np.random.default_rng(100 + r)
     x0, d = rand_orbits(rng, 4000)
@@ -140,7 +140,7 @@ def test_kernel_orbit_gather_matches_oracle(r):
         assert err <= 1e-13 * scale, (k, err, scale)
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_kernel_orbit_deposit_matches_oracle(r):
     rng = np.random.default_rng(200 + r)
     x0, d = rand_orbits(rng, 4000)
@@ -155,7 +155,7 @@ def test_kernel_orbit_deposit_matches_oracle(r):
     assert err <= 1e-13 * scale
 
 
-@pytest.mark.parametrize("r,nq", [(1, 0), (1, 16), (2, 0), (2, 7)])
+@pytest.mark.parametrize("r,nq", [(1, 0), (1, 16), (2, 0), (2, 7), (3, 0), (3, 9)])
 def test_kernel_unsplit_orbit_integrals_match_oracle(r, nq):
     """The unsplit comparison path: one Gauss rule over the whole orbit, each
     point with the stencil of its own cell."""
@@ -176,7 +176,7 @@ def test_kernel_unsplit_orbit_integrals_match_oracle(r, nq):
     assert np.abs(Jg - Jo).max() <= 1e-13 * np.abs(Jo).max()
 
 
-@pytest.mark.parametrize("r,nq", [(1, 16), (2, 0)])
+@pytest.mark.parametrize("r,nq", [(1, 16), (2, 0), (3, 0)])
 def test_unsplit_step_parity_fixed_iterations(r, nq):
     wl = small_random(r)
     g = E.Sim(gpu_cfg(wl, tol=0.0, pmax=3, split=False, quad_points=nq), wl.np)
@@ -198,7 +198,7 @@ def small_random(r, np_=3000, seed=5):
                            drift=(0.03, -0.02, 0.01), seed=seed)
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 @pytest.mark.parametrize("pmax", [0, 3])
 def test_step_parity_fixed_iterations(r, pmax):
     wl = small_random(r)
@@ -212,7 +212,7 @@ def test_step_parity_fixed_iterations(r, pmax):
         compare_states(wl, g, o, f"r={r} pmax={pmax} step {step}")
 
 
-@pytest.mark.parametrize("r", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
 def test_step_parity_tolerance_mode_and_energy(r):
     wl = small_random(r, seed=9)
     g, o = both(wl, tol=1e-11, pmax=30, diagnostics=True)
