@@ -99,6 +99,7 @@ def lib():
         L.orc_rebuild_P.argtypes = [P]
         L.orc_field_energy_grad.argtypes = [P, D]
         L.orc_set_trace.argtypes = [P, D, D, C.c_int]
+        L.orc_init_species.argtypes = [P, D, D, C.POINTER(C.c_int32), C.c_int, D, D, C.c_double]
         L.orc_anderson_mix.argtypes = [C.c_int, C.c_int64, C.POINTER(D), C.POINTER(D), D, D]
         _lib = L
     return _lib
@@ -182,6 +183,19 @@ class OracleSim:
         rc = lib().orc_init_particles(self._h, _p(x), _p(v), q, m, n0)
         if rc != 0:
             raise RuntimeError("orc_init_particles failed")
+
+    def init_species(self, x, v, species, q, m, n0):
+        """Several species: particle i has charge q[species[i]], mass m[species[i]]."""
+        x = _f64(x).reshape(3, self.np)
+        v = _f64(v).reshape(3, self.np)
+        sp = np.ascontiguousarray(species, dtype=np.int32)
+        q, m = _f64(q), _f64(m)
+        self.q, self.m = float(q[0]), float(m[0])
+        rc = lib().orc_init_species(self._h, _p(x), _p(v),
+                                    sp.ctypes.data_as(C.POINTER(C.c_int32)), len(q), _p(q),
+                                    _p(m), n0)
+        if rc != 0:
+            raise ValueError("orc_init_species: bad species")
 
     def step(self):
         info = StepInfo()

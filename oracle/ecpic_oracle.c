@@ -108,7 +108,9 @@ typedef struct {
   int nq;
   double gx[64], gw[64];     /* Gauss-Legendre nodes/weights on [-1, 1] */
   int64_t np;
-  double q, m;
+  double q, m;               /* the species of a one-species run (and of the adjoint) */
+  double *qi, *mi;           /* charge and mass of every particle (np each) */
+  int one_species;           /* 1 when every particle carries (q, m) */
   double *x, *v, *vprev, *P; /* 3*np each, component-major: x[a*np + i] */
   cplx *phi, *psi, *A, *U, *rho; /* Fourier state, A and U hold 3 components */
   double *J;                 /* real-space current of the accepted iterate (3*ncell) */
@@ -518,9 +520,9 @@ static int gather_one(const orc_sim* S, const double x0[3], const double d[3], c
   return 0;
 }
 
-/* point-shape charge deposit rho_g = sum_i q S_g(x_i) / dV (eq. source-moments) */
-static void deposit_point_charge(const grid* G, int r, int64_t np, const double* x, double q,
-                                 double* rho) {
+/* point-shape charge deposit rho_g = sum_i q_i S_g(x_i) / dV (eq. source-moments) */
+static void deposit_point_charge(const grid* G, int r, int64_t np, const double* x,
+                                 const double* qi, double* rho) {
   int w = r + 1;
   for (int64_t i = 0; i < np; ++i) {
     double wv[3][4], dwv[3][4];
@@ -536,7 +538,7 @@ static void deposit_point_charge(const grid* G, int r, int64_t np, const double*
       for (int jj = 0; jj < w; ++jj)
         for (int kk = 0; kk < w; ++kk) {
           int64_t g = node_id(G, first[0] + ii, first[1] + jj, first[2] + kk);
-          rho[g] += q * wv[0][ii] * wv[1][jj] * wv[2][kk] / G->dV;
+          rho[g] += qi[i] * wv[0][ii] * wv[1][jj] * wv[2][kk] / G->dV;
         }
   }
 }
@@ -687,7 +689,7 @@ static double kinetic_energy(const orc_sim* S) {
   for (int64_t i = 0; i < S->np; ++i)
     for (int a = 0; a < 3; ++a) {
       double va = S->v[(int64_t)a * S->np + i];
-      K += 0.5 * S->m * va * va;
+      K += 0.5 * S->mi[i] * va * va;
     }
   return K;
 }
@@ -839,6 +841,17 @@ int orc_check_config(const orc_cfg* c) {
   return 0;
 }
 
+/* every particle of species (q, m) */
+static void set_one_species(orc_sim* S, double q, double m) {
+  S->q = q;
+  S->m = m;
+  S->one_species = 1;
+  for (int64_t i = 0; i < S->np; ++i) {
+    S->qi[i] = q;
+    S->mi[i] = m;
+  }
+}
+
 orc_sim* orc_create(const orc_cfg* c, int64_t np) {
   if (orc_check_config(c) != 0 || np < 0) return NULL;
   orc_sim* S = (orc_sim*)calloc(1, sizeof(orc_sim));
@@ -861,8 +874,9 @@ orc_sim* orc_create(const orc_cfg* c, int64_t np) {
   S->A = (cplx*)calloc(3 * nc, sizeof(cplx));
   S->U = (cplx*)calloc(3 * nc, sizeof(cplx));
   S->J = (double*)calloc(3 * nc, sizeof(double));
-  S->q = -1.0;
-  S->m = 1.0;
+  S->qi = (double*)calloc(np > 0 ? np : 1, sizeof(double));
+  S->mi = (double*)calloc(np > 0 ? np : 1, sizeof(double));
+  set_one_species(S, -1.0, 1.0);
   return S;
 }
 
@@ -872,6 +886,8 @@ void orc_destroy(orc_sim* S) {
   free(S->v);
   free(S->vprev);
   free(S->P);
+  free(S->qi);
+  free(S->mi);
   free(S->phi);
   free(S->psi);
   free(S->rho);
@@ -906,21 +922,46 @@ static void update_energy_start(orc_sim* S) {
 /* Initial state of the two-stream setup (Sec. 5.4): point-shape charge deposit
    plus uniform background n0, mean removed (and zeroed on every k~ = 0 mode),
    phi^0 from -Delta_h phi = sigma1 rho, psi = A = U = 0, P = m v, v^{-1} = v^0. */
+static int init_state(orc_sim* S, const double* x, const double* v, double n0);
+
 int orc_init_particles(orc_sim* S, const double* x, const double* v, double q, double m,
                        double n0) {
+  set_one_species(S, q, m);
+  return init_state(S, x, v, n0);
+}
+
+/* Several species (each particle carries its own q_i and m_i, Sec. 2):
+   particle i has charge q[species[i]] and mass m[species[i]]. */
+int orc_init_species(orc_sim* S, const double* x, const double* v, const int32_t* species,
+                     int nspecies, const double* q, const double* m, double n0) {
+  if (nspecies < 1) return -1;
+  for (int64_t i = 0; i < S->np; ++i)
+    if (species[i] < 0 || species[i] >= nspecies) return -1;
+  S->q = q[0];
+  S->m = m[0];
+  S->one_species = 1;
+  for (int64_t i = 0; i < S->np; ++i) {
+    S->qi[i] = q[species[i]];
+    S->mi[i] = m[species[i]];
+    if (S->qi[i] != q[0] || S->mi[i] != m[0]) S->one_species = 0;
+  }
+  return init_state(S, x, v, n0);
+}
+
+static int init_state(orc_sim* S, const double* x, const double* v, double n0) {
   const grid* G = &S->G;
   int64_t np = S->np, nc = G->ncell;
-  S->q = q;
-  S->m = m;
-  for (int64_t i = 0; i < 3 * np; ++i) {
-    S->v[i] = v[i];
-    S->vprev[i] = v[i];
-    S->P[i] = m * v[i];
-  }
+  for (int a = 0; a < 3; ++a)
+    for (int64_t i = 0; i < np; ++i) {
+      int64_t id = a * np + i;
+      S->v[id] = v[id];
+      S->vprev[id] = v[id];
+      S->P[id] = S->mi[i] * v[id];
+    }
   for (int a = 0; a < 3; ++a)
     for (int64_t i = 0; i < np; ++i) S->x[a * np + i] = wrap_pos(x[a * np + i], G->L[a]);
   double* rho = (double*)calloc(nc, sizeof(double));
-  deposit_point_charge(G, S->c.r, np, S->x, q, rho);
+  deposit_point_charge(G, S->c.r, np, S->x, S->qi, rho);
   double mean = 0.0;
   for (int64_t g = 0; g < nc; ++g) {
     rho[g] += n0;
@@ -961,7 +1002,7 @@ int orc_init_particles(orc_sim* S, const double* x, const double* v, double q, d
 int orc_picard_step(orc_sim* S, orc_step_info* info) {
   const grid* G = &S->G;
   int64_t np = S->np, nc = G->ncell;
-  double dt = S->c.dt, q = S->q, m = S->m;
+  double dt = S->c.dt;
 
   double K_n = kinetic_energy(S);
   double W_n = field_energy(S, S->phi, S->A, S->U);
@@ -1011,10 +1052,10 @@ int orc_picard_step(orc_sim* S, orc_step_info* info) {
         x0[a] = S->x[a * np + i];
         vb[a] = 0.5 * (vit[a * np + i] + S->v[a * np + i]);
         d[a] = dt * vb[a];
-        qv[a] = q * vb[a];
+        qv[a] = S->qi[i] * vb[a];
         vmax = fmax(vmax, fabs(vb[a]));
       }
-      Js += fabs(q) * vmax;
+      Js += fabs(S->qi[i]) * vmax;
       if (deposit_one(S, x0, d, qv, J, buf) != 0) { status = -1; goto done; }
     }
     Js /= G->vol;
@@ -1061,9 +1102,9 @@ int orc_picard_step(orc_sim* S, orc_step_info* info) {
       for (int j = 0; j < 3; ++j) {
         double DTv = 0.0; /* ((D A)^T vbar)_j = sum_l D_lj vbar_l */
         for (int l = 0; l < 3; ++l) DTv += D[l][j] * vb[l];
-        double Pj = S->P[j * np + i] + dt * (-q * gpb[j] + q * DTv);
+        double Pj = S->P[j * np + i] + dt * (-S->qi[i] * gpb[j] + S->qi[i] * DTv);
         Pnew[j * np + i] = Pj;
-        double vj = (Pj - q * Aend[j]) / m;
+        double vj = (Pj - S->qi[i] * Aend[j]) / S->mi[i];
         vnew[j * np + i] = vj;
         dvmax = fmax(dvmax, fabs(vj - vit[j * np + i]));
         vmaxall = fmax(vmaxall, fabs(vj));
@@ -1074,7 +1115,7 @@ int orc_picard_step(orc_sim* S, orc_step_info* info) {
         double RA = Aend[l] - Astart[l] - dt * (Ub[l] + Dv);
         RA2 += RA * RA;
         RAmax = fmax(RAmax, fabs(RA));
-        work += q * vb[l] * (-gpb[l] - Ub[l]);
+        work += S->qi[i] * vb[l] * (-gpb[l] - Ub[l]);
       }
       poumax = fmax(poumax, fabs(pou - 1.0));
     }
@@ -1211,8 +1252,7 @@ int orc_get_state(const orc_sim* S, double* x, double* v, double* vprev, double*
 int orc_set_state(orc_sim* S, const double* x, const double* v, const double* vprev,
                   const double* P, const double* fields, double q, double m) {
   int64_t n3 = 3 * S->np, nc = S->G.ncell;
-  S->q = q;
-  S->m = m;
+  if (m > 0.0) set_one_species(S, q, m); /* m = 0: keep every particle's species */
   if (x) memcpy(S->x, x, sizeof(double) * n3);
   if (v) memcpy(S->v, v, sizeof(double) * n3);
   if (vprev) memcpy(S->vprev, vprev, sizeof(double) * n3);
@@ -1649,7 +1689,7 @@ int orc_adjoint_step(const orc_sim* S, const double* x, const double* v, const d
                      double* lx0, double* lv0, double* lF0, double tol, int maxit,
                      int* iters_out) {
   const grid* G = &S->G;
-  if (S->c.r != 2 || !S->c.split) return -1;
+  if (S->c.r != 2 || !S->c.split || !S->one_species) return -1;
   int64_t np = S->np, nc = G->ncell;
   double dt = S->c.dt, q = S->q, m = S->m;
   double* vb = (double*)malloc(sizeof(double) * 3 * np + 8);
@@ -1811,7 +1851,7 @@ int orc_rebuild_P(orc_sim* S) {
     double x0[3], Ax[3];
     for (int a = 0; a < 3; ++a) x0[a] = S->x[a * np + i];
     interp_point(G, S->c.r, x0, A0r, 3, Ax);
-    for (int a = 0; a < 3; ++a) S->P[a * np + i] = S->m * S->v[a * np + i] + S->q * Ax[a];
+    for (int a = 0; a < 3; ++a) S->P[a * np + i] = S->mi[i] * S->v[a * np + i] + S->qi[i] * Ax[a];
   }
   free(A0r);
   return 0;

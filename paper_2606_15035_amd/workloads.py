@@ -47,6 +47,10 @@ class Workload:
     sigma1: float = 1.0
     sigma2: float = 1.0
     description: str = ""
+    # several species: particle i has charge qs[species[i]] and mass ms[species[i]]
+    species: np.ndarray | None = None
+    qs: tuple | None = None
+    ms: tuple | None = None
 
     @property
     def np(self) -> int:
@@ -193,6 +197,51 @@ def random_plasma(n, L, np_, r, dt, vth, drift=(0.0, 0.0, 0.0), seed=SEED, tol=1
     q, m = _species(1.0, L, np_)
     return Workload(name=name, n=tuple(n), L=tuple(L), dt=dt, steps=1, r=r, tol=tol, pmax=pmax,
                     precision="fp64", x=x, v=v, q=q, m=m, description="random plasma")
+
+
+def electron_ion(n, L, np_, r, dt, vth, mass_ratio=16.0, drift=(0.0, 0.0, 0.0), seed=SEED,
+                 tol=1e-12, pmax=16) -> Workload:
+    """Neutral electron-ion plasma: np_ // 2 electrons (q/m = -1, uniform
+    random positions, Maxwellian velocities of spread vth plus drift) and as
+    many ions of charge +|q_e| and mass mass_ratio m_e at the electrons'
+    positions, with spread vth / sqrt(mass_ratio) and no drift.  No background
+    charge (n0 = 0); species 0 = electrons, 1 = ions, interleaved."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ne = np_ // 2
+    xe = np.stack([rng.uniform(0.0, L[a], size=ne) for a in range(3)])
+    ve = rng.normal(0.0, vth, size=(3, ne)) + np.asarray(drift, dtype=float).reshape(3, 1)
+    vi = rng.normal(0.0, vth / math.sqrt(mass_ratio), size=(3, ne))
+    x = np.empty((3, 2 * ne))
+    v = np.empty((3, 2 * ne))
+    x[:, 0::2], x[:, 1::2] = xe, xe
+    v[:, 0::2], v[:, 1::2] = ve, vi
+    species = np.tile(np.array([0, 1], dtype=np.int32), ne)
+    qe, me = _species(1.0, L, ne)
+    qs, ms = (qe, -qe), (me, mass_ratio * me)
+    return Workload(name="electron-ion", n=tuple(n), L=tuple(L), dt=dt, steps=1, r=r, tol=tol,
+                    pmax=pmax, precision="fp64", x=x, v=v, q=qe, m=me, n0=0.0,
+                    description=f"electron-ion plasma, mass ratio {mass_ratio:g}",
+                    species=species, qs=qs, ms=ms)
+
+
+def plasma_oscillation(mass_ratio, r=1, dt=0.05, amp=1e-4) -> Workload:
+    """Cold electron-ion plasma on the 16x4x4 two-stream box: 8 electrons and
+    8 ions per cell at the same quiet x-lattice positions (rho^0 = 0), ions at
+    rest, electrons with v_x = amp sin(k1 x); Langmuir oscillation of the k1
+    mode."""
+    n = (16, 4, 4)
+    L = (LX, LX / 4, LX / 4)
+    pos = _quiet_x_lattice(n, L, 8)
+    ne = pos.shape[1]
+    x = np.concatenate([pos, pos], axis=1)
+    v = np.zeros_like(x)
+    v[0, :ne] = amp * np.sin(K1 * pos[0])
+    species = np.r_[np.zeros(ne, np.int32), np.ones(ne, np.int32)]
+    qe, me = _species(1.0, L, ne)
+    return Workload(name="plasma-oscillation", n=n, L=L, dt=dt, steps=500, r=r, tol=1e-13,
+                    pmax=30, precision="fp64", x=x, v=v, q=qe, m=me, n0=0.0,
+                    description=f"cold electron-ion Langmuir oscillation, mass ratio {mass_ratio:g}",
+                    species=species, qs=(qe, -qe), ms=(me, mass_ratio * me))
 
 
 def random_fields(n, ncomp, seed=SEED, modes=3, scale=1.0):
