@@ -146,6 +146,19 @@ void ecpic_destroy(ecpic_sim* sim);
 ecpic_status ecpic_init_particles(ecpic_sim* sim, const double* x, const double* v, double q,
                                   double m, double n0);
 
+/* As ecpic_init_particles with several particle species (the model gives
+   every particle its own charge q_i and mass m_i, Sec. 2): particle i (host
+   arrays in the caller's order) has charge q[species[i]] and mass
+   m[species[i]].  nspecies in [1, 4]; q[s] finite and non-zero, m[s] > 0;
+   every species[i] in [0, nspecies), else ECPIC_EINVAL and nothing changes.
+   rho^0 = sum_i q_i S_g(x_i) / dV, P_i = m_i v_i.  With more than one species
+   the state holds one byte per particle for it; the adjoint takes one species
+   only.  In mixed precision the current quanta are those of q[0]: a
+   contribution of species s is quantised as (q[s] / q[0]) vbar Sbar. */
+ecpic_status ecpic_init_species(ecpic_sim* sim, const double* x, const double* v,
+                                const int32_t* species, int32_t nspecies, const double* q,
+                                const double* m, double n0);
+
 /* One time step by Algorithm 1: extrapolated guess, then per Picard pass the
    orbit current (eq. orbit-current), continuity and CN solve, orbit gather and
    orbit-discrete-gradient push (eq. orbit-push); stop when both fixed-point
@@ -170,7 +183,9 @@ ecpic_status ecpic_get_state(ecpic_sim* sim, double* x, double* v, double* vprev
                              double* fields);
 
 /* Replace the state from host buffers (same layout as ecpic_get_state; any may
-   be NULL to keep the current value).  q and m set the particle species. */
+   be NULL to keep the current value).  m > 0: every particle gets charge q and
+   mass m (one species); m = 0: every particle keeps its species (q ignored;
+   ECPIC_ESTATE before the first initialisation). */
 ecpic_status ecpic_set_state(ecpic_sim* sim, const double* x, const double* v,
                              const double* vprev, const double* fields, double q, double m);
 

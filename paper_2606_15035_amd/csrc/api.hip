@@ -158,7 +158,10 @@ struct ecpic_sim {
   Grid G;
   int64_t np;
   hipStream_t stream;
-  double q = -1.0, m = 1.0;
+  double q = -1.0, m = 1.0;  // species 0
+  int nsp = 1;               // species; > 1: the stores hold one byte per particle
+  double qs[kMaxSpecies] = {-1.0}, ms[kMaxSpecies] = {1.0};
+  uint8_t* spb[2] = {nullptr, nullptr};  // species bytes of the two stores
   bool initialized = false;
   // particles (state), stored in cell-sorted order; id[i] = caller index.
   // One of the two stores is live (cfg.precision); [1] is the sort's alternate.
@@ -198,7 +201,35 @@ struct ecpic_sim {
   ecpic_energy en{};
   FieldParams fp() const { return FieldParams{G, cfg.dt, cfg.kappa, cfg.sigma1, cfg.sigma2}; }
   QuadRule rule{};  // rule of the unsplit comparison path
-  StepParams pp() const { return StepParams{G, cfg.dt, q, m, np, cfg.split_orbit_at_knots, rule}; }
+  StepParams pp() const {
+    StepParams P{};
+    P.G = G;
+    P.dt = cfg.dt;
+    P.q = q;
+    P.m = m;
+    P.np = np;
+    P.split = cfg.split_orbit_at_knots;
+    P.rule = rule;
+    P.nsp = nsp;
+    for (int k = 0; k < kMaxSpecies; ++k) {
+      P.qs[k] = qs[k];
+      P.ms[k] = ms[k];
+      P.cq[k] = mixed() ? qs[k] / q : qs[k] / G.dV;
+      P.aq[k] = std::fabs(qs[k]) / G.vol;
+    }
+    return P;
+  }
+  // every particle of species (q, m) (the stores hold no species bytes)
+  void set_one_species(double q_, double m_) {
+    q = q_;
+    m = m_;
+    nsp = 1;
+    for (int k = 0; k < kMaxSpecies; ++k) {
+      qs[k] = q_;
+      ms[k] = m_;
+    }
+    for (int k = 0; k < 2; ++k) f64[k].sp = mx[k].sp = nullptr;
+  }
 };
 
 namespace {
@@ -231,6 +262,7 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   for (int k = 0; k < S->npool; ++k) S->apool[k] = st.take<double>(n3);
   S->vit = S->apool[0];
   S->vnew = S->apool[1];
+  for (int k = 0; k < 2; ++k) S->spb[k] = st.take<uint8_t>(n1);
   S->id = st.take<int>(n1);
   S->id2 = st.take<int>(n1);
   S->sb.key = st.take<int>(n1);
@@ -451,15 +483,11 @@ void ecpic_destroy(ecpic_sim* S) {
   delete S;
 }
 
-ecpic_status ecpic_init_particles(ecpic_sim* S, const double* x, const double* v, double q,
-                                  double m, double n0) {
-  (void)n0;  // a uniform background only changes the k = 0 mode, which is zeroed
-  if (!S) return fail(ECPIC_EINVAL, "null simulation");
-  if (S->np > 0 && (!x || !v)) return fail(ECPIC_EINVAL, "null particle arrays");
-  if (!(m > 0.0) || !std::isfinite(q)) return fail(ECPIC_EINVAL, "invalid q or m");
+namespace {
+
+// x, v into the store (x wrapped; v^{-1} = v^0), rho^0 and phi^0 (species set)
+ecpic_status init_state(ecpic_sim* S, const double* x, const double* v) {
   const int64_t np = S->np, nc = S->G.ncell;
-  S->q = q;
-  S->m = m;
   if (np > 0) {  // through the iterate buffers into the store (x wrapped; v^{-1} = v^0)
     HIPCHK(hipMemcpyAsync(S->vit, x, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
     HIPCHK(hipMemcpyAsync(S->vnew, v, sizeof(double) * 3 * np, hipMemcpyHostToDevice, S->stream));
@@ -476,7 +504,8 @@ ecpic_status ecpic_init_particles(ecpic_sim* S, const double* x, const double* v
     launch_deposit_rho(S->stream, S->cfg.spline_degree, S->pp(), st,
                        CurrentOut{S->realbuf, S->Jfix, S->fix_scale});
   });
-  if (S->mixed()) launch_fixed_current(S->stream, nc, S->Jfix, S->realbuf, q / S->G.dV / S->fix_scale);
+  if (S->mixed())
+    launch_fixed_current(S->stream, nc, S->Jfix, S->realbuf, S->q / S->G.dV / S->fix_scale);
   RealIO in{};
   in.p[0] = S->realbuf;
   in.stride[0] = 1;
@@ -492,6 +521,55 @@ ecpic_status ecpic_init_particles(ecpic_sim* S, const double* x, const double* v
   S->en = ecpic_energy{};
   S->initialized = true;
   return ECPIC_OK;
+}
+
+}  // namespace
+
+ecpic_status ecpic_init_particles(ecpic_sim* S, const double* x, const double* v, double q,
+                                  double m, double n0) {
+  (void)n0;  // a uniform background only changes the k = 0 mode, which is zeroed
+  if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  if (S->np > 0 && (!x || !v)) return fail(ECPIC_EINVAL, "null particle arrays");
+  if (!(m > 0.0) || !std::isfinite(q)) return fail(ECPIC_EINVAL, "invalid q or m");
+  S->set_one_species(q, m);
+  return init_state(S, x, v);
+}
+
+ecpic_status ecpic_init_species(ecpic_sim* S, const double* x, const double* v,
+                                const int32_t* species, int32_t nspecies, const double* q,
+                                const double* m, double n0) {
+  (void)n0;
+  if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  if (nspecies < 1 || nspecies > kMaxSpecies)
+    return fail(ECPIC_EINVAL, "nspecies must be in [1, %d]", kMaxSpecies);
+  if (!q || !m) return fail(ECPIC_EINVAL, "null species tables");
+  if (S->np > 0 && (!x || !v || !species)) return fail(ECPIC_EINVAL, "null particle arrays");
+  for (int k = 0; k < nspecies; ++k)
+    if (!(m[k] > 0.0) || !std::isfinite(m[k]) || !std::isfinite(q[k]) || q[k] == 0.0)
+      return fail(ECPIC_EINVAL, "species %d: q must be finite and non-zero, m positive", k);
+  std::vector<uint8_t> sp(S->np > 0 ? (size_t)S->np : 1, 0);
+  for (int64_t i = 0; i < S->np; ++i) {
+    if (species[i] < 0 || species[i] >= nspecies)
+      return fail(ECPIC_EINVAL, "species[%lld] = %d outside [0, %d)", (long long)i, species[i],
+                  nspecies);
+    sp[i] = (uint8_t)species[i];
+  }
+  S->set_one_species(q[0], m[0]);
+  if (nspecies > 1) {
+    S->nsp = nspecies;
+    for (int k = 0; k < nspecies; ++k) {
+      S->qs[k] = q[k];
+      S->ms[k] = m[k];
+    }
+    // caller order is the stored order until the first sort
+    if (S->np > 0)
+      HIPCHK(hipMemcpyAsync(S->spb[0], sp.data(), (size_t)S->np, hipMemcpyHostToDevice,
+                            S->stream));
+    HIPCHK(hipStreamSynchronize(S->stream));
+    S->f64[0].sp = S->mx[0].sp = S->spb[0];
+    S->f64[1].sp = S->mx[1].sp = S->spb[1];
+  }
+  return init_state(S, x, v);
 }
 
 namespace {
@@ -809,11 +887,12 @@ ecpic_status ecpic_get_state(ecpic_sim* S, double* x, double* v, double* vprev, 
 ecpic_status ecpic_set_state(ecpic_sim* S, const double* x, const double* v, const double* vprev,
                              const double* fields, double q, double m) {
   if (!S) return fail(ECPIC_EINVAL, "null simulation");
-  if (!(m > 0.0) || !std::isfinite(q)) return fail(ECPIC_EINVAL, "invalid q or m");
+  if (m != 0.0 && (!(m > 0.0) || !std::isfinite(q))) return fail(ECPIC_EINVAL, "invalid q or m");
+  if (m == 0.0 && !S->initialized)
+    return fail(ECPIC_ESTATE, "m = 0 keeps the species, but none were set");
   const int64_t np = S->np, nc = S->G.ncell;
   hipStream_t s = S->stream;
-  S->q = q;
-  S->m = m;
+  if (m != 0.0) S->set_one_species(q, m);
   if (np > 0) {  // caller order -> stored order
     if (!S->initialized) launch_iota(s, np, S->id);
     const double* src[3] = {x, v, vprev};
@@ -919,6 +998,7 @@ ecpic_status ecpic_adjoint_step(ecpic_sim* S, void* workspace, size_t workspace_
   if (!S) return fail(ECPIC_EINVAL, "null simulation");
   ecpic_status st = check_adjoint_config(&S->cfg);
   if (st != ECPIC_OK) return st;
+  if (S->nsp != 1) return fail(ECPIC_EINVAL, "adjoint: one particle species only");
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
     return fail(ECPIC_EINVAL, "adjoint workspace must be non-null and 256-byte aligned");
   const int64_t np = S->np, nc = S->G.ncell, n3 = 3 * np;
@@ -1043,6 +1123,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.6"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.7"; }
 
 }  // extern "C"

@@ -56,11 +56,28 @@ struct QuadRule {
 
 struct StepParams {
   Grid G;
-  double dt, q, m;
+  double dt, q, m;  // q, m: species 0, the reference charge of the fixed-point current
   int64_t np;
   int split;      // 1: split orbit integrals at knots; 0: one rule over the orbit
   QuadRule rule;  // the rule of split = 0
+  // particle species (each particle carries its own charge and mass, Sec. 2):
+  // a particle of species s has qs[s], ms[s]; one species: the store holds no
+  // species array and every particle has (q, m) = (qs[0], ms[0])
+  int nsp;
+  double qs[kMaxSpecies];
+  double ms[kMaxSpecies];
+  double cq[kMaxSpecies];  // current coefficient: q_s / dV (FP64), q_s / q_0 (fixed point)
+  double aq[kMaxSpecies];  // |q_s| / |Omega| (beam-current scale J_s)
 };
+
+// the entry of a species table for species s (a select chain: the tables stay
+// in kernel arguments, no per-lane indexing)
+__device__ __forceinline__ double species_value(const double (&t)[kMaxSpecies], int s) {
+  double r = t[0];
+#pragma unroll
+  for (int k = 1; k < kMaxSpecies; ++k) r = s == k ? t[k] : r;
+  return r;
+}
 
 // Slots that many blocks of a kernel update with atomics (maxima, exact
 // integer counts) get kSpread copies, one 128-byte line apart, so that the

@@ -554,7 +554,9 @@ __device__ __forceinline__ unsigned long long quantize(double w, double scale) {
   return (unsigned long long)(long long)round(w * scale);
 }
 
-template <int R, class PS, bool SPLIT>
+// MULTI: the particles carry species (one byte each); otherwise every
+// particle has the coefficients of species 0, kept in scalar registers
+template <int R, class PS, bool SPLIT, bool MULTI>
 __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
                                                    const double* __restrict__ vit,
                                                    CurrentOut out, Scratch sc) {
@@ -583,7 +585,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
     if (i >= P.np) continue;
     double x0[3], d[3], vb[3];
     orbit_of(P, st, vit, i, x0, d, vb);
-    js[0] += fabs(P.q) * fmax(fabs(vb[0]), fmax(fabs(vb[1]), fabs(vb[2]))) / P.G.vol;
+    const double vmax = fmax(fabs(vb[0]), fmax(fabs(vb[1]), fabs(vb[2])));
+    js[0] += (MULTI ? species_value(P.aq, st.species(i)) : P.aq[0]) * vmax;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double u0 = x0[a] * P.G.invH[a], u1 = (x0[a] + d[a]) * P.G.invH[a];
@@ -611,18 +614,18 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
   for (int t = threadIdx.x; t < 3 * nt; t += kBlock) tile[t] = 0.0;  // also integer zero
   __syncthreads();
   // pass 2: accumulate
-  const double qdv = P.q / P.G.dV;
   const int64_t nc = P.G.ncell;
   for (int k = 0; k < kPerThread; ++k) {
     const int64_t i = chunk_particle<R>(base, k);
     if (i >= P.np) continue;
     double x0[3], d[3], vb[3], c3[3];
     orbit_of(P, st, vit, i, x0, d, vb);
+    // FP64: q_i vbar / dV; fixed point: (q_i / q_0) vbar in units of the quantum
+    const double cq = MULTI ? species_value(P.cq, st.species(i)) : P.cq[0];
     int shift[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      // FP64: q vbar / dV; fixed point: vbar in units of the quantum
-      c3[a] = FIX ? vb[a] : qdv * vb[a];
+      c3[a] = cq * vb[a];
       const double u0 = x0[a] * P.G.invH[a], u1 = (x0[a] + d[a]) * P.G.invH[a];
       const int lo = to_int_clamped(floor(fmin(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off - 1;
       const int raw = lo - s_ref[a];
@@ -787,8 +790,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
 template <int R, bool SPLIT, class Acc>
 __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& acc,
                                                 const double* x0, const double* d,
-                                                const double* vb, const double* va,
-                                                double* vn, double& npieces, double& bad) {
+                                                const double* vb, const double* va, double qi,
+                                                double mi, double* vn, double& npieces,
+                                                double& bad) {
   double gp[3] = {0.0, 0.0, 0.0};
   double dtv[3] = {0.0, 0.0, 0.0};  // (D A)^T vbar
   if constexpr (SPLIT) {
@@ -818,9 +822,9 @@ __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& 
   point_A_acc<R>(P.G, x1, sh1, acc, 1, A1e);
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const double Pn = P.m * va[j] + P.q * A0s[j];
-    const double P1 = Pn + P.dt * (-P.q * gp[j] + P.q * dtv[j]);  // eq. orbit-P-update
-    vn[j] = (P1 - P.q * A1e[j]) / P.m;                          // eq. orbit-v-update
+    const double Pn = mi * va[j] + qi * A0s[j];
+    const double P1 = Pn + P.dt * (-qi * gp[j] + qi * dtv[j]);  // eq. orbit-P-update
+    vn[j] = (P1 - qi * A1e[j]) / mi;                          // eq. orbit-v-update
   }
 }
 
@@ -853,7 +857,11 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
   double npieces[1] = {0.0};
   double x0[3] = {0.0, 0.0, 0.0}, va[3] = {0.0, 0.0, 0.0}, vi[3] = {0.0, 0.0, 0.0};
   double vb[3] = {0.0, 0.0, 0.0}, d[3] = {0.0, 0.0, 0.0};
+  double qi = P.q, mi = P.m;
   if (active) {
+    const int spc = st.species(i);
+    qi = species_value(P.qs, spc);
+    mi = species_value(P.ms, spc);
     st.x_of(P.G, P.np, i, x0);
     st.v_of(P.np, i, va);
     load3(vit, P.np, i, vi);
@@ -924,12 +932,12 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
       acc.oz = shift[2] - s_ref[2] - tlo[2];
       acc.dy = dim[1];
       acc.dz = dim[2];
-      gather_push_one<R, SPLIT>(P, acc, x0, d, vb, va, vn, npieces[0], bad);
+      gather_push_one<R, SPLIT>(P, acc, x0, d, vb, va, qi, mi, vn, npieces[0], bad);
     }
   } else {
     if (active) {
       GlobalGather acc{F.g, P.G.mask[0], P.G.mask[1], P.G.mask[2], P.G.shx, P.G.shy};
-      gather_push_one<R, SPLIT>(P, acc, x0, d, vb, va, vn, npieces[0], bad);
+      gather_push_one<R, SPLIT>(P, acc, x0, d, vb, va, qi, mi, vn, npieces[0], bad);
     }
   }
   if (active) {
@@ -984,6 +992,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, PS st,
   double sums[2] = {0.0, 0.0};  // work, |R_A|^2
   double ramax = 0.0, poudev = 0.0;
   if (i < P.np) {
+    const double qi = species_value(P.qs, st.species(i));
     double x0[3], va[3], vi[3], vb[3], d[3];
     st.x_of(P.G, P.np, i, x0);
     st.v_of(P.np, i, va);
@@ -1018,7 +1027,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, PS st,
       const double ra = A1e[l] - A0s[l] - P.dt * (Ub[l] + Dv);
       sums[1] += ra * ra;
       ramax = fmax(ramax, fabs(ra));
-      sums[0] += P.q * vb[l] * (-gp[l] - Ub[l]);
+      sums[0] += qi * vb[l] * (-gp[l] - Ub[l]);
     }
     poudev = fabs(pou - 1.0);
   }
@@ -1038,6 +1047,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, PS st,
   double s[2] = {0.0, 0.0};  // K^{n+1}, K^{n+1} - K^n
   if (i < P.np) {
     double x0[3], vo[3], vi[3], vn[3], x1[3];
+    const double mi = species_value(P.ms, st.species(i));
     st.x_of(P.G, P.np, i, x0);
     st.v_of(P.np, i, vo);
     load3(vit, P.np, i, vi);
@@ -1046,8 +1056,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, PS st,
     for (int a = 0; a < 3; ++a) {
       x1[a] = wrap_pos(x0[a] + P.dt * 0.5 * (vi[a] + vo[a]), P.G.L[a], P.G.invL[a]);
       const double w = PS::stored(vn[a]);
-      s[0] += 0.5 * P.m * w * w;
-      s[1] += 0.5 * P.m * (w - vo[a]) * (w + vo[a]);
+      s[0] += 0.5 * mi * w * w;
+      s[1] += 0.5 * mi * (w - vo[a]) * (w + vo[a]);
     }
     st.set_x(P.G, P.np, i, x1);
     st.set_vp(P.np, i, vo);
@@ -1063,8 +1073,9 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(StepParams P, PS st, Scratch
   if (i < P.np) {
     double va[3];
     st.v_of(P.np, i, va);
+    const double mi = species_value(P.ms, st.species(i));
 #pragma unroll
-    for (int a = 0; a < 3; ++a) s[0] += 0.5 * P.m * va[a] * va[a];
+    for (int a = 0; a < 3; ++a) s[0] += 0.5 * mi * va[a] * va[a];
   }
   block_partials<2>(s, sc.region(P_K));
 }
@@ -1130,7 +1141,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rho(StepParams P, PS st, Cur
     Spline<R>::w(u - base, w[a]);
     f[a] = to_int_clamped(base) + Spline<R>::first_off;
   }
-  const double c = P.q / P.G.dV;
+  const double cq = species_value(P.cq, st.species(i));  // q_i / dV; fixed point: q_i / q_0
 #pragma unroll
   for (int a = 0; a < W; ++a)
 #pragma unroll
@@ -1141,9 +1152,9 @@ __global__ __launch_bounds__(kBlock) void k_deposit_rho(StepParams P, PS st, Cur
                                   wrapi(f[2] + cc, P.G.n[2]));
         const double s = w[0][a] * w[1][b] * w[2][cc];
         if constexpr (PS::kMixed)
-          atomicAdd(out.Jfix + g, quantize(s, out.fix_scale));
+          atomicAdd(out.Jfix + g, quantize(cq * s, out.fix_scale));
         else
-          unsafeAtomicAdd(out.J + g, c * s);
+          unsafeAtomicAdd(out.J + g, cq * s);
       }
 }
 
@@ -1268,16 +1279,23 @@ void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, con
                     CurrentOut out, Scratch sc) {
   if (P.np <= 0) return;
   const unsigned nblk = (unsigned)scatter_blocks(P.np, r);
+  const bool multi = P.nsp > 1;
   if constexpr (!PS::kMixed) {
     if (!P.split) {
       by_degree(r, [&](auto R) {
-        k_scatter<R.value, PS, false><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+        if (multi)
+          k_scatter<R.value, PS, false, true><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+        else
+          k_scatter<R.value, PS, false, false><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
       });
       return;
     }
   }
   by_degree(r, [&](auto R) {
-    k_scatter<R.value, PS, true><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+    if (multi)
+      k_scatter<R.value, PS, true, true><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+    else
+      k_scatter<R.value, PS, true, false><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
   });
 }
 

@@ -8,7 +8,9 @@
 //             time, and every orbit, weight, field and energy operation runs
 //             in FP64 on the decoded values; only the stored state is FP32.
 // The Picard iterates v^{n+1,p} are FP64 arrays outside the store in both
-// forms.  Kernels take the store as a template parameter.
+// forms.  With several species each store also holds one byte per particle,
+// its species (null with one species).  Kernels take the store as a template
+// parameter.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,11 +20,16 @@
 
 namespace ecpic {
 
+constexpr int kMaxSpecies = 4;
+
 struct Fp64Store {
   static constexpr bool kMixed = false;
   double* x;
   double* v;
   double* vp;
+  uint8_t* sp = nullptr;
+
+  __device__ __forceinline__ int species(int64_t i) const { return sp ? (int)sp[i] : 0; }
 
   __device__ __forceinline__ void x_of(const Grid&, int64_t np, int64_t i, double* o) const {
 #pragma unroll
@@ -59,6 +66,7 @@ struct Fp64Store {
   // particle i of this store -> particle j of dst
   __device__ __forceinline__ void move_to(const Fp64Store& dst, int64_t np, int64_t i,
                                           int64_t j) const {
+    if (sp) dst.sp[j] = sp[i];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       dst.x[a * np + j] = x[a * np + i];
@@ -74,6 +82,9 @@ struct MixedStore {
   float* off;
   float* v;
   float* vp;
+  uint8_t* sp = nullptr;
+
+  __device__ __forceinline__ int species(int64_t i) const { return sp ? (int)sp[i] : 0; }
 
   __device__ __forceinline__ void x_of(const Grid& G, int64_t np, int64_t i, double* o) const {
     const int c = cell[i];
@@ -126,6 +137,7 @@ struct MixedStore {
   __device__ __forceinline__ void move_to(const MixedStore& dst, int64_t np, int64_t i,
                                           int64_t j) const {
     dst.cell[j] = cell[i];
+    if (sp) dst.sp[j] = sp[i];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       dst.off[a * np + j] = off[a * np + i];

@@ -88,6 +88,8 @@ def lib():
         L.ecpic_destroy.argtypes = [P]
         L.ecpic_destroy.restype = None
         L.ecpic_init_particles.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double]
+        L.ecpic_init_species.argtypes = [P, D, D, C.POINTER(C.c_int32), C.c_int32, D, D,
+                                         C.c_double]
         L.ecpic_picard_step.argtypes = [P, C.POINTER(StepInfo)]
         L.ecpic_field_solve.argtypes = [P, D]
         L.ecpic_energy_diagnostics.argtypes = [P, C.POINTER(Energy)]
@@ -105,6 +107,7 @@ def lib():
         L.ecpic_last_error.restype = C.c_char_p
         L.ecpic_version.restype = C.c_char_p
         for name in ("ecpic_state_bytes", "ecpic_create", "ecpic_init_particles",
+                     "ecpic_init_species",
                      "ecpic_picard_step", "ecpic_field_solve", "ecpic_energy_diagnostics",
                      "ecpic_get_state", "ecpic_set_state", "ecpic_get_current",
                      "ecpic_orbit_gather", "ecpic_orbit_deposit", "ecpic_set_profiling",
@@ -204,6 +207,18 @@ class Sim:
         self.q, self.m = float(q), float(m)
         _check(lib().ecpic_init_particles(self._h, _hp(x), _hp(v), float(q), float(m), float(n0)))
 
+    def init_species(self, x, v, species, q, m, n0=0.0):
+        """Several species: particle i has charge q[species[i]], mass m[species[i]]."""
+        x = _host(x, (3, self.np))
+        v = _host(v, (3, self.np))
+        sp = np.ascontiguousarray(species, dtype=np.int32).reshape(self.np)
+        qa = np.ascontiguousarray(q, dtype=np.float64)
+        ma = np.ascontiguousarray(m, dtype=np.float64)
+        self.q, self.m = float(qa[0]), float(ma[0])
+        _check(lib().ecpic_init_species(self._h, _hp(x), _hp(v),
+                                        sp.ctypes.data_as(C.POINTER(C.c_int32)), len(qa),
+                                        _hp(qa), _hp(ma), float(n0)))
+
     def picard_step(self):
         info = StepInfo()
         st = _check(lib().ecpic_picard_step(self._h, C.byref(info)), allow=(OK, ENOCONV))
@@ -228,10 +243,14 @@ class Sim:
         return {"x": x, "v": v, "vprev": vp, "fields": f}
 
     def set_state(self, x=None, v=None, vprev=None, fields=None, q=None, m=None):
-        q = self.q if q is None else float(q)
-        m = self.m if m is None else float(m)
+        """Replace parts of the state.  With q and m every particle becomes of
+        that one species; without them every particle keeps its species."""
         args = [None if a is None else _host(a) for a in (x, v, vprev, fields)]
-        self.q, self.m = q, m
+        if m is None:
+            q, m = 0.0, 0.0
+        else:
+            q, m = float(q), float(m)
+            self.q, self.m = q, m
         _check(lib().ecpic_set_state(self._h, *[_hp(a) for a in args], q, m))
 
     def set_profiling(self, enable=True):
