@@ -183,6 +183,7 @@ struct ecpic_sim {
   double* gbuf;      // interleaved gather fields
   double* Jb[2];     // orbit current, double-buffered across Picard passes
   int jlast = 0;     // index of the current of the last accepted pass
+  bool jclean = true;  // Jb[1 - jlast] is zero (each pass's transform clears the other buffer)
   // workspace
   double2* Jh;
   double2* batch;
@@ -281,7 +282,7 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->realbuf = w.take<double>(9 * nc);
   S->Uhalf = w.take<double>(3 * nc);
   for (int a = 0; a < 3; ++a) S->tw[a] = w.take<double2>(S->G.n[a] / 2);
-  S->gflags = w.take<int>(particle_blocks(np) > 0 ? particle_blocks(np) : 1);
+  S->gflags = w.take<int>(particle_blocks(np) + 1);  // gather work list: count, block indices
   if (S->mixed()) S->Jfix = w.take<unsigned long long>(3 * nc);
   S->sc.red = w.take<double>(S_NSLOTS);
   S->sc.spread = w.take<double>((size_t)S_NSLOTS * kSpread * kSpreadStride);
@@ -462,8 +463,8 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
   if (hipMemsetAsync(S->sc.red, 0, sizeof(double) * S_NSLOTS, S->stream) != hipSuccess ||
       hipMemsetAsync(S->sc.spread, 0, sizeof(double) * S_NSLOTS * kSpread * kSpreadStride,
                      S->stream) != hipSuccess ||
-      hipMemsetAsync(S->gflags, 0, sizeof(int) * std::max<int64_t>(particle_blocks(n_particles), 1),
-                     S->stream) != hipSuccess ||
+      hipMemsetAsync(S->gflags, 0, sizeof(int) * (particle_blocks(n_particles) + 1), S->stream) !=
+          hipSuccess ||
       (S->Jfix && hipMemsetAsync(S->Jfix, 0, sizeof(unsigned long long) * 3 * S->G.ncell,
                                  S->stream) != hipSuccess) ||
       hipStreamSynchronize(S->stream) != hipSuccess) {
@@ -630,6 +631,8 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   const double fix_unit = S->q / S->G.dV / S->fix_scale;
   launch_reset_slots(s, S->sc, S_PIECES, 1);
   int p = 0, jcur = 1 - S->jlast;
+  if (!S->jclean && !S->mixed()) launch_fill(s, 3 * nc, S->Jb[jcur], 0.0);  // after a failed step
+  S->jclean = false;
   bool converged = false;
   double err_v = 0.0, err_J = INFINITY;
   for (p = 0; p <= S->cfg.picard_max; ++p) {
@@ -647,8 +650,9 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     }
     double* J = S->Jb[jcur];
     double* Jprev = S->Jb[1 - jcur];
-    launch_reset_slots(s, S->sc, S_DVMAX, 5);  // DVMAX, VMAX, DJMAX, JS, BAD
-    if (!S->mixed()) launch_fill(s, 3 * nc, J, 0.0);
+    // J is zero here: the previous pass's transform cleared it (FP64), or the
+    // fixed-point conversion overwrites it (mixed); the atomic slots of the
+    // pass were cleared when the previous pass's finishing kernel folded them
     if (prof) HIPCHK(hipEventRecord(S->ev[0], s));
     on_store(S, [&](auto& st, auto&) {  // J^{n+1/2,p}
       CurrentOut o = cout;
@@ -658,7 +662,8 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     if (S->mixed()) launch_fixed_current(s, 3 * nc, S->Jfix, J, fix_unit);
     if (prof) HIPCHK(hipEventRecord(S->ev[1], s));
     RealIO jin = soa_io(J, nc, 3);
-    fft3_forward(s, S->G, 3, S->Jh, &jin, p >= 1 ? Jprev : nullptr, twp(S), S->sc);
+    fft3_forward(s, S->G, 3, S->Jh, &jin, p >= 1 ? Jprev : nullptr, twp(S), S->sc,
+                 S->mixed() ? nullptr : Jprev);  // Jprev is the next pass's J
     launch_cn_update(s, F, cur, S->Jh, nxt, S->batch, S->sc);  // continuity + CN
     fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));         // grad phi^{n+1/2}, A^{n+1}
     if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
@@ -673,7 +678,8 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     }
     if (mk >= 2) launch_anderson_dots(s, mk, n3, av, S->sc);
     {
-      const FinishJob jobs[6] = {{P_CN, (int)mesh_blocks(nc), 3, S_JE},
+      const FinishJob jobs[7] = {{P_CN, (int)mesh_blocks(nc), 3, S_JE},
+                                 {0, 0, 1, S_DJMAX, F_SPREAD_MAX},
                                  {P_JS, (int)scatter_blocks(S->np, r), 1, S_JS},
                                  {0, 0, 2, S_DVMAX, F_SPREAD_MAX},
                                  {0, 0, 1, S_BAD, F_SPREAD_MAX},
@@ -681,7 +687,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
                                  {P_AA,
                                   mk == 1 ? (int)particle_blocks(S->np) : anderson_dot_blocks(n3),
                                   anderson_sums(mk), S_AA}};
-      launch_finish(s, S->sc, jobs, S->np > 0 ? (mk > 0 ? 6 : 5) : 1);
+      launch_finish(s, S->sc, jobs, S->np > 0 ? (mk > 0 ? 7 : 6) : 2, S->gflags);
     }
     HIPCHK(hipGetLastError());
     ecpic_status st = sync_read(S, S_DVMAX, (S_AA - S_DVMAX) + anderson_sums(mk));
@@ -725,6 +731,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     push_front(wl, nw, am + 1, wnext);
   }
   if (p > S->cfg.picard_max) p = S->cfg.picard_max;
+  S->jclean = true;
 
   // consistency sweep of the accepted iterate (its orbit, current and fields)
   if (prof) HIPCHK(hipEventRecord(S->ev[0], s));

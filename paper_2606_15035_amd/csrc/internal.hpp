@@ -99,8 +99,9 @@ struct Scratch {
 
 // One row reduction for the finishing kernel: rows row0 .. row0 + M - 1 of
 // site `site`, each over nb partials, into red[slot .. slot + M).
-// F_SUM: set the slot to the sum of the partial row; F_SPREAD_MAX / F_SPREAD_SUM:
-// set the slot to the max / sum of its kSpread copies (site, nb, row0 unused)
+// F_SUM: set the slot to the sum of the partial row; F_SPREAD_MAX: set the slot
+// to the max of its kSpread copies; F_SPREAD_SUM: add the sum of the copies to
+// the slot.  Spread copies are cleared once folded (site, nb, row0 unused).
 enum FinishOp : int { F_SUM = 0, F_SPREAD_MAX = 1, F_SPREAD_SUM = 2 };
 struct FinishJob {
   int site, nb, M, slot;
@@ -108,7 +109,9 @@ struct FinishJob {
   int row0 = 0;
 };
 constexpr int kMaxFinishJobs = 8;
-void launch_finish(hipStream_t s, Scratch sc, const FinishJob* jobs, int njobs);
+// clear_int (optional): an int set to zero after the jobs (the gather's work-list count)
+void launch_finish(hipStream_t s, Scratch sc, const FinishJob* jobs, int njobs,
+                   int* clear_int = nullptr);
 
 // Anderson mixing (anderson.hip): iterates w[j] and images g[j] of passes
 // p - j, j = 0..mk, each 3 x np doubles.
@@ -221,8 +224,10 @@ struct RealIO {
 // forward: real input from `in` (may be nullptr for complex in-place), and
 // optionally max|in - prev| folded into S_DJMAX.  inverse: real part of the
 // result to `out` (nullptr keeps the complex result in place).
+// clear (optional): a real buffer laid out like prev, zeroed by the first pass
 void fft3_forward(hipStream_t s, const Grid& G, int nb, double2* data, const RealIO* in,
-                  const double* prev, const double2* const* tw, Scratch sc);
+                  const double* prev, const double2* const* tw, Scratch sc,
+                  double* clear = nullptr);
 void fft3_inverse(hipStream_t s, const Grid& G, int nb, double2* data, const RealIO* out,
                   const double2* const* tw);
 

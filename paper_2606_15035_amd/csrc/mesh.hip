@@ -36,8 +36,9 @@ struct FftPass {
   int N, logN;
   double sgn;         // -1 forward, +1 inverse (sign of the exponent)
   RealIO io;          // real input (forward first pass) or output (inverse last pass)
-  const double* prev; // optional: max |in - prev| -> S_DJMAX
-  double* red;
+  const double* prev; // optional: max |in - prev| -> S_DJMAX (a spread slot)
+  double* clear;      // optional: real buffer (same layout as prev) zeroed by the pass
+  Scratch sc;
 };
 
 // MODE 0: complex in place; 1: real input -> complex; 2: complex -> real output.
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass A) {
       if constexpr (MODE == 1) {
         const double re = A.io.p[b][g * A.io.stride[b]];
         if (A.prev) dmax = fmax(dmax, fabs(re - A.prev[b * A.ncell + g]));
+        if (A.clear) A.clear[b * A.ncell + g] = 0.0;  // after prev was read (same element)
         val = make_double2(re, 0.0);
       } else {
         val = A.data[b * A.ncell + g];
@@ -109,7 +111,10 @@ __global__ __launch_bounds__(kBlock) void k_fft(FftPass A) {
     }
   }
   if constexpr (MODE == 1) {
-    if (A.prev) block_max_to(dmax, A.red + S_DJMAX);
+    if (A.prev) {
+      const double r = block_max(dmax);
+      if (threadIdx.x == 0) atomic_max_nonneg(A.sc.spread_copy(S_DJMAX), r);
+    }
   }
 }
 
@@ -375,36 +380,47 @@ struct FinishArgs {
   Scratch sc;
   FinishJob job[kMaxFinishJobs];
   int njobs;
+  int* clear_int;  // optional: set to zero once every job is done (a work-list count)
 };
 
-// One block: each requested row of block partials summed in a fixed order,
-// or a spread slot's copies folded by max or sum.
-__global__ __launch_bounds__(kBlock) void k_finish(FinishArgs F) {
+constexpr int kFinishThreads = 1024;  // one wavefront per row, 16 rows at a time
+static_assert(kSpread == kWave, "the finishing kernel folds one copy per lane");
+
+// One block; every requested row is reduced by one wavefront in a fixed
+// order (lanes stride the row, then a fixed butterfly): a row of block
+// partials is summed into its slot, a spread slot's copies are folded by max
+// (slot = max) or sum (slot += sum) and then cleared for the next pass.
+__global__ __launch_bounds__(kFinishThreads) void k_finish(FinishArgs F) {
+  constexpr int NW = kFinishThreads / kWave;
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  int row = 0;
   for (int j = 0; j < F.njobs; ++j) {
     const FinishJob jb = F.job[j];
-    for (int m = 0; m < jb.M; ++m) {
+    for (int m = 0; m < jb.M; ++m, ++row) {
+      if (row % NW != wid) continue;
       double* slot = F.sc.red + jb.slot + m;
       if (jb.op == F_SUM) {
-        const double* row = F.sc.region(jb.site) + (size_t)(jb.row0 + m) * jb.nb;
-        double acc[1] = {0.0};
+        const double* r = F.sc.region(jb.site) + (size_t)(jb.row0 + m) * jb.nb;
+        double acc = 0.0;
 #pragma unroll 8
-        for (int b = threadIdx.x; b < jb.nb; b += kBlock) acc[0] += row[b];
-        block_sum<1>(acc);
-        if (threadIdx.x == 0) *slot = acc[0];
+        for (int b = lane; b < jb.nb; b += kWave) acc += r[b];
+        acc = wave_sum(acc);
+        if (lane == 0) *slot = acc;
       } else {
-        const double* cp = F.sc.spread + (size_t)(jb.slot + m) * kSpread * kSpreadStride;
-        const double c = threadIdx.x < kSpread ? cp[(size_t)threadIdx.x * kSpreadStride] : 0.0;
+        double* cp = F.sc.spread + ((size_t)(jb.slot + m) * kSpread + lane) * kSpreadStride;
+        const double c = *cp;  // kSpread == kWave: one copy per lane
+        *cp = 0.0;
         if (jb.op == F_SPREAD_MAX) {
-          const double r = block_max(c);
-          if (threadIdx.x == 0) *slot = r;
+          const double r = wave_max(c);
+          if (lane == 0) *slot = r;
         } else {
-          double acc[1] = {c};
-          block_sum<1>(acc);
-          if (threadIdx.x == 0) *slot = acc[0];
+          const double r = wave_sum(c);
+          if (lane == 0) *slot += r;
         }
       }
     }
   }
+  if (F.clear_int && threadIdx.x == 0) *F.clear_int = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_reset_slots(Scratch sc, int first, int count) {
@@ -456,7 +472,8 @@ int ilog2(int n) {
 // One pass along `axis` over nb batch fields.
 template <int MODE>
 void fft_pass(hipStream_t s, const Grid& G, int nb, double2* data, int axis, double sgn,
-              const double2* tw, const RealIO* io, const double* prev, double* red) {
+              const double2* tw, const RealIO* io, const double* prev, double* clear,
+              const Scratch& sc) {
   FftPass A;
   A.data = data;
   A.tw = tw;
@@ -476,7 +493,8 @@ void fft_pass(hipStream_t s, const Grid& G, int nb, double2* data, int axis, dou
       A.io.stride[b] = 1;
     }
   A.prev = prev;
-  A.red = red;
+  A.clear = clear;
+  A.sc = sc;
   const int P = kBlock / (A.N / 2);
   const unsigned nblk = (unsigned)((A.npencils + P - 1) / P);
   k_fft<MODE><<<nblk, kBlock, 0, s>>>(A);
@@ -603,24 +621,25 @@ __global__ __launch_bounds__(kBlock) void k_fields_EB(Grid G, const double2* cur
 }  // namespace
 
 void fft3_forward(hipStream_t s, const Grid& G, int nb, double2* data, const RealIO* in,
-                  const double* prev, const double2* const* tw, Scratch sc) {
+                  const double* prev, const double2* const* tw, Scratch sc, double* clear) {
   // z (contiguous) first, reading the real input; then y and x in place
   if (in)
-    fft_pass<1>(s, G, nb, data, 2, -1.0, tw[2], in, prev, sc.red);
+    fft_pass<1>(s, G, nb, data, 2, -1.0, tw[2], in, prev, clear, sc);
   else
-    fft_pass<0>(s, G, nb, data, 2, -1.0, tw[2], nullptr, nullptr, sc.red);
-  fft_pass<0>(s, G, nb, data, 1, -1.0, tw[1], nullptr, nullptr, sc.red);
-  fft_pass<0>(s, G, nb, data, 0, -1.0, tw[0], nullptr, nullptr, sc.red);
+    fft_pass<0>(s, G, nb, data, 2, -1.0, tw[2], nullptr, nullptr, nullptr, sc);
+  fft_pass<0>(s, G, nb, data, 1, -1.0, tw[1], nullptr, nullptr, nullptr, sc);
+  fft_pass<0>(s, G, nb, data, 0, -1.0, tw[0], nullptr, nullptr, nullptr, sc);
 }
 
 void fft3_inverse(hipStream_t s, const Grid& G, int nb, double2* data, const RealIO* out,
                   const double2* const* tw) {
-  fft_pass<0>(s, G, nb, data, 0, +1.0, tw[0], nullptr, nullptr, nullptr);
-  fft_pass<0>(s, G, nb, data, 1, +1.0, tw[1], nullptr, nullptr, nullptr);
+  const Scratch none{};
+  fft_pass<0>(s, G, nb, data, 0, +1.0, tw[0], nullptr, nullptr, nullptr, none);
+  fft_pass<0>(s, G, nb, data, 1, +1.0, tw[1], nullptr, nullptr, nullptr, none);
   if (out)
-    fft_pass<2>(s, G, nb, data, 2, +1.0, tw[2], out, nullptr, nullptr);
+    fft_pass<2>(s, G, nb, data, 2, +1.0, tw[2], out, nullptr, nullptr, none);
   else
-    fft_pass<0>(s, G, nb, data, 2, +1.0, tw[2], nullptr, nullptr, nullptr);
+    fft_pass<0>(s, G, nb, data, 2, +1.0, tw[2], nullptr, nullptr, nullptr, none);
 }
 
 void launch_cn_update(hipStream_t s, const FieldParams& F, const double2* cur, const double2* Jh,
@@ -666,12 +685,13 @@ void launch_set_A0(hipStream_t s, int64_t ncell, const double* A, double* gbuf) 
   k_set_A0<<<blocks_for(ncell), kBlock, 0, s>>>(ncell, A, gbuf);
 }
 
-void launch_finish(hipStream_t s, Scratch sc, const FinishJob* jobs, int njobs) {
+void launch_finish(hipStream_t s, Scratch sc, const FinishJob* jobs, int njobs, int* clear_int) {
   FinishArgs F;
   F.sc = sc;
   F.njobs = njobs < kMaxFinishJobs ? njobs : kMaxFinishJobs;
   for (int j = 0; j < F.njobs; ++j) F.job[j] = jobs[j];
-  if (F.njobs > 0) k_finish<<<1, kBlock, 0, s>>>(F);
+  F.clear_int = clear_int;
+  if (F.njobs > 0 || clear_int) k_finish<<<1, kFinishThreads, 0, s>>>(F);
 }
 
 int64_t mesh_blocks(int64_t ncell) { return (ncell + kBlock - 1) / kBlock; }

@@ -9,6 +9,7 @@
 // run of contiguous loads.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -832,26 +833,23 @@ __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& 
 // box of nodes its orbits touch (one node of margin per side against rounding
 // of piece midpoints), copies the gather fields of that box into LDS, and
 // every stencil read of the node loop then comes from LDS; a block whose box
-// does not fit the tile only raises its flag.  TILED = false: the blocks
-// whose flag is raised (all blocks when flags is null) read the gather
-// buffer in global memory.  Two kernels keep each one's register budget.
+// does not fit the tile appends its index to a work list (work[0] = count,
+// work[1..] = block indices).  TILED = false: the blocks on that list (all
+// blocks when work is null) read the gather buffer in global memory, a small
+// grid looping over the list.  Two kernels keep each one's register budget.
 constexpr int kGatherTileNodes = 512;
+constexpr int kGatherListGrid = 512;  // blocks of the global-memory kernel with a list
 
+// Block bid of 256 particles; thread 0 must have run late_reduce_init<4>()
+// and late_reduce_init<2>() before a barrier that precedes the call.
 template <int R, bool TILED, class PS, bool SPLIT>
-__global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
-                                                       const double* __restrict__ vit,
-                                                       double* __restrict__ vnew, AosFields F,
-                                                       int* __restrict__ flags, Scratch sc,
-                                                       AndersonPrev prev) {
+__device__ __forceinline__ void gather_block(const StepParams& P, const PS& st,
+                                             const double* __restrict__ vit,
+                                             double* __restrict__ vnew, const AosFields& F,
+                                             int* __restrict__ work, const Scratch& sc,
+                                             const AndersonPrev& prev, int bid) {
   constexpr int W = R + 1;
-  late_reduce_init<4>();
-  late_reduce_init<2>();
-  if (!TILED) {
-    if (flags && flags[blockIdx.x] == 0) return;  // done by the tiled kernel
-    __syncthreads();
-    if (threadIdx.x == 0 && flags) flags[blockIdx.x] = 0;
-  }
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = (int64_t)bid * kBlock + threadIdx.x;
   const bool active = i < P.np;
   double dvm = 0.0, vm = 0.0, bad = 0.0;
   double npieces[1] = {0.0};
@@ -909,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
                       dim[2] <= kGatherTileNodes;
     const int64_t vol = fits ? (int64_t)dim[0] * dim[1] * dim[2] : kGatherTileNodes + 1;
     if (vol > kGatherTileNodes) {  // leave the block to the global kernel
-      if (threadIdx.x == 0) flags[blockIdx.x] = 1;
+      if (threadIdx.x == 0) work[1 + atomicAdd(work, 1)] = bid;
       return;
     }
     const int nt2 = (int)vol * (kGbufStride / 2);
@@ -975,9 +973,33 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
     const bool sums[2] = {false, false};
     double ab[2];
     if (late_reduce<2>(aa, sums, ab)) {
-      sc.region(P_AA)[blockIdx.x] = ab[0];
-      sc.region(P_AA)[gridDim.x + blockIdx.x] = ab[1];
+      const int64_t nb = (P.np + kBlock - 1) / kBlock;
+      sc.region(P_AA)[bid] = ab[0];
+      sc.region(P_AA)[nb + bid] = ab[1];
     }
+  }
+}
+
+template <int R, bool TILED, class PS, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
+                                                       const double* __restrict__ vit,
+                                                       double* __restrict__ vnew, AosFields F,
+                                                       int* __restrict__ work, Scratch sc,
+                                                       AndersonPrev prev) {
+  if (TILED || !work) {
+    late_reduce_init<4>();
+    late_reduce_init<2>();
+    if (!TILED) __syncthreads();  // the tiled path has a barrier before its first use
+    gather_block<R, TILED, PS, SPLIT>(P, st, vit, vnew, F, work, sc, prev, blockIdx.x);
+    return;
+  }
+  const int count = work[0];  // written by the tiled kernel (previous launch)
+  for (int j = blockIdx.x; j < count; j += gridDim.x) {
+    __syncthreads();  // the previous block's LDS reductions are complete
+    late_reduce_init<4>();
+    late_reduce_init<2>();
+    __syncthreads();
+    gather_block<R, TILED, PS, SPLIT>(P, st, vit, vnew, F, work, sc, prev, work[1 + j]);
   }
 }
 
@@ -1301,15 +1323,16 @@ void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, con
 
 template <class PS>
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
-                        const double* vit, double* vnew, const double* gbuf, int* flags,
+                        const double* vit, double* vnew, const double* gbuf, int* work,
                         Scratch sc, AndersonPrev prev) {
   if (P.np <= 0) return;
   AosFields F{gbuf};
   const unsigned nb = blocks_for(P.np);
+  const unsigned ng = work ? std::min<unsigned>(nb, kGatherListGrid) : nb;
 #define ECPIC_GATHER_PAIR(R_, SPLIT_)                                                          \
-  k_gather_push<R_, true, PS, SPLIT_><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc,   \
+  k_gather_push<R_, true, PS, SPLIT_><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, work, sc,    \
                                                              prev);                            \
-  k_gather_push<R_, false, PS, SPLIT_><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, flags, sc,  \
+  k_gather_push<R_, false, PS, SPLIT_><<<ng, kBlock, 0, s>>>(P, st, vit, vnew, F, work, sc,   \
                                                               prev)
   if constexpr (!PS::kMixed) {
     if (!P.split) {
