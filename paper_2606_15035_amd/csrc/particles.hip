@@ -474,19 +474,23 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const T* __r
 
 // Orbit current of a chunk of kChunk particles per block.  Lanes take
 // particles with a stride of kChunk / 64 inside the chunk, so that for
-// cell-sorted particles the 64 lanes of a wavefront sit in ~kChunk / 64 / ppc
-// different cells and their LDS atomics rarely hit the same address.
+// cell-sorted particles the 64 lanes of a wavefront sit in up to
+// kChunk / (particles per cell) different cells and their LDS atomics rarely
+// hit the same address.
 // Pass 1 finds the box of nodes the chunk's orbits touch (unwrapped indices
 // relative to the chunk's first particle, one node of margin per side);
 // pass 2 accumulates the current in an LDS tile over that box; the tile is
 // then flushed with one global atomic per non-zero node value.  A chunk whose
-// box exceeds the tile adds straight to global memory.  Cubic stencils reach
-// two nodes further per axis, so their chunks hold half as many particles
-// (the box of 32 cells plus margins would overflow the tile).
-constexpr int kTileNodes = 2048;
+// box exceeds the tile adds straight to global memory.  A 4096-particle chunk
+// spans 64 cells at 64 particles per cell, so the 64 lanes of a wavefront sit
+// in 64 different cells and their atomics never meet on one address (2048
+// particles put two lanes in every cell: scatter 0.287 -> 0.245 ms at 32^3);
+// the 3072-node tile (72 KB) still leaves room for two blocks per CU.  Cubic
+// stencils reach two nodes further per axis, so their chunks are smaller.
+constexpr int kTileNodes = 3072;
 template <int R>
 struct ScatterChunk {
-  static constexpr int kChunk = R >= 3 ? 1024 : 2048;
+  static constexpr int kChunk = R >= 3 ? 1024 : 4096;
   static constexpr int kPerThread = kChunk / kBlock;  // particles per thread
   static constexpr int kSlot = kChunk / kWave;        // sorted particles per lane slot
 };
@@ -614,11 +618,17 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
   const int nt = use_tile ? dim[0] * dim[1] * dim[2] : 0;
   for (int t = threadIdx.x; t < 3 * nt; t += kBlock) tile[t] = 0.0;  // also integer zero
   __syncthreads();
-  // pass 2: accumulate
+  // pass 2: accumulate.  Pieces whose stencil lies outside the tile are
+  // skipped and their particles marked; a third pass adds those pieces to
+  // global memory.  Keeping the global path out of the main loop keeps the
+  // loop's register count (and so the kernel's occupancy) that of the tile path.
   const int64_t nc = P.G.ncell;
-  for (int k = 0; k < kPerThread; ++k) {
+  unsigned outside_mask = 0u;
+  auto process = [&](int k, auto global_phase) -> bool {
+    constexpr bool GLOBAL = decltype(global_phase)::value;
+    bool outside = false;
     const int64_t i = chunk_particle<R>(base, k);
-    if (i >= P.np) continue;
+    if (i >= P.np) return false;
     double x0[3], d[3], vb[3], c3[3];
     orbit_of(P, st, vit, i, x0, d, vb);
     // FP64: q_i vbar / dV; fixed point: (q_i / q_0) vbar in units of the quantum
@@ -638,7 +648,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
       const int oz = f[2] - s_ref[2] + shift[2] - tlo[2];
       const bool inside = use_tile && ox >= 0 && oy >= 0 && oz >= 0 && ox + W <= dim[0] &&
                           oy + W <= dim[1] && oz + W <= dim[2];
-      if (inside) {
+      outside = outside || !inside;
+      if (!GLOBAL && inside) {
 #pragma unroll
         for (int a = 0; a < W; ++a)
 #pragma unroll
@@ -655,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
                   atomicAdd(&tile[3 * t + l], w * c3[l]);
               }
             }
-      } else {
+      } else if (GLOBAL && !inside) {
 #pragma unroll
         for (int a = 0; a < W; ++a)
 #pragma unroll
@@ -687,6 +698,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
       const int oz = f[2] - s_ref[2] + shift[2] - tlo[2];
       const bool inside = use_tile && ox >= 0 && oy >= 0 && oz >= 0 && ox + W <= dim[0] &&
                           oy + W <= dim[1] && oz + W <= dim[2];
+      outside = outside || !inside;
+      if (GLOBAL == inside) return;
 #pragma unroll
       for (int a = 0; a < W; ++a)
 #pragma unroll
@@ -699,7 +712,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
             double w = 0.0;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) w += xy[q] * Z[q][c];
-            if (inside) {
+            if (!GLOBAL) {
               const int t = ((ox + a) * dim[1] + (oy + b)) * dim[2] + (oz + c);
 #pragma unroll
               for (int l = 0; l < 3; ++l) {
@@ -757,8 +770,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
         deposit(Iw, f);
       }
     }
-    if (!ok) bad = 1.0;
-  }
+    if (!ok && !GLOBAL) bad = 1.0;
+    return outside;
+  };
+  for (int k = 0; k < kPerThread; ++k)
+    if (process(k, std::false_type{})) outside_mask |= 1u << k;
+  for (int k = 0; k < kPerThread; ++k)
+    if ((outside_mask >> k) & 1u) process(k, std::true_type{});
   __syncthreads();
   const float inv_d1 = 1.0f / (float)max(dim[1], 1), inv_d2 = 1.0f / (float)max(dim[2], 1);
   for (int t = threadIdx.x; t < nt; t += kBlock) {
