@@ -1130,6 +1130,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.8"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.9"; }
 
 }  // extern "C"

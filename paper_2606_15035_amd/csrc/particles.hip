@@ -304,7 +304,9 @@ __device__ __forceinline__ void gather_piece(const Grid& G, const double* x0, co
 // product S_g = X_a Y_b Z_c is used once more: along each z column of the
 // stencil the quadrature-point sums B_q = sum_c b_c(s_q) Z_c(q) and
 // B'_q = sum_c b_c(s_q) Z'_c(q) are formed first, and the x and y factors
-// multiply those column sums, not every node.
+// multiply those column sums, not every node.  Derivatives are taken per unit
+// of cell coordinate: dtv accumulates H_j ((D A)^T vbar)_j, and the caller
+// multiplies by 1/H_j once per particle.
 template <int R, int NQ, class Acc>
 __device__ __forceinline__ void push_points(const Grid& G, const double* x0, const double* d,
                                             const double* base, const double* sq,
@@ -318,8 +320,6 @@ __device__ __forceinline__ void push_points(const Grid& G, const double* x0, con
     tx[q] = (x0[0] + s * d[0]) * G.invH[0] - base[0];
     ty[q] = (x0[1] + s * d[1]) * G.invH[1] - base[1];
     Spline<R>::wd((x0[2] + s * d[2]) * G.invH[2] - base[2], Z[q], dZ[q]);
-#pragma unroll
-    for (int k = 0; k < W; ++k) dZ[q][k] *= G.invH[2];
   }
   const int fx = to_int_clamped(base[0]) + Spline<R>::first_off;
   const int fy = to_int_clamped(base[1]) + Spline<R>::first_off;
@@ -332,7 +332,7 @@ __device__ __forceinline__ void push_points(const Grid& G, const double* x0, con
       double Xq, dXq;
       Spline<R>::wk(a, tx[q], Xq, dXq);
       Xw[q] = wq[q] * Xq;
-      dXw[q] = wq[q] * (dXq * G.invH[0]);
+      dXw[q] = wq[q] * dXq;
     }
 #pragma unroll
     for (int b = 0; b < W; ++b) {
@@ -343,7 +343,7 @@ __device__ __forceinline__ void push_points(const Grid& G, const double* x0, con
         Spline<R>::wk(b, ty[q], Yq, dYq);
         xyw[q] = Xw[q] * Yq;
         dxyw[q] = dXw[q] * Yq;
-        xdyw[q] = Xw[q] * (dYq * G.invH[1]);
+        xdyw[q] = Xw[q] * dYq;
       }
       const int row = acc.row(fx + a, fy + b);
       double B[NQ], dB[NQ];
@@ -486,11 +486,12 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const T* __r
 // in 64 different cells and their atomics never meet on one address (2048
 // particles put two lanes in every cell: scatter 0.287 -> 0.245 ms at 32^3);
 // the 3072-node tile (72 KB) still leaves room for two blocks per CU.  Cubic
-// stencils reach two nodes further per axis, so their chunks are smaller.
+// stencils reach two nodes further per axis, so their chunks are half as long
+// (one column of 32 cells plus the wider margins fits the tile).
 constexpr int kTileNodes = 3072;
 template <int R>
 struct ScatterChunk {
-  static constexpr int kChunk = R >= 3 ? 1024 : 4096;
+  static constexpr int kChunk = R >= 3 ? 2048 : 4096;
   static constexpr int kPerThread = kChunk / kBlock;  // particles per thread
   static constexpr int kSlot = kChunk / kWave;        // sorted particles per lane slot
 };
@@ -813,7 +814,7 @@ __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& 
                                                 double mi, double* vn, double& npieces,
                                                 double& bad) {
   double gp[3] = {0.0, 0.0, 0.0};
-  double dtv[3] = {0.0, 0.0, 0.0};  // (D A)^T vbar
+  double dtv[3] = {0.0, 0.0, 0.0};  // H_j ((D A)^T vbar)_j until the pieces are summed
   if constexpr (SPLIT) {
     const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
       push_piece<R>(P.G, x0, d, s0, s1, vb, acc, gp, dtv);
@@ -842,7 +843,8 @@ __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& 
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const double Pn = mi * va[j] + qi * A0s[j];
-    const double P1 = Pn + P.dt * (-qi * gp[j] + qi * dtv[j]);  // eq. orbit-P-update
+    const double DAv = dtv[j] * P.G.invH[j];                  // ((D A)^T vbar)_j
+    const double P1 = Pn + P.dt * (-qi * gp[j] + qi * DAv);   // eq. orbit-P-update
     vn[j] = (P1 - qi * A1e[j]) / mi;                          // eq. orbit-v-update
   }
 }
