@@ -288,7 +288,7 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->sc.spread = w.take<double>((size_t)S_NSLOTS * kSpread * kSpreadStride);
   const int64_t maxblk = std::max<int64_t>(
       std::max<int64_t>(particle_blocks(np), scatter_blocks(np, S->cfg.spline_degree)),
-      mesh_blocks(nc));
+      std::max<int64_t>(mesh_blocks(nc), cn_pencil_blocks(S->G)));
   S->sc.part_stride = std::max<int64_t>((int64_t)kMaxSumValues * (maxblk > 0 ? maxblk : 1),
                                         (int64_t)kAndersonSums * anderson_dot_blocks(3 * np));
   S->sc.part = w.take<double>((size_t)P_NSITES * S->sc.part_stride);
@@ -629,6 +629,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   on_store(S, [&](auto& st, auto&) { launch_extrapolate(s, S->np, st, S->vit); });
   const CurrentOut cout{nullptr, S->Jfix, S->fix_scale};
   const double fix_unit = S->q / S->G.dV / S->fix_scale;
+  const bool fused = fused_field_solve_fits(S->G);
   launch_reset_slots(s, S->sc, S_PIECES, 1);
   int p = 0, jcur = 1 - S->jlast;
   if (!S->jclean && !S->mixed()) launch_fill(s, 3 * nc, S->Jb[jcur], 0.0);  // after a failed step
@@ -661,11 +662,19 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     });
     if (S->mixed()) launch_fixed_current(s, 3 * nc, S->Jfix, J, fix_unit);
     if (prof) HIPCHK(hipEventRecord(S->ev[1], s));
-    RealIO jin = soa_io(J, nc, 3);
-    fft3_forward(s, S->G, 3, S->Jh, &jin, p >= 1 ? Jprev : nullptr, twp(S), S->sc,
-                 S->mixed() ? nullptr : Jprev);  // Jprev is the next pass's J
-    launch_cn_update(s, F, cur, S->Jh, nxt, S->batch, S->sc);  // continuity + CN
-    fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));         // grad phi^{n+1/2}, A^{n+1}
+    // transform of J (max|J - J_prev| folded into S_DJMAX; J_prev, the next
+    // pass's J, cleared in FP64), continuity + CN, inverse transform of
+    // grad phi^{n+1/2} and A^{n+1} into the gather buffer
+    double* jclear = S->mixed() ? nullptr : Jprev;
+    if (fused) {
+      field_solve_fused(s, F, J, p >= 1 ? Jprev : nullptr, jclear, cur, nxt, S->Jh, S->batch, gout,
+                        twp(S), S->sc);
+    } else {
+      RealIO jin = soa_io(J, nc, 3);
+      fft3_forward(s, S->G, 3, S->Jh, &jin, p >= 1 ? Jprev : nullptr, twp(S), S->sc, jclear);
+      launch_cn_update(s, F, cur, S->Jh, nxt, S->batch, S->sc);
+      fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));
+    }
     if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
     on_store(S, [&](auto& st, auto&) {  // v^{n+1,p+1}
       launch_gather_push(s, r, P, st, S->vit, S->vnew, S->gbuf, S->gflags, S->sc, prev);
@@ -678,7 +687,8 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     }
     if (mk >= 2) launch_anderson_dots(s, mk, n3, av, S->sc);
     {
-      const FinishJob jobs[7] = {{P_CN, (int)mesh_blocks(nc), 3, S_JE},
+      const FinishJob jobs[7] = {{P_CN, fused ? cn_pencil_blocks(S->G) : (int)mesh_blocks(nc), 3,
+                                  S_JE},
                                  {0, 0, 1, S_DJMAX, F_SPREAD_MAX},
                                  {P_JS, (int)scatter_blocks(S->np, r), 1, S_JS},
                                  {0, 0, 2, S_DVMAX, F_SPREAD_MAX},
@@ -1130,6 +1140,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.9"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.10"; }
 
 }  // extern "C"

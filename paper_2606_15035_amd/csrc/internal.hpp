@@ -239,6 +239,16 @@ struct FieldParams {
 // Continuity + CN update of every mode; writes the next spectral level, the
 // inverse-transform inputs [i k (phi0+phi1)/2, A1] / ncell, and S_JE, S_WNEXT,
 // S_DW.
+// The field solve of a Picard pass in three kernels (transforms along z and y
+// per x-plane, then x with the continuity + CN update per block of x-pencils,
+// then the inverse along y and z into the gather buffer); same results as
+// fft3_forward + launch_cn_update + fft3_inverse up to rounding.  Needs
+// ny nz <= 4096; the P_CN partial rows have cn_pencil_blocks(G) blocks.
+bool fused_field_solve_fits(const Grid& G);
+int cn_pencil_blocks(const Grid& G);
+void field_solve_fused(hipStream_t s, const FieldParams& F, const double* J, const double* prev,
+                       double* clear, const double2* cur, double2* next, double2* Jh,
+                       double2* batch, const RealIO& out, const double2* const* tw, Scratch sc);
 void launch_cn_update(hipStream_t s, const FieldParams& F, const double2* cur, const double2* Jh,
                       double2* next, double2* inv, Scratch sc);
 // (U0 + U1)/2 / ncell into inv[0..2]

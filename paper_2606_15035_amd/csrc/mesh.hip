@@ -10,6 +10,8 @@
 // kernel that prepares its input.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.hpp"
 #include "reduce.hpp"
 
@@ -171,98 +173,112 @@ struct CNArgs {
   Scratch sc;
 };
 
+// One mode: c = the 9 level-n spectra (field order of a level), J = the 3
+// current spectra; out = the 9 level-(n+1) spectra, inv = the inverse-transform
+// inputs [i k phi^{n+1/2} (3), A^{n+1} (3)] / ncell, sums = JE, W^{n+1} and
+// W^{n+1} - W^n of this mode (times dV / ncell, Parseval).
+__device__ __forceinline__ void cn_mode(const FieldParams& F, const double* k, const double2* J,
+                                        const double2* c, double2* out, double2* inv,
+                                        double* sums) {
+  const Grid& G = F.G;
+  const double dt = F.dt, a = 0.5 * dt, kap2 = F.kappa * F.kappa;
+  const double w2 = kap2 * (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  const double inv_den = 1.0 / (1.0 + a * a * w2);
+  const double c_old = 1.0 - a * a * w2, c_x = 2.0 * a * w2;
+  double2 A0[3], U0[3], A1[3], U1[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    A0[l] = c[F_A + l];
+    U0[l] = c[F_U + l];
+  }
+  const double2 phi0 = c[F_PHI], psi0 = c[F_PSI], rho0 = c[F_RHO];
+  const double2 divJ = cadd(cadd(ik(k[0], J[0]), ik(k[1], J[1])), ik(k[2], J[2]));
+  const double2 rho1 = csub(rho0, cscale(divJ, dt));
+  const double2 rhoh = cscale(cadd(rho0, rho1), 0.5);
+  const double src1 = dt * kap2 * F.sigma1, src2 = dt * kap2 * F.sigma2;
+  double2 psi1, phi1;
+  psi1.x = (c_old * psi0.x - c_x * phi0.x + src1 * rhoh.x) * inv_den;
+  psi1.y = (c_old * psi0.y - c_x * phi0.y + src1 * rhoh.y) * inv_den;
+  phi1 = cadd(phi0, cscale(cadd(psi0, psi1), a));
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    U1[l].x = (c_old * U0[l].x - c_x * A0[l].x + src2 * J[l].x) * inv_den;
+    U1[l].y = (c_old * U0[l].y - c_x * A0[l].y + src2 * J[l].y) * inv_den;
+    A1[l] = cadd(A0[l], cscale(cadd(U0[l], U1[l]), a));
+  }
+  out[F_PHI] = phi1;
+  out[F_PSI] = psi1;
+  out[F_RHO] = rho1;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    out[F_A + l] = A1[l];
+    out[F_U + l] = U1[l];
+  }
+  // inverse-transform inputs: grad_h phi^{n+1/2} and A^{n+1}, scaled by 1/ncell
+  const double sc = 1.0 / (double)G.ncell;
+  const double2 phih = cscale(cadd(phi0, phi1), 0.5);
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    inv[l] = cscale(ik(k[l], phih), sc);
+    inv[3 + l] = cscale(A1[l], sc);
+  }
+  // Parseval: sum_g f_g h_g = (1/ncell) sum_k Re(conj(f^_k) h^_k)
+  const double h1 = 0.5 / F.sigma1, h2 = 0.5 / F.sigma2;
+  double je = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double2 Uh = cscale(cadd(U0[l], U1[l]), 0.5);
+    const double2 Eh = csub(make_double2(k[l] * phih.y, -k[l] * phih.x), Uh);  // -i k phi - U
+    je += J[l].x * Eh.x + J[l].y * Eh.y;
+  }
+  const double e1 = mode_energy(k, phi1, A1, U1, h1, h2);
+  // W^{n+1} - W^n per mode as (f1 - f0).(f1 + f0) to keep the difference accurate
+  double de = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double2 E1 = csub(make_double2(k[l] * phi1.y, -k[l] * phi1.x), U1[l]);
+    const double2 E0 = csub(make_double2(k[l] * phi0.y, -k[l] * phi0.x), U0[l]);
+    const double2 dE = csub(E1, E0), sE = cadd(E1, E0);
+    de += h1 * (dE.x * sE.x + dE.y * sE.y);
+  }
+  double2 dA[3], sA[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    dA[l] = csub(A1[l], A0[l]);
+    sA[l] = cadd(A1[l], A0[l]);
+  }
+  const double2 dB[3] = {csub(ik(k[1], dA[2]), ik(k[2], dA[1])),
+                         csub(ik(k[2], dA[0]), ik(k[0], dA[2])),
+                         csub(ik(k[0], dA[1]), ik(k[1], dA[0]))};
+  const double2 sB[3] = {csub(ik(k[1], sA[2]), ik(k[2], sA[1])),
+                         csub(ik(k[2], sA[0]), ik(k[0], sA[2])),
+                         csub(ik(k[0], sA[1]), ik(k[1], sA[0]))};
+#pragma unroll
+  for (int l = 0; l < 3; ++l) de += h2 * (dB[l].x * sB[l].x + dB[l].y * sB[l].y);
+  const double f = G.dV / (double)G.ncell;
+  sums[0] = je * f;
+  sums[1] = e1 * f;
+  sums[2] = de * f;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cn(CNArgs C) {
   const Grid& G = C.F.G;
   const int64_t nc = G.ncell;
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  double sums[3] = {0.0, 0.0, 0.0};  // JE, W^{n+1}, W^{n+1} - W^n (before the dV/ncell factor)
+  double sums[3] = {0.0, 0.0, 0.0};  // JE, W^{n+1}, W^{n+1} - W^n
   if (g < nc) {
     double k[3];
     mode_k(G, g, k);
-    const double dt = C.F.dt, a = 0.5 * dt, kap2 = C.F.kappa * C.F.kappa;
-    const double w2 = kap2 * (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
-    const double inv_den = 1.0 / (1.0 + a * a * w2);
-    const double c_old = 1.0 - a * a * w2, c_x = 2.0 * a * w2;
-    double2 J[3], A0[3], U0[3], A1[3], U1[3];
+    double2 J[3], c[9], out[9], inv[6];
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      J[l] = C.Jh[l * nc + g];
-      A0[l] = ld(C.cur, F_A + l, nc, g);
-      U0[l] = ld(C.cur, F_U + l, nc, g);
-    }
-    const double2 phi0 = ld(C.cur, F_PHI, nc, g), psi0 = ld(C.cur, F_PSI, nc, g);
-    const double2 rho0 = ld(C.cur, F_RHO, nc, g);
-    const double2 divJ = cadd(cadd(ik(k[0], J[0]), ik(k[1], J[1])), ik(k[2], J[2]));
-    const double2 rho1 = csub(rho0, cscale(divJ, dt));
-    const double2 rhoh = cscale(cadd(rho0, rho1), 0.5);
-    const double src1 = dt * kap2 * C.F.sigma1, src2 = dt * kap2 * C.F.sigma2;
-    double2 psi1, phi1;
-    psi1.x = (c_old * psi0.x - c_x * phi0.x + src1 * rhoh.x) * inv_den;
-    psi1.y = (c_old * psi0.y - c_x * phi0.y + src1 * rhoh.y) * inv_den;
-    phi1 = cadd(phi0, cscale(cadd(psi0, psi1), a));
+    for (int l = 0; l < 3; ++l) J[l] = C.Jh[l * nc + g];
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      U1[l].x = (c_old * U0[l].x - c_x * A0[l].x + src2 * J[l].x) * inv_den;
-      U1[l].y = (c_old * U0[l].y - c_x * A0[l].y + src2 * J[l].y) * inv_den;
-      A1[l] = cadd(A0[l], cscale(cadd(U0[l], U1[l]), a));
-    }
-    double2* nx = C.next;
-    nx[F_PHI * nc + g] = phi1;
-    nx[F_PSI * nc + g] = psi1;
-    nx[F_RHO * nc + g] = rho1;
+    for (int f = 0; f < 9; ++f) c[f] = ld(C.cur, f, nc, g);
+    cn_mode(C.F, k, J, c, out, inv, sums);
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      nx[(F_A + l) * nc + g] = A1[l];
-      nx[(F_U + l) * nc + g] = U1[l];
-    }
-    // inverse-transform inputs: grad_h phi^{n+1/2} and A^{n+1}, scaled by 1/ncell
-    const double sc = 1.0 / (double)nc;
-    const double2 phih = cscale(cadd(phi0, phi1), 0.5);
+    for (int f = 0; f < 9; ++f) C.next[f * nc + g] = out[f];
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      C.inv[l * nc + g] = cscale(ik(k[l], phih), sc);
-      C.inv[(3 + l) * nc + g] = cscale(A1[l], sc);
-    }
-    // Parseval: sum_g f_g h_g = (1/ncell) sum_k Re(conj(f^_k) h^_k)
-    const double h1 = 0.5 / C.F.sigma1, h2 = 0.5 / C.F.sigma2;
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      const double2 Uh = cscale(cadd(U0[l], U1[l]), 0.5);
-      const double2 Eh = csub(make_double2(k[l] * phih.y, -k[l] * phih.x), Uh);  // -i k phi - U
-      sums[0] += J[l].x * Eh.x + J[l].y * Eh.y;
-    }
-    const double e1 = mode_energy(k, phi1, A1, U1, h1, h2);
-    sums[1] = e1;
-    // W^{n+1} - W^n per mode as (f1 - f0).(f1 + f0) to keep the difference accurate
-    {
-      double de = 0.0;
-#pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        const double2 E1 = csub(make_double2(k[l] * phi1.y, -k[l] * phi1.x), U1[l]);
-        const double2 E0 = csub(make_double2(k[l] * phi0.y, -k[l] * phi0.x), U0[l]);
-        const double2 dE = csub(E1, E0), sE = cadd(E1, E0);
-        de += h1 * (dE.x * sE.x + dE.y * sE.y);
-      }
-      double2 dA[3], sA[3];
-#pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        dA[l] = csub(A1[l], A0[l]);
-        sA[l] = cadd(A1[l], A0[l]);
-      }
-      const double2 dB[3] = {csub(ik(k[1], dA[2]), ik(k[2], dA[1])),
-                             csub(ik(k[2], dA[0]), ik(k[0], dA[2])),
-                             csub(ik(k[0], dA[1]), ik(k[1], dA[0]))};
-      const double2 sB[3] = {csub(ik(k[1], sA[2]), ik(k[2], sA[1])),
-                             csub(ik(k[2], sA[0]), ik(k[0], sA[2])),
-                             csub(ik(k[0], sA[1]), ik(k[1], sA[0]))};
-#pragma unroll
-      for (int l = 0; l < 3; ++l) de += h2 * (dB[l].x * sB[l].x + dB[l].y * sB[l].y);
-      sums[2] = de;
-    }
-    const double f = G.dV / (double)nc;
-    sums[0] *= f;
-    sums[1] *= f;
-    sums[2] *= f;
+    for (int f = 0; f < 6; ++f) C.inv[f * nc + g] = inv[f];
   }
   block_partials<3>(sums, C.sc.region(P_CN));  // -> S_JE, S_WNEXT, S_DW
 }
@@ -500,6 +516,186 @@ void fft_pass(hipStream_t s, const Grid& G, int nb, double2* data, int axis, dou
   k_fft<MODE><<<nblk, kBlock, 0, s>>>(A);
 }
 
+// ---- fused field solve of a Picard pass -----------------------------------
+// Three kernels instead of seven: (1) per field and x-plane, the forward
+// transform along z and y of the real current in LDS (with max|J - J_prev|
+// and the clearing of J_prev); (2) per block of x-pencils, the forward
+// transform along x, the continuity + CN update of every mode of those
+// pencils, and the inverse transform along x of the six gather fields;
+// (3) per field and x-plane, the inverse transform along y and z with the real
+// part written to the gather buffer.  Four x-pencils per block: at 32^3
+// that is 256 blocks (16 pencils per block: 64 blocks, 23 us for the pencil
+// kernel alone; 4: 0.035 ms for the whole solve against 0.047 for seven
+// kernels).  Every 1-D transform is the radix-2
+// decimation in time of k_fft with bit-reversed LDS input; in a plane both
+// indices are bit-reversed at load, so the z and y stages run back to back.
+constexpr int kPlaneMax = 4096;  // ny nz limit of the plane kernels (64 KB of LDS)
+
+__device__ __forceinline__ int brev(int e, int logn) {
+  return (int)(__brev((unsigned)e) >> (32 - logn));
+}
+
+__device__ __forceinline__ void butterfly(double2* lds, int i0, int i1, double2 w) {
+  const double2 a = lds[i0];
+  const double2 b = cmul(lds[i1], w);
+  lds[i0] = cadd(a, b);
+  lds[i1] = csub(a, b);
+}
+
+struct PlaneArgs {
+  Grid G;
+  const double2* tw_y;  // exp(-2 pi i t / ny), t < ny/2
+  const double2* tw_z;
+  int logy, logz;
+  // forward: real SoA input (nb fields), optional prev / clear, complex output
+  const double* in;
+  const double* prev;
+  double* clear;
+  double2* cout;
+  // inverse: complex input, real output through io
+  const double2* cin;
+  RealIO io;
+  Scratch sc;
+};
+
+// INVERSE = false: block = (field, x-plane) of the forward transform;
+// true: of the inverse transform (conjugate twiddles, real output).
+template <bool INVERSE>
+__global__ __launch_bounds__(kBlock) void k_fft_plane(PlaneArgs A) {
+  __shared__ double2 buf[kPlaneMax];
+  const Grid& G = A.G;
+  const int ny = G.n[1], nz = G.n[2], plane = ny * nz, nx = G.n[0];
+  const int b = blockIdx.x / nx, ix = blockIdx.x % nx;
+  const int64_t base = (int64_t)ix * plane, fo = (int64_t)b * G.ncell;
+  double dmax = 0.0;
+  for (int e = threadIdx.x; e < plane; e += kBlock) {
+    const int iy = e >> A.logz, iz = e & (nz - 1);
+    const int64_t g = base + e;
+    double2 v;
+    if constexpr (INVERSE) {
+      v = A.cin[fo + g];
+    } else {
+      const double re = A.in[fo + g];
+      if (A.prev) dmax = fmax(dmax, fabs(re - A.prev[fo + g]));
+      if (A.clear) A.clear[fo + g] = 0.0;  // after prev was read (same element)
+      v = make_double2(re, 0.0);
+    }
+    buf[(brev(iy, A.logy) << A.logz) | brev(iz, A.logz)] = v;
+  }
+  __syncthreads();
+  const int hz = nz >> 1, hy = ny >> 1;
+  for (int hs = 1; hs < nz; hs <<= 1) {  // along z: rows of nz
+    for (int u = threadIdx.x; u < ny * hz; u += kBlock) {
+      const int row = u / hz, j = u - row * hz, pos = j % hs;
+      const int i0 = (j / hs) * 2 * hs + pos;
+      double2 w = A.tw_z[pos * (hz / hs)];
+      if (INVERSE) w.y = -w.y;
+      butterfly(buf + row * nz, i0, i0 + hs, w);
+    }
+    __syncthreads();
+  }
+  for (int hs = 1; hs < ny; hs <<= 1) {  // along y: columns of ny, stride nz
+    for (int u = threadIdx.x; u < hy * nz; u += kBlock) {
+      const int col = u & (nz - 1), j = u >> A.logz, pos = j % hs;
+      const int i0 = (j / hs) * 2 * hs + pos;
+      double2 w = A.tw_y[pos * (hy / hs)];
+      if (INVERSE) w.y = -w.y;
+      butterfly(buf, i0 * nz + col, (i0 + hs) * nz + col, w);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < plane; e += kBlock) {
+    const int64_t g = base + e;
+    if constexpr (INVERSE)
+      A.io.p[b][g * A.io.stride[b]] = buf[e].x;
+    else
+      A.cout[fo + g] = buf[e];
+  }
+  if constexpr (!INVERSE) {
+    if (A.prev) {
+      const double r = block_max(dmax);
+      if (threadIdx.x == 0) atomic_max_nonneg(A.sc.spread_copy(S_DJMAX), r);
+    }
+  }
+}
+
+struct PencilArgs {
+  FieldParams F;
+  const double2* tw_x;
+  int logx, npl;       // pencils per block
+  const double2* Jh;   // 3 fields after the z and y transforms
+  const double2* cur;  // level n (9 fields)
+  double2* next;       // level n+1 (9 fields)
+  double2* inv;        // 6 gather fields after the inverse x transform
+  Scratch sc;
+};
+
+constexpr int kPencilLds = 2 * kBlock + 16;  // npl * (nx + 1) <= 2 kBlock + npl, npl <= 16
+
+__global__ __launch_bounds__(kBlock) void k_cn_pencils(PencilArgs A) {
+  __shared__ double2 jb[3 * kPencilLds];
+  __shared__ double2 ib[6 * kPencilLds];
+  const Grid& G = A.F.G;
+  const int nx = G.n[0], hx = nx >> 1, npl = A.npl, ld = nx + 1;  // padded pencil stride
+  const int64_t S = (int64_t)G.n[1] * G.n[2], nc = G.ncell;
+  const int64_t q0 = (int64_t)blockIdx.x * npl;  // first pencil (iy nz + iz) of the block
+  const int span = npl * nx;
+  // the three current spectra, pencil by pencil, bit-reversed along x
+  for (int f = 0; f < 3; ++f)
+    for (int e = threadIdx.x; e < span; e += kBlock) {
+      const int kx = e / npl, pl = e - kx * npl;
+      jb[f * kPencilLds + pl * ld + brev(kx, A.logx)] = A.Jh[f * nc + kx * S + q0 + pl];
+    }
+  __syncthreads();
+  for (int hs = 1; hs < nx; hs <<= 1) {
+    for (int u = threadIdx.x; u < 3 * npl * hx; u += kBlock) {
+      const int f = u / (npl * hx), r = u - f * npl * hx, pl = r / hx, j = r - pl * hx;
+      const int pos = j % hs, i0 = (j / hs) * 2 * hs + pos;
+      butterfly(jb + f * kPencilLds + pl * ld, i0, i0 + hs, A.tw_x[pos * (hx / hs)]);
+    }
+    __syncthreads();
+  }
+  // continuity + CN of every mode of the block's pencils
+  double sums[3] = {0.0, 0.0, 0.0};
+  for (int e = threadIdx.x; e < span; e += kBlock) {
+    const int kx = e / npl, pl = e - kx * npl;
+    const int64_t g = kx * S + q0 + pl;
+    double k[3];
+    mode_k(G, g, k);
+    double2 J[3], c[9], out[9], iv[6];
+    double s3[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) J[l] = jb[l * kPencilLds + pl * ld + kx];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) c[f] = A.cur[f * nc + g];
+    cn_mode(A.F, k, J, c, out, iv, s3);
+#pragma unroll
+    for (int f = 0; f < 9; ++f) A.next[f * nc + g] = out[f];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) ib[f * kPencilLds + pl * ld + brev(kx, A.logx)] = iv[f];
+    sums[0] += s3[0];
+    sums[1] += s3[1];
+    sums[2] += s3[2];
+  }
+  __syncthreads();
+  for (int hs = 1; hs < nx; hs <<= 1) {
+    for (int u = threadIdx.x; u < 6 * npl * hx; u += kBlock) {
+      const int f = u / (npl * hx), r = u - f * npl * hx, pl = r / hx, j = r - pl * hx;
+      const int pos = j % hs, i0 = (j / hs) * 2 * hs + pos;
+      double2 w = A.tw_x[pos * (hx / hs)];
+      w.y = -w.y;
+      butterfly(ib + f * kPencilLds + pl * ld, i0, i0 + hs, w);
+    }
+    __syncthreads();
+  }
+  for (int f = 0; f < 6; ++f)
+    for (int e = threadIdx.x; e < span; e += kBlock) {
+      const int kx = e / npl, pl = e - kx * npl;
+      A.inv[f * nc + kx * S + q0 + pl] = ib[f * kPencilLds + pl * ld + kx];
+    }
+  block_partials<3>(sums, A.sc.region(P_CN));  // -> S_JE, S_WNEXT, S_DW
+}
+
 // ---- adjoint of the field update ----------------------------------------
 // Complex spectra carry adjoints in the convention dL = Re sum conj(lambda) dz;
 // every coefficient of k_cn is real except -dt i k of the continuity update,
@@ -640,6 +836,53 @@ void fft3_inverse(hipStream_t s, const Grid& G, int nb, double2* data, const Rea
     fft_pass<2>(s, G, nb, data, 2, +1.0, tw[2], out, nullptr, nullptr, none);
   else
     fft_pass<0>(s, G, nb, data, 2, +1.0, tw[2], nullptr, nullptr, nullptr, none);
+}
+
+bool fused_field_solve_fits(const Grid& G) {
+  return G.n[1] * G.n[2] <= kPlaneMax && G.n[0] <= 2 * kBlock;
+}
+
+int cn_pencil_blocks(const Grid& G) {
+  const int npl = std::min(4, kBlock / (G.n[0] / 2));
+  return (int)((int64_t)G.n[1] * G.n[2] / npl);
+}
+
+void field_solve_fused(hipStream_t s, const FieldParams& F, const double* J, const double* prev,
+                       double* clear, const double2* cur, double2* next, double2* Jh,
+                       double2* batch, const RealIO& out, const double2* const* tw, Scratch sc) {
+  const Grid& G = F.G;
+  PlaneArgs A{};
+  A.G = G;
+  A.tw_y = tw[1];
+  A.tw_z = tw[2];
+  A.logy = ilog2(G.n[1]);
+  A.logz = ilog2(G.n[2]);
+  A.in = J;
+  A.prev = prev;
+  A.clear = clear;
+  A.cout = Jh;
+  A.sc = sc;
+  k_fft_plane<false><<<3 * G.n[0], kBlock, 0, s>>>(A);
+  PencilArgs C{};
+  C.F = F;
+  C.tw_x = tw[0];
+  C.logx = ilog2(G.n[0]);
+  C.npl = std::min(4, kBlock / (G.n[0] / 2));
+  C.Jh = Jh;
+  C.cur = cur;
+  C.next = next;
+  C.inv = batch;
+  C.sc = sc;
+  k_cn_pencils<<<cn_pencil_blocks(G), kBlock, 0, s>>>(C);
+  PlaneArgs B{};
+  B.G = G;
+  B.tw_y = tw[1];
+  B.tw_z = tw[2];
+  B.logy = A.logy;
+  B.logz = A.logz;
+  B.cin = batch;
+  B.io = out;
+  k_fft_plane<true><<<6 * G.n[0], kBlock, 0, s>>>(B);
 }
 
 void launch_cn_update(hipStream_t s, const FieldParams& F, const double2* cur, const double2* Jh,

@@ -272,6 +272,17 @@ def test_gather_tiled_and_global_blocks():
         compare_states(wl, g, o, f"tiled+global step {step}")
 
 
+def test_large_plane_mesh_uses_the_seven_kernel_solve():
+    """ny nz = 8192 exceeds the plane kernels of the fused field solve, so the
+    Picard pass takes the per-axis transforms and the separate CN kernel."""
+    wl = W.random_plasma((4, 128, 64), (0.3, 2.0, 1.0), 2000, r=2, dt=0.2, vth=0.05,
+                         drift=(0.02, 0.01, -0.01), seed=23)
+    g, o = both(wl, tol=0.0, pmax=2)
+    for step in range(2):
+        assert g.picard_step()["iters"] == o.step()["iters"] == 3
+        compare_states(wl, g, o, f"4x128x64 step {step}")
+
+
 def test_no_particles_vacuum_fields():
     """Empty particle set: the step is the source-free CN update of the fields."""
     wl = small_random(2, np_=1)
