@@ -39,6 +39,7 @@ enum Slot : int {
   S_RL2,        // sum R_h^2                            (sum)
   S_WCUR,       // W of the current field level         (sum)
   S_PIECES,     // orbit pieces summed over particles    (sum of integers)
+  S_SMISS,      // scatter chunks whose node box missed the LDS tile (sum of integers)
   S_NSLOTS
 };
 // Producer sites of block partial sums (each has its own region).
@@ -63,6 +64,7 @@ struct StepParams {
   // particle species (each particle carries its own charge and mass, Sec. 2):
   // a particle of species s has qs[s], ms[s]; one species: the store holds no
   // species array and every particle has (q, m) = (qs[0], ms[0])
+  int chunk;  // particles per scatter block: 4096 or 2048 (always 2048 for degree 3)
   int nsp;
   double qs[kMaxSpecies];
   double ms[kMaxSpecies];
@@ -133,7 +135,7 @@ void launch_anderson_update(hipStream_t s, int mk, int64_t n, const AndersonVecs
 // host: gamma (mk values) from the anderson_sums(mk) sums of k_aa_dots
 void anderson_gamma(int mk, const double* sums, double* gamma);
 // grid sizes of the producing kernels
-int64_t scatter_blocks(int64_t np, int r);
+int64_t scatter_blocks(int64_t np, int chunk);
 int64_t particle_blocks(int64_t np);
 int64_t mesh_blocks(int64_t ncell);
 

@@ -485,13 +485,14 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const T* __r
 // spans 64 cells at 64 particles per cell, so the 64 lanes of a wavefront sit
 // in 64 different cells and their atomics never meet on one address (2048
 // particles put two lanes in every cell: scatter 0.287 -> 0.245 ms at 32^3);
-// the 3072-node tile (72 KB) still leaves room for two blocks per CU.  Cubic
-// stencils reach two nodes further per axis, so their chunks are half as long
-// (one column of 32 cells plus the wider margins fits the tile).
+// the 3072-node tile (72 KB) still leaves room for two blocks per CU.  Where
+// the box of such a chunk does not fit (more particles per cell, longer
+// orbits: the 64^3 thermal workload) blocks count the miss and the host
+// switches to 2048-particle chunks; cubic stencils use those from the start.
 constexpr int kTileNodes = 3072;
-template <int R>
+template <int CH>
 struct ScatterChunk {
-  static constexpr int kChunk = R >= 3 ? 2048 : 4096;
+  static constexpr int kChunk = CH;
   static constexpr int kPerThread = kChunk / kBlock;  // particles per thread
   static constexpr int kSlot = kChunk / kWave;        // sorted particles per lane slot
 };
@@ -532,9 +533,9 @@ __device__ __forceinline__ void block_min_ints(int (&v)[M]) {
   __syncthreads();
 }
 
-template <int R>
+template <int CH>
 __device__ __forceinline__ int64_t chunk_particle(int64_t base, int k) {
-  return base + (int64_t)(threadIdx.x % kWave) * ScatterChunk<R>::kSlot + threadIdx.x / kWave +
+  return base + (int64_t)(threadIdx.x % kWave) * ScatterChunk<CH>::kSlot + threadIdx.x / kWave +
          (int64_t)(kBlock / kWave) * k;
 }
 
@@ -562,7 +563,7 @@ __device__ __forceinline__ unsigned long long quantize(double w, double scale) {
 
 // MULTI: the particles carry species (one byte each); otherwise every
 // particle has the coefficients of species 0, kept in scalar registers
-template <int R, class PS, bool SPLIT, bool MULTI>
+template <int R, class PS, bool SPLIT, bool MULTI, int CH>
 __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
                                                    const double* __restrict__ vit,
                                                    CurrentOut out, Scratch sc) {
@@ -571,7 +572,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
   __shared__ double tile[3 * kTileNodes];  // FIX: int64 quanta in the same bytes
   __shared__ int s_ref[3];
   unsigned long long* tile_q = reinterpret_cast<unsigned long long*>(tile);
-  constexpr int kChunk = ScatterChunk<R>::kChunk, kPerThread = ScatterChunk<R>::kPerThread;
+  constexpr int kChunk = ScatterChunk<CH>::kChunk, kPerThread = ScatterChunk<CH>::kPerThread;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   double js[1] = {0.0};
   double bad = 0.0;
@@ -587,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
   // pass 1: node box of the chunk's orbits
   int rmin[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, rmax[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
   for (int k = 0; k < kPerThread; ++k) {
-    const int64_t i = chunk_particle<R>(base, k);
+    const int64_t i = chunk_particle<CH>(base, k);
     if (i >= P.np) continue;
     double x0[3], d[3], vb[3];
     orbit_of(P, st, vit, i, x0, d, vb);
@@ -617,6 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
   const bool use_tile = dim[0] > 0 && dim[0] <= kTileNodes && dim[1] <= kTileNodes &&
                         dim[2] <= kTileNodes && (int64_t)dim[0] * dim[1] * dim[2] <= kTileNodes;
   const int nt = use_tile ? dim[0] * dim[1] * dim[2] : 0;
+  if (!use_tile && threadIdx.x == 0) unsafeAtomicAdd(sc.spread_copy(S_SMISS), 1.0);
   for (int t = threadIdx.x; t < 3 * nt; t += kBlock) tile[t] = 0.0;  // also integer zero
   __syncthreads();
   // pass 2: accumulate.  Pieces whose stencil lies outside the tile are
@@ -628,7 +630,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
   auto process = [&](int k, auto global_phase) -> bool {
     constexpr bool GLOBAL = decltype(global_phase)::value;
     bool outside = false;
-    const int64_t i = chunk_particle<R>(base, k);
+    const int64_t i = chunk_particle<CH>(base, k);
     if (i >= P.np) return false;
     double x0[3], d[3], vb[3], c3[3];
     orbit_of(P, st, vit, i, x0, d, vb);
@@ -1291,10 +1293,7 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 }  // namespace
 
-int64_t scatter_blocks(int64_t np, int r) {
-  const int64_t c = r >= 3 ? ScatterChunk<3>::kChunk : ScatterChunk<2>::kChunk;
-  return (np + c - 1) / c;
-}
+int64_t scatter_blocks(int64_t np, int chunk) { return (np + chunk - 1) / chunk; }
 int64_t particle_blocks(int64_t np) { return (np + kBlock - 1) / kBlock; }
 
 // ---- launchers ---------------------------------------------------------------
@@ -1320,25 +1319,32 @@ template <class PS>
 void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
                     CurrentOut out, Scratch sc) {
   if (P.np <= 0) return;
-  const unsigned nblk = (unsigned)scatter_blocks(P.np, r);
+  const unsigned nblk = (unsigned)scatter_blocks(P.np, P.chunk);
   const bool multi = P.nsp > 1;
+  // degree x (split) x species x chunk length
+  auto go = [&](auto R, auto SPLIT) {
+    auto launch = [&](auto MULTI, auto CH) {
+      k_scatter<R.value, PS, SPLIT.value, MULTI.value, CH.value>
+          <<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+    };
+    auto by_multi = [&](auto CH) {
+      if (multi)
+        launch(std::true_type{}, CH);
+      else
+        launch(std::false_type{}, CH);
+    };
+    if (R.value < 3 && P.chunk == 4096)
+      by_multi(std::integral_constant<int, 4096>{});
+    else
+      by_multi(std::integral_constant<int, 2048>{});
+  };
   if constexpr (!PS::kMixed) {
     if (!P.split) {
-      by_degree(r, [&](auto R) {
-        if (multi)
-          k_scatter<R.value, PS, false, true><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
-        else
-          k_scatter<R.value, PS, false, false><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
-      });
+      by_degree(r, [&](auto R) { go(R, std::false_type{}); });
       return;
     }
   }
-  by_degree(r, [&](auto R) {
-    if (multi)
-      k_scatter<R.value, PS, true, true><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
-    else
-      k_scatter<R.value, PS, true, false><<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
-  });
+  by_degree(r, [&](auto R) { go(R, std::true_type{}); });
 }
 
 template <class PS>
