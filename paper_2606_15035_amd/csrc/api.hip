@@ -190,7 +190,7 @@ struct ecpic_sim {
   double2* batch;
   double* realbuf;
   double* Uhalf;
-  int* gflags;  // per-block "box did not fit the LDS tile" flags of the gather
+  int* gwork;  // gather work list: [count, indices of blocks whose box missed the LDS tile]
   double2* tw[3];
   Scratch sc;
   double* host = nullptr;  // pinned read-back
@@ -286,7 +286,7 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->realbuf = w.take<double>(9 * nc);
   S->Uhalf = w.take<double>(3 * nc);
   for (int a = 0; a < 3; ++a) S->tw[a] = w.take<double2>(S->G.n[a] / 2);
-  S->gflags = w.take<int>(particle_blocks(np) + 1);  // gather work list: count, block indices
+  S->gwork = w.take<int>(particle_blocks(np) + 1);
   if (S->mixed()) S->Jfix = w.take<unsigned long long>(3 * nc);
   S->sc.red = w.take<double>(S_NSLOTS);
   S->sc.spread = w.take<double>((size_t)S_NSLOTS * kSpread * kSpreadStride);
@@ -467,7 +467,7 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
   if (hipMemsetAsync(S->sc.red, 0, sizeof(double) * S_NSLOTS, S->stream) != hipSuccess ||
       hipMemsetAsync(S->sc.spread, 0, sizeof(double) * S_NSLOTS * kSpread * kSpreadStride,
                      S->stream) != hipSuccess ||
-      hipMemsetAsync(S->gflags, 0, sizeof(int) * (particle_blocks(n_particles) + 1), S->stream) !=
+      hipMemsetAsync(S->gwork, 0, sizeof(int) * (particle_blocks(n_particles) + 1), S->stream) !=
           hipSuccess ||
       (S->Jfix && hipMemsetAsync(S->Jfix, 0, sizeof(unsigned long long) * 3 * S->G.ncell,
                                  S->stream) != hipSuccess) ||
@@ -681,7 +681,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     }
     if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
     on_store(S, [&](auto& st, auto&) {  // v^{n+1,p+1}
-      launch_gather_push(s, r, P, st, S->vit, S->vnew, S->gbuf, S->gflags, S->sc, prev);
+      launch_gather_push(s, r, P, st, S->vit, S->vnew, S->gbuf, S->gwork, S->sc, prev);
     });
     if (prof) HIPCHK(hipEventRecord(S->ev[3], s));
     AndersonVecs av{};
@@ -701,7 +701,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
                                  {P_AA,
                                   mk == 1 ? (int)particle_blocks(S->np) : anderson_dot_blocks(n3),
                                   anderson_sums(mk), S_AA}};
-      launch_finish(s, S->sc, jobs, S->np > 0 ? (mk > 0 ? 7 : 6) : 2, S->gflags);
+      launch_finish(s, S->sc, jobs, S->np > 0 ? (mk > 0 ? 7 : 6) : 2, S->gwork);
     }
     HIPCHK(hipGetLastError());
     ecpic_status st = sync_read(S, S_DVMAX, (S_AA - S_DVMAX) + anderson_sums(mk));

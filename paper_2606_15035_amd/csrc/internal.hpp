@@ -163,10 +163,13 @@ struct AndersonPrev {
   const double* w = nullptr;
   const double* g = nullptr;
 };
-// flags: one int per 256-particle block, zero on entry and on exit
+// work: 1 + (blocks of 256 particles) ints, work[0] = 0 on entry; the tiled
+// kernel lists the blocks whose node box missed the LDS tile, the second
+// kernel runs them from global memory; the per-pass finishing kernel resets
+// work[0]
 template <class PS>
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
-                        const double* vit, double* vnew, const double* gbuf, int* flags,
+                        const double* vit, double* vnew, const double* gbuf, int* work,
                         Scratch sc, AndersonPrev prev = AndersonPrev{});
 template <class PS>
 void launch_sweep(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
