@@ -124,7 +124,8 @@ typedef struct {
 typedef struct ecpic_sim ecpic_sim;
 
 /* Bytes of device state and workspace for this configuration and particle
-   count.  Returns ECPIC_EINVAL for an invalid configuration. */
+   count (0 <= n_particles <= 2^31 - 1: particle ids and cell offsets are
+   32-bit).  Returns ECPIC_EINVAL for an invalid configuration or count. */
 ecpic_status ecpic_state_bytes(const ecpic_config* cfg, int64_t n_particles, size_t* state_bytes,
                                size_t* workspace_bytes);
 

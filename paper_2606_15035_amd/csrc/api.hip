@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -46,6 +47,8 @@ bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 ecpic_status check_config(const ecpic_config* c, int64_t np) {
   if (!c) return fail(ECPIC_EINVAL, "null configuration");
   if (np < 0) return fail(ECPIC_EINVAL, "negative particle count");
+  if (np > INT32_MAX)  // particle ids and cell offsets are 32-bit
+    return fail(ECPIC_EINVAL, "particle count %lld exceeds 2^31 - 1", (long long)np);
   for (int a = 0; a < 3; ++a) {
     if (!is_pow2(c->n[a]) || c->n[a] < 4 || c->n[a] > 256)
       return fail(ECPIC_EINVAL, "n[%d] = %d must be a power of two in [4, 256]", a, c->n[a]);

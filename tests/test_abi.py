@@ -77,6 +77,14 @@ def test_invalid_configurations_are_rejected(lib, bad):
     assert len(lib.ecpic_last_error()) > 0
 
 
+@pytest.mark.parametrize("count", [-1, 2 ** 31])
+def test_particle_count_outside_the_32_bit_range_is_rejected(lib, count):
+    with pytest.raises(E.EcpicError) as ei:
+        E.state_bytes(good_cfg(), count)
+    assert ei.value.status == E.EINVAL
+    E.state_bytes(good_cfg(), 2 ** 31 - 1)  # the largest count is accepted
+
+
 def test_mixed_precision_state_is_smaller(lib):
     s64, _ = E.state_bytes(good_cfg(), 100000)
     smx, _ = E.state_bytes(good_cfg(precision=E.MIXED), 100000)
