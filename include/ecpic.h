@@ -164,7 +164,11 @@ ecpic_status ecpic_init_species(ecpic_sim* sim, const double* x, const double* v
    orbit current (eq. orbit-current), continuity and CN solve, orbit gather and
    orbit-discrete-gradient push (eq. orbit-push); stop when both fixed-point
    errors are below tau (p >= 1) or at p_max.  Returns ECPIC_OK, or
-   ECPIC_ENOCONV when p_max was reached (the step is still taken). */
+   ECPIC_ENOCONV when p_max was reached (the step is still taken).  Errors
+   (the step is not taken): ECPIC_ENONFINITE for a non-finite velocity or
+   current; ECPIC_EINVAL for an orbit crossing more than 63 knots in one step
+   or, in mixed precision, a particle whose |q_s / q_0| |vbar_l|
+   fixed_point_scale reaches 2^50 (the range of the rounding to quanta). */
 ecpic_status ecpic_picard_step(ecpic_sim* sim, ecpic_step_info* info);
 
 /* Continuity + CN field update alone (eqs. cn-continuity, cn-field-update)

@@ -724,6 +724,9 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     const double dv = S->host[0], vm = S->host[1], dj = S->host[2], js = S->host[3];
     if (S->host[4] >= 2.0 || S->host[4] != S->host[4])
       return fail(ECPIC_ENONFINITE, "non-finite velocity in Picard pass %d", p);
+    if (S->host[4] == 1.5)
+      return fail(ECPIC_EINVAL,
+                  "a current contribution exceeds 2^50 fixed-point quanta; lower fixed_point_scale");
     if (S->host[4] != 0.0)
       return fail(ECPIC_EINVAL, "an orbit crossed more than %d knots in one step", kMaxPieces - 1);
     if (!std::isfinite(dv) || !std::isfinite(vm) || !std::isfinite(dj) || !std::isfinite(js))
@@ -1151,6 +1154,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.11"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.12"; }
 
 }  // extern "C"

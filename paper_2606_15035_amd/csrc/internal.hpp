@@ -21,7 +21,8 @@ enum Slot : int {
   S_VMAX,       // max_i |v^{p+1}|_inf                  (bit-pattern max)
   S_DJMAX,      // max_g |J^p - J^{p-1}|                (bit-pattern max)
   S_JS,         // J_s = sum_i |q| |vbar_i|_inf / |Omega| (sum)
-  S_BAD,        // 1: an orbit had too many pieces, 2: a non-finite velocity (max)
+  S_BAD,        // 1: an orbit had too many pieces, 1.5: a current contribution beyond the
+                // fixed-point range, 2: a non-finite velocity (max)
   S_AA,         // Anderson sums dF_i . dF_j (i <= j), then dF_i . f_p   (sums)
   S_AA_END = S_AA + kAndersonSums - 1,
   S_JE,         // sum_g J . E^{n+1/2} dV               (sum)

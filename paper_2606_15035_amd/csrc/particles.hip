@@ -554,11 +554,30 @@ __device__ __forceinline__ void orbit_of(const StepParams& P, const PS& st,
   }
 }
 
-// Fixed-point quantum count of a current contribution (round to nearest,
-// ties away from zero), as the two's-complement bit pattern that 64-bit
-// integer atomics add.
+// Fixed-point quantum count of a current contribution w: the product
+// w x scale rounded once to the nearest integer (ties to even), as the
+// two's-complement bit pattern that 64-bit integer atomics add.  Adding
+// 1.5 x 2^52 in the same fused operation leaves that integer in the low
+// mantissa bits of the sum while the sum stays in (2^52, 2^53), which holds
+// for |w scale| < 2^50: one FMA and one 64-bit subtraction in place of a
+// rounding and a software FP64 -> int64 conversion.  The caller guarantees
+// the range (the scatter checks it once per particle and flags a particle
+// outside it).
+__device__ __forceinline__ unsigned long long quantize_in_range(double w, double scale) {
+  constexpr double kMagic = 0x1.8p52;
+  const double t = fma(w, scale, kMagic);
+  return (unsigned long long)(__double_as_longlong(t) - __double_as_longlong(kMagic));
+}
+
+// Bound on |w scale| for quantize_in_range.  The orbit weights of a piece
+// are at most 1, so a particle whose |c_l| scale stays below it has every
+// contribution in range.
+constexpr double kFixedRange = 0x1p50;
+
+// The same rounding for any w (a conversion outside the range).
 __device__ __forceinline__ unsigned long long quantize(double w, double scale) {
-  return (unsigned long long)(long long)round(w * scale);
+  if (fabs(w) * scale < kFixedRange) return quantize_in_range(w, scale);
+  return (unsigned long long)(long long)rint(w * scale);
 }
 
 // MULTI: the particles carry species (one byte each); otherwise every
@@ -664,7 +683,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
 #pragma unroll
               for (int l = 0; l < 3; ++l) {
                 if constexpr (FIX)
-                  atomicAdd(&tile_q[3 * t + l], quantize(w * c3[l], out.fix_scale));
+                  atomicAdd(&tile_q[3 * t + l], quantize_in_range(w * c3[l], out.fix_scale));
                 else
                   atomicAdd(&tile[3 * t + l], w * c3[l]);
               }
@@ -681,7 +700,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
 #pragma unroll
               for (int l = 0; l < 3; ++l) {
                 if constexpr (FIX)
-                  atomicAdd(out.Jfix + l * nc + g, quantize(w * c3[l], out.fix_scale));
+                  atomicAdd(out.Jfix + l * nc + g, quantize_in_range(w * c3[l], out.fix_scale));
                 else
                   unsafeAtomicAdd(out.J + l * nc + g, w * c3[l]);
               }
@@ -720,7 +739,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
 #pragma unroll
               for (int l = 0; l < 3; ++l) {
                 if constexpr (FIX)
-                  atomicAdd(&tile_q[3 * t + l], quantize(w * c3[l], out.fix_scale));
+                  atomicAdd(&tile_q[3 * t + l], quantize_in_range(w * c3[l], out.fix_scale));
                 else
                   atomicAdd(&tile[3 * t + l], w * c3[l]);
               }
@@ -729,7 +748,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
 #pragma unroll
               for (int l = 0; l < 3; ++l) {
                 if constexpr (FIX)
-                  atomicAdd(out.Jfix + l * nc + g, quantize(w * c3[l], out.fix_scale));
+                  atomicAdd(out.Jfix + l * nc + g, quantize_in_range(w * c3[l], out.fix_scale));
                 else
                   unsafeAtomicAdd(out.J + l * nc + g, w * c3[l]);
               }
@@ -774,6 +793,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
       }
     }
     if (!ok && !GLOBAL) bad = 1.0;
+    if constexpr (FIX) {  // contributions beyond the fixed-point range
+      const double cmax = fmax(fabs(c3[0]), fmax(fabs(c3[1]), fabs(c3[2])));
+      if (!GLOBAL && !(cmax * out.fix_scale < kFixedRange)) bad = fmax(bad, 1.5);
+    }
     return outside;
   };
   for (int k = 0; k < kPerThread; ++k)

@@ -171,3 +171,26 @@ def test_mixed_two_stream_energy_and_constraints():
     # the two beams round alike, so the errors partly add up).
     assert step_g <= 2.0 ** -23 and drift_g <= wl.steps * 2.0 ** -23
     assert step_o < 1e-13
+
+
+def test_contribution_beyond_the_fixed_point_range_is_an_error():
+    """A current contribution of 2^50 quanta or more is refused (the step
+    returns ECPIC_EINVAL and is not taken); the same particles with a
+    smaller quantum step normally."""
+    wl = W.random_plasma((8, 8, 4), (1.0, 1.0, 0.5), 500, r=2, dt=0.25, vth=0.01,
+                         drift=(0.5, 0.0, 0.0), seed=41)
+    x, v = to_storage(wl, wl.x, wl.v)
+    # |vbar| ~ 0.5: 0.5 x 2^52 = 2^51 quanta, beyond the range
+    g = E.Sim(mixed_cfg(wl, fixed_point_scale=2.0 ** 52), wl.np)
+    g.init_particles(x, v, wl.q, wl.m, wl.n0)
+    before = g.get_state()
+    with pytest.raises(E.EcpicError) as ei:
+        g.picard_step()
+    assert ei.value.status == E.EINVAL
+    assert "fixed-point" in str(ei.value)
+    after = g.get_state()
+    for k in ("x", "v"):
+        assert np.array_equal(before[k], after[k])
+    ok = E.Sim(mixed_cfg(wl, fixed_point_scale=2.0 ** 44), wl.np)
+    ok.init_particles(x, v, wl.q, wl.m, wl.n0)
+    assert ok.picard_step()["converged"]
