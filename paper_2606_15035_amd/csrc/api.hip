@@ -215,9 +215,10 @@ struct ecpic_sim {
     P.np = np;
     P.split = cfg.split_orbit_at_knots;
     P.rule = rule;
-    // long chunks pay off for FP64 LDS atomics (c2: 0.287 -> 0.245 ms per pass),
-    // not for the int64 quanta of the mixed form (0.317 -> 0.324 ms)
-    P.chunk = cfg.spline_degree >= 3 || mixed() ? 2048 : chunk;
+    // long chunks pay off for the LDS atomics (32^3 two-stream: FP64
+    // 0.287 -> 0.245 ms per pass, mixed 0.247 -> 0.239 ms); the wider cubic
+    // stencil takes the short ones
+    P.chunk = cfg.spline_degree >= 3 ? 2048 : chunk;
     P.nsp = nsp;
     for (int k = 0; k < kMaxSpecies; ++k) {
       P.qs[k] = qs[k];
