@@ -100,6 +100,11 @@ typedef struct {
                                    In mixed precision the mixing coefficients are FP64 sums
                                    over the particles, so with m > 0 the step is no longer
                                    bitwise independent of the particle order. */
+  int32_t scatter_chunk;        /* cell-sorted particles per block of the current scatter:
+                                   0 = automatic (4096, switched to 2048 for good once more
+                                   than 1% of a step's chunks overflow the LDS tile; 2048 for
+                                   r = 3), or 2048, or 4096 for r <= 2.  Results are the same
+                                   up to the order of the FP64 atomic additions. */
 } ecpic_config;
 
 typedef struct {

@@ -81,6 +81,10 @@ ecpic_status check_config(const ecpic_config* c, int64_t np) {
     return fail(ECPIC_EINVAL, "fixed_point_scale must be in [0, 2^52] (0 = 2^40)");
   if (c->anderson_depth < 0 || c->anderson_depth > kMaxAnderson)
     return fail(ECPIC_EINVAL, "anderson_depth must be in [0, %d]", kMaxAnderson);
+  if (c->scatter_chunk != 0 && c->scatter_chunk != 2048 && c->scatter_chunk != 4096)
+    return fail(ECPIC_EINVAL, "scatter_chunk must be 0, 2048 or 4096");
+  if (c->spline_degree >= 3 && c->scatter_chunk == 4096)
+    return fail(ECPIC_EINVAL, "cubic stencils take 2048-particle scatter chunks");
   return ECPIC_OK;
 }
 
@@ -218,7 +222,8 @@ struct ecpic_sim {
     // long chunks pay off for the LDS atomics (32^3 two-stream: FP64
     // 0.287 -> 0.245 ms per pass, mixed 0.247 -> 0.239 ms); the wider cubic
     // stencil takes the short ones
-    P.chunk = cfg.spline_degree >= 3 ? 2048 : chunk;
+    P.chunk = cfg.scatter_chunk > 0 ? cfg.scatter_chunk
+                                    : (cfg.spline_degree >= 3 ? 2048 : chunk);
     P.nsp = nsp;
     for (int k = 0; k < kMaxSpecies; ++k) {
       P.qs[k] = qs[k];

@@ -489,12 +489,15 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const T* __r
 // the box of such a chunk does not fit (more particles per cell, longer
 // orbits: the 64^3 thermal workload) blocks count the miss and the host
 // switches to 2048-particle chunks; cubic stencils use those from the start.
-constexpr int kTileNodes = 3072;
-template <int CH>
+// Quadratic and linear 2048-particle chunks fit a 2048-node tile (48 KB),
+// which lets three blocks share a CU (three waves per SIMD at 168 registers:
+// 64^3 mixed scatter 5.04 -> 4.71 ms per pass); the cubic ones need 3072.
+template <int R, int CH>
 struct ScatterChunk {
   static constexpr int kChunk = CH;
   static constexpr int kPerThread = kChunk / kBlock;  // particles per thread
-  static constexpr int kSlot = kChunk / kWave;        // sorted particles per lane slot
+  static constexpr int kTileNodes = (CH == 2048 && R < 3) ? 2048 : 3072;
+  static constexpr int kWavesPerSimd = (CH == 2048 && R < 3) ? 3 : 1;  // minimum asked for
 };
 
 __device__ __forceinline__ int min_image(int raw, int n) {
@@ -535,7 +538,7 @@ __device__ __forceinline__ void block_min_ints(int (&v)[M]) {
 
 template <int CH>
 __device__ __forceinline__ int64_t chunk_particle(int64_t base, int k) {
-  return base + (int64_t)(threadIdx.x % kWave) * ScatterChunk<CH>::kSlot + threadIdx.x / kWave +
+  return base + (int64_t)(threadIdx.x % kWave) * (CH / kWave) + threadIdx.x / kWave +
          (int64_t)(kBlock / kWave) * k;
 }
 
@@ -583,15 +586,17 @@ __device__ __forceinline__ unsigned long long quantize(double w, double scale) {
 // MULTI: the particles carry species (one byte each); otherwise every
 // particle has the coefficients of species 0, kept in scalar registers
 template <int R, class PS, bool SPLIT, bool MULTI, int CH>
-__global__ __launch_bounds__(kBlock) void k_scatter(StepParams P, PS st,
+__global__ __launch_bounds__(kBlock) __attribute__((
+    amdgpu_waves_per_eu(ScatterChunk<R, CH>::kWavesPerSimd))) void k_scatter(StepParams P, PS st,
                                                    const double* __restrict__ vit,
                                                    CurrentOut out, Scratch sc) {
   constexpr int W = R + 1;
   constexpr bool FIX = PS::kMixed;  // int64 fixed-point deposit
+  constexpr int kTileNodes = ScatterChunk<R, CH>::kTileNodes;
   __shared__ double tile[3 * kTileNodes];  // FIX: int64 quanta in the same bytes
   __shared__ int s_ref[3];
   unsigned long long* tile_q = reinterpret_cast<unsigned long long*>(tile);
-  constexpr int kChunk = ScatterChunk<CH>::kChunk, kPerThread = ScatterChunk<CH>::kPerThread;
+  constexpr int kChunk = ScatterChunk<R, CH>::kChunk, kPerThread = ScatterChunk<R, CH>::kPerThread;
   const int64_t base = (int64_t)blockIdx.x * kChunk;
   double js[1] = {0.0};
   double bad = 0.0;
@@ -1342,11 +1347,12 @@ template <class PS>
 void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
                     CurrentOut out, Scratch sc) {
   if (P.np <= 0) return;
-  const unsigned nblk = (unsigned)scatter_blocks(P.np, P.chunk);
   const bool multi = P.nsp > 1;
-  // degree x (split) x species x chunk length
+  // degree x (split) x species x chunk length (4096 for r <= 2 only; the
+  // host validates P.chunk, whose block count the reductions also use)
   auto go = [&](auto R, auto SPLIT) {
     auto launch = [&](auto MULTI, auto CH) {
+      const unsigned nblk = (unsigned)scatter_blocks(P.np, CH.value);
       k_scatter<R.value, PS, SPLIT.value, MULTI.value, CH.value>
           <<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
     };

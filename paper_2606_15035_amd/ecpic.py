@@ -37,7 +37,7 @@ class Config(C.Structure):
                 ("split_orbit_at_knots", C.c_int32), ("quad_points", C.c_int32),
                 ("precision", C.c_int32), ("fixed_point_scale", C.c_double),
                 ("diagnostics", C.c_int32), ("sort_interval", C.c_int32),
-                ("anderson_depth", C.c_int32)]
+                ("anderson_depth", C.c_int32), ("scatter_chunk", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -126,7 +126,7 @@ def _check(status, allow=(OK,)):
 
 def make_config(n, L, dt, r=1, kappa=1.0, sigma1=1.0, sigma2=1.0, tol=1e-12, pmax=16,
                 split=True, quad_points=0, precision=FP64, fixed_point_scale=0.0,
-                diagnostics=False, sort_interval=0, anderson=0) -> Config:
+                diagnostics=False, sort_interval=0, anderson=0, scatter_chunk=0) -> Config:
     c = Config()
     for a in range(3):
         c.n[a] = int(n[a])
@@ -141,6 +141,7 @@ def make_config(n, L, dt, r=1, kappa=1.0, sigma1=1.0, sigma2=1.0, tol=1e-12, pma
     c.diagnostics = int(bool(diagnostics))
     c.sort_interval = int(sort_interval)
     c.anderson_depth = int(anderson)
+    c.scatter_chunk = int(scatter_chunk)
     return c
 
 

@@ -69,6 +69,8 @@ def test_state_bytes_scale_with_particles(lib):
     dict(quad_points=3),                  # split quadratic pieces need 4 points
     dict(r=3, quad_points=4),             # split cubic pieces need 5 points
     dict(split=False, precision=1),       # unsplit comparison path is FP64 only
+    dict(scatter_chunk=1024),             # chunk lengths: 0 (automatic), 2048, 4096
+    dict(r=3, scatter_chunk=4096),        # cubic stencils take 2048
 ])
 def test_invalid_configurations_are_rejected(lib, bad):
     with pytest.raises(E.EcpicError) as ei:

@@ -69,11 +69,11 @@ def small_random(r, seed):
                            drift=(0.03, -0.02, 0.01), seed=seed)
 
 
-@pytest.mark.parametrize("name,r", [("c3", 1), ("random", 2)])
-def test_mixed_step_matches_oracle(name, r):
+@pytest.mark.parametrize("name,r,chunk", [("c3", 1, 0), ("random", 2, 0), ("random", 2, 2048)])
+def test_mixed_step_matches_oracle(name, r, chunk):
     wl = W.two_stream("c3") if name == "c3" else small_random(r, seed=13)
     x, v = to_storage(wl, wl.x, wl.v)
-    g = E.Sim(mixed_cfg(wl, tol=0.0, pmax=3), wl.np)
+    g = E.Sim(mixed_cfg(wl, tol=0.0, pmax=3, scatter_chunk=chunk), wl.np)
     g.init_particles(x, v, wl.q, wl.m, wl.n0)
     oargs = wl.cfg_kwargs()
     oargs.update(tol=0.0, pmax=3)

@@ -47,7 +47,7 @@ def gpu_cfg(wl, **kw):
 
 def orc_cfg(wl, **kw):
     args = wl.cfg_kwargs()
-    m = {"diagnostics": None, "sort_interval": None}
+    m = {"diagnostics": None, "sort_interval": None, "scatter_chunk": None}
     for k, v in kw.items():
         if k in m:
             continue
@@ -210,6 +210,18 @@ def test_step_parity_fixed_iterations(r, pmax):
         assert not ig["converged"] and not io["converged"]
         np.testing.assert_allclose(ig["err_v"], io["err_v"], rtol=1e-6)
         compare_states(wl, g, o, f"r={r} pmax={pmax} step {step}")
+
+
+@pytest.mark.parametrize("r,chunk", [(1, 2048), (2, 2048), (2, 4096), (3, 2048)])
+def test_step_parity_with_each_scatter_chunk(r, chunk):
+    """Each scatter chunk length and tile size, forced (the automatic choice
+    takes 4096 for r <= 2 until long chunks overflow the tile, 2048 for
+    r = 3): several chunks and a ragged last one."""
+    wl = small_random(r, np_=9000, seed=13)
+    g, o = both(wl, tol=0.0, pmax=2, scatter_chunk=chunk)
+    for step in range(2):
+        assert g.picard_step()["iters"] == o.step()["iters"] == 3
+        compare_states(wl, g, o, f"r={r} chunk={chunk} step {step}")
 
 
 @pytest.mark.parametrize("r", [1, 2, 3])
