@@ -623,12 +623,6 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
 
   const auto t_start = std::chrono::steady_clock::now();
   const bool prof = S->profiling;
-  const int sort_every = S->cfg.sort_interval <= 0 ? 1 : S->cfg.sort_interval;
-  if (S->cfg.sort_interval >= 0 && (S->en.step % sort_every) == 0)
-    on_store(S, [&](auto& st, auto& alt) {  // cell order of x^n
-      launch_sort(s, S->G, S->np, st, alt, S->id, S->id2, S->sb);
-    });
-  // v^{n+1,0} = 2 v^n - v^{n-1}
   // Iterates w_{p-j} (wl[j]) and images g_{p-j} (gl[j]) of the passes the
   // Anderson mixing still needs, newest first (the plain iteration keeps one
   // of each and takes w_{p+1} = g_p without a copy).
@@ -639,7 +633,15 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   int nw = 0, ng = 0;
   push_front(wl, nw, am + 1, S->apool[0]);
   S->vit = wl[0];
-  on_store(S, [&](auto& st, auto&) { launch_extrapolate(s, S->np, st, S->vit); });
+  // cell order of x^n, and v^{n+1,0} = 2 v^n - v^{n-1} (written by the sort's
+  // permutation when the step sorts)
+  const int sort_every = S->cfg.sort_interval <= 0 ? 1 : S->cfg.sort_interval;
+  if (S->cfg.sort_interval >= 0 && (S->en.step % sort_every) == 0 && S->np > 0)
+    on_store(S, [&](auto& st, auto& alt) {
+      launch_sort(s, S->G, S->np, st, alt, S->id, S->id2, S->sb, S->vit);
+    });
+  else
+    on_store(S, [&](auto& st, auto&) { launch_extrapolate(s, S->np, st, S->vit); });
   const CurrentOut cout{nullptr, S->Jfix, S->fix_scale};
   const double fix_unit = S->q / S->G.dV / S->fix_scale;
   const bool fused = fused_field_solve_fits(S->G);
@@ -1160,6 +1162,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.12"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.13"; }
 
 }  // extern "C"

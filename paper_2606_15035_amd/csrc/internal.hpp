@@ -212,10 +212,12 @@ struct SortScratch {
 int64_t sort_scan_blocks(int64_t ncell);
 void launch_iota(hipStream_t s, int64_t n, int* p);
 // Sorts the particles of cur (with their ids) into alt, then swaps cur/alt
-// and id/id2, so that cur and id hold the sorted particles.
+// and id/id2, so that cur and id hold the sorted particles.  With vit, the
+// permutation also writes the first Picard guess 2 v^n - v^{n-1} of every
+// particle there, in the sorted order (3 x np FP64, component-major).
 template <class PS>
 void launch_sort(hipStream_t s, const Grid& G, int64_t np, PS& cur, PS& alt, int*& id, int*& id2,
-                 const SortScratch& b);
+                 const SortScratch& b, double* vit = nullptr);
 void launch_to_caller(hipStream_t s, int64_t np, const int* id, const double* src, double* dst);
 void launch_from_caller(hipStream_t s, int64_t np, const int* id, const double* src, double* dst);
 
