@@ -175,6 +175,7 @@ struct ecpic_sim {
   Fp64Store f64[2];
   MixedStore mx[2];
   double *vit, *vnew;  // Picard iterate w_p and image g_p of the current pass (FP64)
+  double* vbar = nullptr;  // vbar of the next scatter, written ahead (plain Picard only)
   // 2 (m + 1) buffers of 3 np doubles for the iterates and images that the
   // Anderson mixing of depth m still needs (m = 0: the two of the plain iteration)
   double* apool[2 * (kMaxAnderson + 1)] = {};
@@ -296,6 +297,9 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->Uhalf = w.take<double>(3 * nc);
   for (int a = 0; a < 3; ++a) S->tw[a] = w.take<double2>(S->G.n[a] / 2);
   S->gwork = w.take<int>(particle_blocks(np) + 1);
+  // the plain iteration's next iterate is the gather's output, so the gather
+  // (and the step's set-up) can hand the scatter vbar^p directly
+  S->vbar = S->cfg.anderson_depth == 0 ? w.take<double>(n3) : nullptr;
   if (S->mixed()) S->Jfix = w.take<unsigned long long>(3 * nc);
   S->sc.red = w.take<double>(S_NSLOTS);
   S->sc.spread = w.take<double>((size_t)S_NSLOTS * kSpread * kSpreadStride);
@@ -638,10 +642,10 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   const int sort_every = S->cfg.sort_interval <= 0 ? 1 : S->cfg.sort_interval;
   if (S->cfg.sort_interval >= 0 && (S->en.step % sort_every) == 0 && S->np > 0)
     on_store(S, [&](auto& st, auto& alt) {
-      launch_sort(s, S->G, S->np, st, alt, S->id, S->id2, S->sb, S->vit);
+      launch_sort(s, S->G, S->np, st, alt, S->id, S->id2, S->sb, S->vit, S->vbar);
     });
   else
-    on_store(S, [&](auto& st, auto&) { launch_extrapolate(s, S->np, st, S->vit); });
+    on_store(S, [&](auto& st, auto&) { launch_extrapolate(s, S->np, st, S->vit, S->vbar); });
   const CurrentOut cout{nullptr, S->Jfix, S->fix_scale};
   const double fix_unit = S->q / S->G.dV / S->fix_scale;
   const bool fused = fused_field_solve_fits(S->G);
@@ -673,7 +677,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     on_store(S, [&](auto& st, auto&) {  // J^{n+1/2,p}
       CurrentOut o = cout;
       o.J = J;
-      launch_scatter(s, r, P, st, S->vit, o, S->sc);
+      launch_scatter(s, r, P, st, S->vit, S->vbar, o, S->sc);
     });
     if (S->mixed()) launch_fixed_current(s, 3 * nc, S->Jfix, J, fix_unit);
     if (prof) HIPCHK(hipEventRecord(S->ev[1], s));
@@ -692,7 +696,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     }
     if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
     on_store(S, [&](auto& st, auto&) {  // v^{n+1,p+1}
-      launch_gather_push(s, r, P, st, S->vit, S->vnew, S->gbuf, S->gwork, S->sc, prev);
+      launch_gather_push(s, r, P, st, S->vit, S->vnew, S->vbar, S->gbuf, S->gwork, S->sc, prev);
     });
     if (prof) HIPCHK(hipEventRecord(S->ev[3], s));
     AndersonVecs av{};
@@ -1061,7 +1065,7 @@ ecpic_status ecpic_adjoint_step(ecpic_sim* S, void* workspace, size_t workspace_
   launch_reset_slots(s, S->sc, S_BAD, 1);
   {
     Fp64Store view{const_cast<double*>(x), const_cast<double*>(v), nullptr};
-    launch_scatter(s, 2, P, view, w, CurrentOut{A.J, nullptr, 0.0}, S->sc);
+    launch_scatter(s, 2, P, view, w, nullptr, CurrentOut{A.J, nullptr, 0.0}, S->sc);
   }
   RealIO jin = soa_io(A.J, nc, 3);
   fft3_forward(s, G, 3, A.Jh, &jin, nullptr, twp(S), S->sc);

@@ -152,11 +152,15 @@ struct CurrentOut {
   unsigned long long* Jfix;
   double fix_scale;  // quanta per unit of vbar Sbar (2^40 by default)
 };
+// v^{n+1,0} = 2 v^n - v^{n-1} into vit and, with vbar, its vbar^0 there
 template <class PS>
-void launch_extrapolate(hipStream_t s, int64_t np, const PS& st, double* vit);
+void launch_extrapolate(hipStream_t s, int64_t np, const PS& st, double* vit,
+                        double* vbar = nullptr);
+// Orbit current of iterate vit; with vbar non-null, vbar^p (3 x np) is read
+// from there instead of being formed from v^n and vit
 template <class PS>
 void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
-                    CurrentOut out, Scratch sc);
+                    const double* vbar, CurrentOut out, Scratch sc);
 // Iterate and image of the previous Picard pass: with w non-null the gather
 // also writes the block partial sums dF . dF and dF . f_p of Anderson mixing
 // over one difference (dF = f_p - f_{p-1}, f = image - iterate) to site P_AA.
@@ -167,11 +171,12 @@ struct AndersonPrev {
 // work: 1 + (blocks of 256 particles) ints, work[0] = 0 on entry; the tiled
 // kernel lists the blocks whose node box missed the LDS tile, the second
 // kernel runs them from global memory; the per-pass finishing kernel resets
-// work[0]
+// work[0].  vbar_out (nullable): (vnew + v^n) / 2, the vbar of a next pass
+// whose iterate is vnew
 template <class PS>
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
-                        const double* vit, double* vnew, const double* gbuf, int* work,
-                        Scratch sc, AndersonPrev prev = AndersonPrev{});
+                        const double* vit, double* vnew, double* vbar_out, const double* gbuf,
+                        int* work, Scratch sc, AndersonPrev prev = AndersonPrev{});
 template <class PS>
 void launch_sweep(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
                   const double* gbuf, const double* Uhalf, Scratch sc);
@@ -214,10 +219,11 @@ void launch_iota(hipStream_t s, int64_t n, int* p);
 // Sorts the particles of cur (with their ids) into alt, then swaps cur/alt
 // and id/id2, so that cur and id hold the sorted particles.  With vit, the
 // permutation also writes the first Picard guess 2 v^n - v^{n-1} of every
-// particle there, in the sorted order (3 x np FP64, component-major).
+// particle there, in the sorted order (3 x np FP64, component-major), and
+// with vbar its vbar^0.
 template <class PS>
 void launch_sort(hipStream_t s, const Grid& G, int64_t np, PS& cur, PS& alt, int*& id, int*& id2,
-                 const SortScratch& b, double* vit = nullptr);
+                 const SortScratch& b, double* vit = nullptr, double* vbar = nullptr);
 void launch_to_caller(hipStream_t s, int64_t np, const int* id, const double* src, double* dst);
 void launch_from_caller(hipStream_t s, int64_t np, const int* id, const double* src, double* dst);
 

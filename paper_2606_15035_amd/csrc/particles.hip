@@ -467,9 +467,13 @@ __device__ __forceinline__ void load3(const double* __restrict__ p, int64_t np, 
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const T* __restrict__ v,
                                                        const T* __restrict__ vprev,
-                                                       double* __restrict__ vit) {
+                                                       double* __restrict__ vit,
+                                                       double* __restrict__ vbar) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n3) vit[i] = 2.0 * (double)v[i] - (double)vprev[i];  // v^{n+1,0} = 2 v^n - v^{n-1}
+  if (i >= n3) return;
+  const double w = 2.0 * (double)v[i] - (double)vprev[i];  // v^{n+1,0} = 2 v^n - v^{n-1}
+  vit[i] = w;
+  if (vbar) vbar[i] = 0.5 * (w + (double)v[i]);
 }
 
 // Orbit current of a chunk of kChunk particles per block.  Lanes take
@@ -542,19 +546,26 @@ __device__ __forceinline__ int64_t chunk_particle(int64_t base, int k) {
          (int64_t)(kBlock / kWave) * k;
 }
 
+// x^n, vbar^p = (v^{n+1,p} + v^n) / 2 and the unwrapped displacement
+// d = dt vbar^p of particle i; vbar^p read from vbar when the previous pass
+// (or the step's set-up) wrote it, else formed from v^n and the iterate
 template <class PS>
 __device__ __forceinline__ void orbit_of(const StepParams& P, const PS& st,
-                                         const double* __restrict__ vit, int64_t i, double* x0,
+                                         const double* __restrict__ vit,
+                                         const double* __restrict__ vbar, int64_t i, double* x0,
                                          double* d, double* vb) {
-  double va[3], vi[3];
   st.x_of(P.G, P.np, i, x0);
-  st.v_of(P.np, i, va);
-  load3(vit, P.np, i, vi);
+  if (vbar) {
+    load3(vbar, P.np, i, vb);
+  } else {
+    double va[3], vi[3];
+    st.v_of(P.np, i, va);
+    load3(vit, P.np, i, vi);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    vb[a] = 0.5 * (vi[a] + va[a]);  // vbar^p = (v^{n+1,p} + v^n) / 2
-    d[a] = P.dt * vb[a];            // unwrapped displacement
+    for (int a = 0; a < 3; ++a) vb[a] = 0.5 * (vi[a] + va[a]);
   }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) d[a] = P.dt * vb[a];
 }
 
 // Fixed-point quantum count of a current contribution w: the product
@@ -589,6 +600,7 @@ template <int R, class PS, bool SPLIT, bool MULTI, int CH>
 __global__ __launch_bounds__(kBlock) __attribute__((
     amdgpu_waves_per_eu(ScatterChunk<R, CH>::kWavesPerSimd))) void k_scatter(StepParams P, PS st,
                                                    const double* __restrict__ vit,
+                                                   const double* __restrict__ vbar,
                                                    CurrentOut out, Scratch sc) {
   constexpr int W = R + 1;
   constexpr bool FIX = PS::kMixed;  // int64 fixed-point deposit
@@ -615,7 +627,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((
     const int64_t i = chunk_particle<CH>(base, k);
     if (i >= P.np) continue;
     double x0[3], d[3], vb[3];
-    orbit_of(P, st, vit, i, x0, d, vb);
+    orbit_of(P, st, vit, vbar, i, x0, d, vb);
     const double vmax = fmax(fabs(vb[0]), fmax(fabs(vb[1]), fabs(vb[2])));
     js[0] += (MULTI ? species_value(P.aq, st.species(i)) : P.aq[0]) * vmax;
 #pragma unroll
@@ -657,7 +669,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((
     const int64_t i = chunk_particle<CH>(base, k);
     if (i >= P.np) return false;
     double x0[3], d[3], vb[3], c3[3];
-    orbit_of(P, st, vit, i, x0, d, vb);
+    orbit_of(P, st, vit, vbar, i, x0, d, vb);
     // FP64: q_i vbar / dV; fixed point: (q_i / q_0) vbar in units of the quantum
     const double cq = MULTI ? species_value(P.cq, st.species(i)) : P.cq[0];
     int shift[3];
@@ -895,7 +907,8 @@ constexpr int kGatherListGrid = 512;  // blocks of the global-memory kernel with
 template <int R, bool TILED, class PS, bool SPLIT>
 __device__ __forceinline__ void gather_block(const StepParams& P, const PS& st,
                                              const double* __restrict__ vit,
-                                             double* __restrict__ vnew, const AosFields& F,
+                                             double* __restrict__ vnew,
+                                             double* __restrict__ vbar_out, const AosFields& F,
                                              int* __restrict__ work, const Scratch& sc,
                                              const AndersonPrev& prev, int bid) {
   constexpr int W = R + 1;
@@ -992,6 +1005,7 @@ __device__ __forceinline__ void gather_block(const StepParams& P, const PS& st,
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       vnew[j * P.np + i] = vn[j];
+      if (vbar_out) vbar_out[j * P.np + i] = 0.5 * (vn[j] + va[j]);  // the next pass's vbar
       dvm = fmax(dvm, fabs(vn[j] - vi[j]));
       vm = fmax(vm, fabs(vn[j]));
       if (!isfinite(vn[j])) bad = 2.0;  // max-reductions drop NaN: flag it explicitly
@@ -1033,14 +1047,15 @@ __device__ __forceinline__ void gather_block(const StepParams& P, const PS& st,
 template <int R, bool TILED, class PS, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
                                                        const double* __restrict__ vit,
-                                                       double* __restrict__ vnew, AosFields F,
+                                                       double* __restrict__ vnew,
+                                                       double* __restrict__ vbar_out, AosFields F,
                                                        int* __restrict__ work, Scratch sc,
                                                        AndersonPrev prev) {
   if (TILED || !work) {
     late_reduce_init<4>();
     late_reduce_init<2>();
     if (!TILED) __syncthreads();  // the tiled path has a barrier before its first use
-    gather_block<R, TILED, PS, SPLIT>(P, st, vit, vnew, F, work, sc, prev, blockIdx.x);
+    gather_block<R, TILED, PS, SPLIT>(P, st, vit, vnew, vbar_out, F, work, sc, prev, blockIdx.x);
     return;
   }
   const int count = work[0];  // written by the tiled kernel (previous launch)
@@ -1049,7 +1064,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
     late_reduce_init<4>();
     late_reduce_init<2>();
     __syncthreads();
-    gather_block<R, TILED, PS, SPLIT>(P, st, vit, vnew, F, work, sc, prev, work[1 + j]);
+    gather_block<R, TILED, PS, SPLIT>(P, st, vit, vnew, vbar_out, F, work, sc, prev, work[1 + j]);
   }
 }
 
@@ -1338,14 +1353,14 @@ void by_degree(int r, F&& f) {
 }
 
 template <class PS>
-void launch_extrapolate(hipStream_t s, int64_t np, const PS& st, double* vit) {
+void launch_extrapolate(hipStream_t s, int64_t np, const PS& st, double* vit, double* vbar) {
   if (np <= 0) return;
-  k_extrapolate<<<blocks_for(3 * np), kBlock, 0, s>>>(3 * np, st.v, st.vp, vit);
+  k_extrapolate<<<blocks_for(3 * np), kBlock, 0, s>>>(3 * np, st.v, st.vp, vit, vbar);
 }
 
 template <class PS>
 void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
-                    CurrentOut out, Scratch sc) {
+                    const double* vbar, CurrentOut out, Scratch sc) {
   if (P.np <= 0) return;
   const bool multi = P.nsp > 1;
   // degree x (split) x species x chunk length (4096 for r <= 2 only; the
@@ -1354,7 +1369,7 @@ void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, con
     auto launch = [&](auto MULTI, auto CH) {
       const unsigned nblk = (unsigned)scatter_blocks(P.np, CH.value);
       k_scatter<R.value, PS, SPLIT.value, MULTI.value, CH.value>
-          <<<nblk, kBlock, 0, s>>>(P, st, vit, out, sc);
+          <<<nblk, kBlock, 0, s>>>(P, st, vit, vbar, out, sc);
     };
     auto by_multi = [&](auto CH) {
       if (multi)
@@ -1378,17 +1393,17 @@ void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, con
 
 template <class PS>
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
-                        const double* vit, double* vnew, const double* gbuf, int* work,
-                        Scratch sc, AndersonPrev prev) {
+                        const double* vit, double* vnew, double* vbar_out, const double* gbuf,
+                        int* work, Scratch sc, AndersonPrev prev) {
   if (P.np <= 0) return;
   AosFields F{gbuf};
   const unsigned nb = blocks_for(P.np);
   const unsigned ng = work ? std::min<unsigned>(nb, kGatherListGrid) : nb;
 #define ECPIC_GATHER_PAIR(R_, SPLIT_)                                                          \
-  k_gather_push<R_, true, PS, SPLIT_><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, F, work, sc,    \
-                                                             prev);                            \
-  k_gather_push<R_, false, PS, SPLIT_><<<ng, kBlock, 0, s>>>(P, st, vit, vnew, F, work, sc,   \
-                                                              prev)
+  k_gather_push<R_, true, PS, SPLIT_><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, vbar_out, F,    \
+                                                             work, sc, prev);                  \
+  k_gather_push<R_, false, PS, SPLIT_><<<ng, kBlock, 0, s>>>(P, st, vit, vnew, vbar_out, F,   \
+                                                              work, sc, prev)
   if constexpr (!PS::kMixed) {
     if (!P.split) {
       by_degree(r, [&](auto R) { ECPIC_GATHER_PAIR(R.value, false); });
@@ -1457,12 +1472,12 @@ void launch_fixed_current(hipStream_t s, int64_t n, unsigned long long* Jfix, do
 }
 
 #define ECPIC_INSTANTIATE_STORE(PS)                                                              \
-  template void launch_extrapolate<PS>(hipStream_t, int64_t, const PS&, double*);                \
+  template void launch_extrapolate<PS>(hipStream_t, int64_t, const PS&, double*, double*);                \
   template void launch_scatter<PS>(hipStream_t, int, const StepParams&, const PS&, const double*, \
-                                   CurrentOut, Scratch);                                         \
+                                   const double*, CurrentOut, Scratch);                          \
   template void launch_gather_push<PS>(hipStream_t, int, const StepParams&, const PS&,           \
-                                       const double*, double*, const double*, int*, Scratch,     \
-                                       AndersonPrev);                                            \
+                                       const double*, double*, double*, const double*, int*,     \
+                                       Scratch, AndersonPrev);                                   \
   template void launch_sweep<PS>(hipStream_t, int, const StepParams&, const PS&, const double*,  \
                                  const double*, const double*, Scratch);                         \
   template void launch_finalize<PS>(hipStream_t, const StepParams&, const PS&, const double*,     \

@@ -163,7 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_permute(int64_t np, const int* __res
                                                    int* __restrict__ cursor, PS src, PS dst,
                                                    const int* __restrict__ id,
                                                    int* __restrict__ id2,
-                                                   double* __restrict__ vit) {
+                                                   double* __restrict__ vit,
+                                                   double* __restrict__ vbar) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = i < np;
   const int k = active ? key[i] : 0;
@@ -176,7 +177,11 @@ __global__ __launch_bounds__(kBlock) void k_permute(int64_t np, const int* __res
     src.v_of(np, i, v);
     src.vp_of(np, i, vp);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) vit[a * np + j] = 2.0 * v[a] - vp[a];
+    for (int a = 0; a < 3; ++a) {
+      const double w = 2.0 * v[a] - vp[a];
+      vit[a * np + j] = w;
+      if (vbar) vbar[a * np + j] = 0.5 * (w + v[a]);
+    }
   }
 }
 
@@ -212,7 +217,7 @@ void launch_iota(hipStream_t s, int64_t n, int* p) {
 
 template <class PS>
 void launch_sort(hipStream_t s, const Grid& G, int64_t np, PS& cur, PS& alt, int*& id, int*& id2,
-                 const SortScratch& b, double* vit) {
+                 const SortScratch& b, double* vit, double* vbar) {
   if (np <= 0) return;
   const int64_t nkeys = 8 * G.ncell;
   k_fill_int<<<blocks_for(nkeys), kBlock, 0, s>>>(nkeys, b.count, 0);
@@ -221,7 +226,8 @@ void launch_sort(hipStream_t s, const Grid& G, int64_t np, PS& cur, PS& alt, int
   k_scan_totals<<<(unsigned)nb, kBlock, 0, s>>>(nkeys, b.count, b.scan_totals);
   k_scan_block_totals<<<1, kBlock, 0, s>>>(nb, b.scan_totals, b.offset, nkeys);
   k_scan_apply<<<(unsigned)nb, kBlock, 0, s>>>(nkeys, b.count, b.scan_totals, b.offset, b.cursor);
-  k_permute<PS><<<blocks_for(np), kBlock, 0, s>>>(np, b.key, b.cursor, cur, alt, id, id2, vit);
+  k_permute<PS><<<blocks_for(np), kBlock, 0, s>>>(np, b.key, b.cursor, cur, alt, id, id2, vit,
+                                                   vbar);
   // the sorted copies become the particle arrays
   const PS t = cur;
   cur = alt;
@@ -232,9 +238,11 @@ void launch_sort(hipStream_t s, const Grid& G, int64_t np, PS& cur, PS& alt, int
 }
 
 template void launch_sort<Fp64Store>(hipStream_t, const Grid&, int64_t, Fp64Store&, Fp64Store&,
-                                     int*&, int*&, const SortScratch&, double*);
+                                     int*&, int*&, const SortScratch&, double*,
+                                     double*);
 template void launch_sort<MixedStore>(hipStream_t, const Grid&, int64_t, MixedStore&,
-                                      MixedStore&, int*&, int*&, const SortScratch&, double*);
+                                      MixedStore&, int*&, int*&, const SortScratch&, double*,
+                                     double*);
 
 void launch_to_caller(hipStream_t s, int64_t np, const int* id, const double* src, double* dst) {
   if (np > 0) k_to_caller<<<blocks_for(np), kBlock, 0, s>>>(np, id, src, dst);
