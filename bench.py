@@ -44,25 +44,26 @@ def gather_flops_per_push(r: int, pieces_per_orbit: float) -> float:
     contraction 6: 1251; knot-merge bookkeeping 6; total 1920.  Per particle:
     two point interpolants of A (2 x 228), the momentum update and velocity
     closure (36), orbit set-up, end-point wrap, crossing set-up and error
-    maxima (~66) = 560.  For r = 1 (2-point rule, 2x2x2 nodes) the same
-    terms give 410 per piece and 250 per particle."""
+    maxima (~66), the next pass's vbar (6) = 566.  For r = 1 (2-point rule,
+    2x2x2 nodes) the same terms give 410 per piece and 256 per particle."""
     if r == 2:
-        return 560.0 + pieces_per_orbit * 1920.0
-    return 250.0 + pieces_per_orbit * 410.0
+        return 566.0 + pieces_per_orbit * 1920.0
+    return 256.0 + pieces_per_orbit * 410.0
 
 
 def gather_bytes_per_push() -> float:
-    """Algorithmic HBM bytes of the gather + push kernel per particle-push:
-    read x^n, v^n, v^{n+1,p} (3 x 24 B), write v^{n+1,p+1} (24 B); the mesh
-    fields (80 B per node, 2.6 MB at 32^3) stay in L2 / MALL."""
-    return 96.0
+    """Algorithmic HBM bytes of the gather + push kernel per particle-push
+    of the plain Picard iteration: read x^n, v^n, v^{n+1,p} (3 x 24 B),
+    write v^{n+1,p+1} and the next pass's vbar (2 x 24 B); the mesh fields
+    (80 B per node, 2.6 MB at 32^3) stay in L2 / MALL."""
+    return 120.0
 
 
 # Calibrated HBM traffic per launch of k_gather_push<2> on the 32^3 /
 # 2,097,152-particle workload, from FETCH_SIZE and WRITE_SIZE runs scaled by
 # the same counters on a streaming kernel of known size; valid only for the
 # library version it was measured on (profiles/hbm_traffic_gather_scatter_32cubed_fp64.md).
-MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.11", "workload": "c2", "bytes": 209.6e6}
+MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.14", "workload": "c2", "bytes": 259.9e6}
 
 
 def time_workload(E, wl, precision, steps, warmup, anderson=0):
