@@ -194,3 +194,32 @@ def test_contribution_beyond_the_fixed_point_range_is_an_error():
     ok = E.Sim(mixed_cfg(wl, fixed_point_scale=2.0 ** 44), wl.np)
     ok.init_particles(x, v, wl.q, wl.m, wl.n0)
     assert ok.picard_step()["converged"]
+
+
+def test_full_size_64cubed_mixed_steps_keep_the_invariants():
+    """The 64^3 / 33,554,432-particle thermal two-stream workload in the mixed
+    form, at the scatter chunk the library settles on (the oracle cannot run
+    this size, so the check is by the properties that hold at any size):
+    every step converges, the energy error per step stays within the FP32
+    rounding of the accepted velocities (2^-23), the discrete chain rule
+    (R_A) and the partition of unity hold at roundoff, and the Gauss and
+    gauge residuals stay at roundoff of the charge and potential scales."""
+    wl = W.two_stream("c4")
+    x, v = to_storage(wl, wl.x, wl.v)
+    g = E.Sim(mixed_cfg(wl, diagnostics=True), wl.np)
+    g.init_particles(x, v, wl.q, wl.m, wl.n0)
+    for step in range(3):
+        info = g.picard_step()
+        e = g.energy_diagnostics()
+        f = g.get_state()["fields"]
+        rho, A, psi = np.abs(f[8]).max(), np.abs(f[2:5]).max(), np.abs(f[1]).max()
+        kmax = np.pi * max(wl.n[a] / wl.L[a] for a in range(3))
+        log(f"[c4 step {step}] {info['iters']} passes, R_total/E {e['R_total'] / e['E_total']:.2e}, "
+            f"RA_max {e['RA_max']:.2e}, pou {e['pou_max']:.2e}, gauss {e['gauss_max']:.2e} "
+            f"(rho {rho:.2e}), gauge {e['gauge_max']:.2e} (psi {psi:.2e}, A {A:.2e})")
+        assert info["converged"]
+        assert abs(e["R_total"]) <= 2.0 ** -23 * e["E_total"]
+        assert e["RA_max"] <= 1e-12 * A and e["pou_max"] < 1e-14
+        # Theorem 1: the residuals are rounding of the spectral sums
+        assert e["gauss_max"] <= 1e-11 * rho
+        assert e["gauge_max"] <= 1e-11 * max(psi, kmax * A)
