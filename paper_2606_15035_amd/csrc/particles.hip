@@ -495,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_extrapolate(int64_t n3, const T* __r
 // switches to 2048-particle chunks; cubic stencils use those from the start.
 // Quadratic and linear 2048-particle chunks fit a 2048-node tile (48 KB),
 // which lets three blocks share a CU (three waves per SIMD at 168 registers:
-// 64^3 mixed scatter 5.04 -> 4.71 ms per pass); the cubic ones need 3072.
+// 64^3 mixed scatter 5.04 -> 4.79 ms per pass); the cubic ones need 3072.
 template <int R, int CH>
 struct ScatterChunk {
   static constexpr int kChunk = CH;
