@@ -63,7 +63,7 @@ def gather_bytes_per_push() -> float:
 # 2,097,152-particle workload, from FETCH_SIZE and WRITE_SIZE runs scaled by
 # the same counters on a streaming kernel of known size; valid only for the
 # library version it was measured on (profiles/hbm_traffic_gather_scatter_32cubed_fp64.md).
-MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.14", "workload": "c2", "bytes": 259.9e6}
+MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.15", "workload": "c2", "bytes": 259.9e6}
 
 
 def time_workload(E, wl, precision, steps, warmup, anderson=0):
@@ -80,7 +80,7 @@ def time_workload(E, wl, precision, steps, warmup, anderson=0):
     for _ in range(warmup):
         sim.picard_step()
     torch.cuda.synchronize()
-    sim.set_profiling(True)
+    sim.set_profiling(2)  # events around the gather only
     iters, rel = [], 0.0
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -88,15 +88,28 @@ def time_workload(E, wl, precision, steps, warmup, anderson=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = sim.get_profile()
-    sim.set_profiling(False)
+    sim.set_profiling(0)
     e = sim.energy_diagnostics()  # the last step's R_total and the level's energy
     rel = abs(e["R_total"]) / e["E_total"]
     drift = abs(e["E_total"] - E0) / E0
+    prof["phases"] = phase_split(sim)
     out = (wl.np * sum(iters) / wall, wall / steps * 1e3, float(np.mean(iters)), rel, drift, prof)
     sim.close()
     del sim
     torch.cuda.empty_cache()
     return out
+
+
+def phase_split(sim, steps=2):
+    """Per-pass times of the scatter, field solve and gather phases from
+    `steps` more steps with events around every phase (after the timed
+    region: each event between two kernels idles the GPU a few us)."""
+    sim.set_profiling(1)
+    for _ in range(steps):
+        sim.picard_step()
+    p = sim.get_profile()
+    sim.set_profiling(0)
+    return {k: p[k]["ms"] / max(p[k]["launches"], 1) for k in ("scatter", "field_solve", "gather_push")}
 
 
 def run_cpu_baseline(wl, seconds_budget=30.0):
@@ -151,7 +164,7 @@ def main():
         sim.picard_step()
     torch.cuda.synchronize()
 
-    sim.set_profiling(True)
+    sim.set_profiling(2)  # HIP events around the gather only
     iters = []
     dE = []
     torch.cuda.synchronize()
@@ -162,7 +175,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = sim.get_profile()
-    sim.set_profiling(False)
+    sim.set_profiling(0)
     wall = t1 - t0
     pushes = wl.np * sum(iters)
     value = pushes / wall
@@ -207,8 +220,9 @@ def main():
                    "spline_degree": wl.r, "dt": wl.dt, "picard_tol": wl.tol,
                    "precision": "fp64", "picard_passes_mean": float(np.mean(iters)),
                    "dE_over_E_step": rel_step, "dE_over_E_run": drift},
-        "phases_ms_per_pass": {k: prof[k]["ms"] / max(prof[k]["launches"], 1)
-                               for k in ("scatter", "field_solve", "gather_push")},
+        # two more steps with events around every phase (outside the timed
+        # region, whose gather events give the roofline)
+        "phases_ms_per_pass": phase_split(sim),
         "roofline": roofline,
     }
     del sim
@@ -240,9 +254,7 @@ def main():
                            "steps": steps, "warmup": warm, "particles": wlm.np,
                            "mesh": list(wlm.n), "picard_passes_mean": it_,
                            "dE_over_E_step": rel_, "dE_over_E_run": drift_,
-                           "phases_ms_per_pass": {k: pr_[k]["ms"] / max(pr_[k]["launches"], 1)
-                                                  for k in ("scatter", "field_solve",
-                                                            "gather_push")},
+                           "phases_ms_per_pass": pr_["phases"],
                            "pieces_per_orbit": pr_["pieces"] / max(wlm.np * g_["launches"], 1),
                            "workload": wlm.description}
         out["mixed"] = mixed

@@ -221,22 +221,25 @@ ecpic_status ecpic_orbit_gather(const ecpic_config* cfg, int64_t n, const double
 ecpic_status ecpic_orbit_deposit(const ecpic_config* cfg, int64_t n, const double* x0,
                                  const double* d, const double* qv, double* J, void* hip_stream);
 
-/* Kernel timing.  When enabled, ecpic_picard_step() records HIP events on the
+/* Kernel timing.  level 1: ecpic_picard_step() records HIP events on the
    simulation's stream around each phase of every Picard pass and accumulates
    the elapsed times (milliseconds) and launch counts per phase:
      0 orbit current scatter, 1 field solve (forward FFT, continuity + CN,
      inverse FFT), 2 orbit gather + push, 3 consistency sweep, 4 end-of-step
      update, 5 whole steps (host wall clock from entry to return).
+   level 2: phases 2 and 5 only (two events per pass instead of four; each
+   event between two kernels costs a few microseconds of idle GPU).
+   level 0 turns timing off; other levels are ECPIC_EINVAL.
    pieces: total orbit pieces summed over particles and gather launches, so
    that pieces / (np * launches[2]) is the mean number of pieces per orbit.
-   Enabling resets the counters. */
+   Setting a level resets the counters. */
 typedef struct {
   double ms[8];
   int64_t launches[8];
   double pieces;
 } ecpic_profile;
 
-ecpic_status ecpic_set_profiling(ecpic_sim* sim, int32_t enable);
+ecpic_status ecpic_set_profiling(ecpic_sim* sim, int32_t level);
 ecpic_status ecpic_get_profile(ecpic_sim* sim, ecpic_profile* out);
 
 /* ---- Differentiation: adjoint of one converged step --------------------

@@ -203,7 +203,7 @@ struct ecpic_sim {
   Scratch sc;
   double* host = nullptr;  // pinned read-back
   // kernel timing
-  bool profiling = false;
+  int profiling = 0;  // 0 off, 1 every phase, 2 the gather phase only
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   ecpic_profile prof{};
   // energy bookkeeping
@@ -626,7 +626,8 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   double2* nxt = S->spec[1 - S->cur];
 
   const auto t_start = std::chrono::steady_clock::now();
-  const bool prof = S->profiling;
+  const bool prof = S->profiling == 1;         // events around every phase
+  const bool prof_g = S->profiling != 0;       // events around the gather
   // Iterates w_{p-j} (wl[j]) and images g_{p-j} (gl[j]) of the passes the
   // Anderson mixing still needs, newest first (the plain iteration keeps one
   // of each and takes w_{p+1} = g_p without a copy).
@@ -694,11 +695,11 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
       launch_cn_update(s, F, cur, S->Jh, nxt, S->batch, S->sc);
       fft3_inverse(s, S->G, 6, S->batch, &gout, twp(S));
     }
-    if (prof) HIPCHK(hipEventRecord(S->ev[2], s));
+    if (prof_g) HIPCHK(hipEventRecord(S->ev[2], s));
     on_store(S, [&](auto& st, auto&) {  // v^{n+1,p+1}
       launch_gather_push(s, r, P, st, S->vit, S->vnew, S->vbar, S->gbuf, S->gwork, S->sc, prev);
     });
-    if (prof) HIPCHK(hipEventRecord(S->ev[3], s));
+    if (prof_g) HIPCHK(hipEventRecord(S->ev[3], s));
     AndersonVecs av{};
     for (int j = 0; j <= mk; ++j) {
       av.w[j] = wl[j];
@@ -722,15 +723,18 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     ecpic_status st = sync_read(S, S_DVMAX, (S_AA - S_DVMAX) + anderson_sums(mk));
     if (st != ECPIC_OK) return st;
     if (prof) {
-      float t01 = 0.f, t12 = 0.f, t23 = 0.f;
+      float t01 = 0.f, t12 = 0.f;
       HIPCHK(hipEventElapsedTime(&t01, S->ev[0], S->ev[1]));
       HIPCHK(hipEventElapsedTime(&t12, S->ev[1], S->ev[2]));
-      HIPCHK(hipEventElapsedTime(&t23, S->ev[2], S->ev[3]));
       S->prof.ms[0] += t01;
       S->prof.ms[1] += t12;
-      S->prof.ms[2] += t23;
       S->prof.launches[0] += 1;
       S->prof.launches[1] += 1;
+    }
+    if (prof_g) {
+      float t23 = 0.f;
+      HIPCHK(hipEventElapsedTime(&t23, S->ev[2], S->ev[3]));
+      S->prof.ms[2] += t23;
       S->prof.launches[2] += 1;
     }
     const double dv = S->host[0], vm = S->host[1], dj = S->host[2], js = S->host[3];
@@ -809,6 +813,8 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     }
     S->prof.ms[4] += tb;
     S->prof.launches[4] += 1;
+  }
+  if (prof_g) {
     S->prof.pieces += h[S_PIECES];
     S->prof.ms[5] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     S->prof.launches[5] += 1;
@@ -1005,10 +1011,11 @@ ecpic_status ecpic_orbit_deposit(const ecpic_config* cfg, int64_t n, const doubl
 
 ecpic_status ecpic_set_profiling(ecpic_sim* S, int32_t enable) {
   if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  if (enable < 0 || enable > 2) return fail(ECPIC_EINVAL, "profiling level must be 0, 1 or 2");
   if (enable)
     for (auto& e : S->ev)
       if (!e) HIPCHK(hipEventCreate(&e));
-  S->profiling = enable != 0;
+  S->profiling = enable;
   S->prof = ecpic_profile{};
   return ECPIC_OK;
 }
@@ -1166,6 +1173,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.14"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.15"; }
 
 }  // extern "C"

@@ -254,8 +254,9 @@ class Sim:
             self.q, self.m = q, m
         _check(lib().ecpic_set_state(self._h, *[_hp(a) for a in args], q, m))
 
-    def set_profiling(self, enable=True):
-        _check(lib().ecpic_set_profiling(self._h, int(bool(enable))))
+    def set_profiling(self, level=1):
+        """0 off, 1 (or True) every phase, 2 the gather phase only."""
+        _check(lib().ecpic_set_profiling(self._h, int(level)))
 
     def get_profile(self):
         p = Profile()
