@@ -63,7 +63,7 @@ def gather_bytes_per_push() -> float:
 # 2,097,152-particle workload, from FETCH_SIZE and WRITE_SIZE runs scaled by
 # the same counters on a streaming kernel of known size; valid only for the
 # library version it was measured on (profiles/hbm_traffic_gather_scatter_32cubed_fp64.md).
-MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.15", "workload": "c2", "bytes": 259.9e6}
+MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.15", "workload": "c2", "bytes": 264.9e6}
 
 
 def time_workload(E, wl, precision, steps, warmup, anderson=0):
