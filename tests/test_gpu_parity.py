@@ -356,3 +356,35 @@ def test_errors_are_reported():
     s2.init_particles(wl.x, wl.v, wl.q, wl.m)
     info = s2.picard_step()
     assert info["status"] == E.ENOCONV and info["iters"] == 1
+
+
+def test_profiling_levels():
+    """Level 1 times every phase of every pass; level 2 only the gather (and
+    whole steps); other levels are rejected.  Timing changes no result."""
+    wl = small_random(2, np_=3000, seed=17)
+    runs = {}
+    for level in (0, 1, 2):
+        g = E.Sim(gpu_cfg(wl, tol=0.0, pmax=2), wl.np)
+        g.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
+        g.set_profiling(level)
+        for _ in range(2):
+            g.picard_step()
+        p = g.get_profile()
+        runs[level] = g.get_state()
+        if level == 1:
+            assert all(p[k]["launches"] == 6 for k in ("scatter", "field_solve", "gather_push"))
+            assert p["gather_push"]["ms"] > 0.0 and p["scatter"]["ms"] > 0.0
+        elif level == 2:
+            assert p["gather_push"]["launches"] == 6 and p["scatter"]["launches"] == 0
+            assert p["step"]["launches"] == 2
+            assert p["pieces"] > wl.np * 6  # every orbit has at least one piece
+        else:
+            assert p["gather_push"]["launches"] == 0
+        if level == 2:
+            with pytest.raises(E.EcpicError) as ei:
+                g.set_profiling(3)
+            assert ei.value.status == E.EINVAL
+    for k in ("x", "v", "fields"):  # FP64 atomics: equal up to their order
+        scale = np.abs(runs[0][k]).max()
+        for level in (1, 2):
+            assert np.abs(runs[0][k] - runs[level][k]).max() <= 1e-13 * scale, (k, level)
