@@ -140,8 +140,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU particle decomposition is a design note, not built.", flush=True)
+        print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); "
+              "the particle decomposition over several GPUs is designed, not implemented.",
+              flush=True)
         sys.exit(2)
 
     import torch
