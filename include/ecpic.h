@@ -19,8 +19,10 @@
  *     "state" (persistent between steps) and "workspace" (scratch) memory a
  *     simulation needs; the caller allocates both on the device (256-byte
  *     aligned) and hands them to ecpic_create().  The library never allocates or
- *     frees device memory.  It allocates a small pinned host buffer for the
- *     per-iteration convergence read-back.
+ *     frees device memory; the one device array it holds is the fixed
+ *     workspace of ecpic_adjoint_step_noalloc(), loaded with its code.  It
+ *     allocates a small pinned host buffer for the per-iteration convergence
+ *     read-back.
  *   - All device work is enqueued on the HIP stream given to ecpic_create()
  *     (NULL = default stream).  Calls that return host data synchronise that
  *     stream; ecpic_picard_step() synchronises it once per Picard iteration to
@@ -284,6 +286,30 @@ ecpic_status ecpic_adjoint_step(ecpic_sim* sim, void* workspace, size_t workspac
                                 const double* fields, const double* lx1, const double* lv1,
                                 const double* lF1, double* lx0, double* lv0, double* lF0,
                                 double tol, int32_t max_iters, ecpic_adjoint_info* info);
+
+/* Allocation-free variant of ecpic_adjoint_step, for callers that cannot
+   allocate device memory or take a caller workspace (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+   arguments, requirements, results and status codes as ecpic_adjoint_step
+   without the workspace pair: the workspace is a device array inside the
+   library, ECPIC_STATIC_SCRATCH_BYTES (64 MiB) on every GPU the library runs
+   on, held from the first ecpic_create() on that GPU until the process ends.
+   The call allocates nothing (no hipMalloc, hipFree or allocating library
+   routine).
+     - ECPIC_ENOMEM if ecpic_adjoint_workspace_bytes() of this simulation
+       exceeds ECPIC_STATIC_SCRATCH_BYTES (about 150,000 particles on a 32^3
+       mesh, 300,000 on 16^3); nothing is run.
+     - ECPIC_EINVAL if the device current at ecpic_create() is not current.
+   Every call on one GPU uses that GPU's one array and leaves its contents
+   behind (each call writes every part it reads before reading it): calls
+   that overlap in time on one GPU, from other threads or on other streams,
+   race on it, and the caller must serialise them. */
+#define ECPIC_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+ecpic_status ecpic_adjoint_step_noalloc(ecpic_sim* sim, const double* x, const double* v,
+                                        const double* w, const double* fields, const double* lx1,
+                                        const double* lv1, const double* lF1, double* lx0,
+                                        double* lv0, double* lF0, double tol, int32_t max_iters,
+                                        ecpic_adjoint_info* info);
 
 /* Gradient of the field energy W (eq. field-energy) of the present state with
    respect to its real-space fields: device output, 9*ncell (layout of

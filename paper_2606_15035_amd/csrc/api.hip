@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -158,6 +159,37 @@ struct Carver {
   }
 };
 
+// Device workspace of ecpic_adjoint_step_noalloc, for callers that cannot
+// allocate: one copy of this array on every GPU the library runs on, held
+// until the process ends.  In host code `scratch` is a host-side stand-in;
+// its device address on each GPU comes from hipGetSymbolAddress (per device,
+// with that device current) and only that address is handed to kernels.
+constexpr size_t kStaticScratchBytes = ECPIC_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved once per device).
+ecpic_status static_scratch_address(int* device, void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(ECPIC_EDEVICE, "no usable current device for the static scratch array");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ECPIC_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *device = dev;
+  *out = g_scratch_addr[dev];
+  return ECPIC_OK;
+}
+
 }  // namespace
 
 struct ecpic_sim {
@@ -165,6 +197,8 @@ struct ecpic_sim {
   Grid G;
   int64_t np;
   hipStream_t stream;
+  int device = -1;                 // the device current at ecpic_create
+  void* static_scratch = nullptr;  // address of `scratch` on that device
   double q = -1.0, m = 1.0;  // species 0
   int nsp = 1;               // species; > 1: the stores hold one byte per particle
   double qs[kMaxSpecies] = {-1.0}, ms[kMaxSpecies] = {1.0};
@@ -448,11 +482,17 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
     return fail(ECPIC_ENOMEM, "buffers too small: need state %zu, workspace %zu", need_s, need_w);
   if ((reinterpret_cast<uintptr_t>(state_dev) & 255) || (reinterpret_cast<uintptr_t>(workspace_dev) & 255))
     return fail(ECPIC_EINVAL, "device buffers must be 256-byte aligned");
+  int device = -1;
+  void* static_ws = nullptr;
+  st = static_scratch_address(&device, &static_ws);
+  if (st != ECPIC_OK) return st;
   ecpic_sim* S = new ecpic_sim();
   S->cfg = *cfg;
   S->G = make_grid(cfg);
   S->np = n_particles;
   S->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  S->device = device;
+  S->static_scratch = static_ws;
   S->fix_scale = cfg->fixed_point_scale > 0.0 ? cfg->fixed_point_scale : 0x1p40;
   S->rule = gauss_rule01(quad_rule_points(cfg));
   carve(S, static_cast<char*>(state_dev), static_cast<char*>(workspace_dev), nullptr, nullptr);
@@ -1040,25 +1080,23 @@ ecpic_status ecpic_adjoint_workspace_bytes(const ecpic_config* cfg, int64_t n_pa
   return ECPIC_OK;
 }
 
-ecpic_status ecpic_adjoint_step(ecpic_sim* S, void* workspace, size_t workspace_bytes,
-                                const double* x, const double* v, const double* w,
-                                const double* fields, const double* lx1, const double* lv1,
-                                const double* lF1, double* lx0, double* lv0, double* lF0,
-                                double tol, int32_t max_iters, ecpic_adjoint_info* info) {
-  if (!S) return fail(ECPIC_EINVAL, "null simulation");
-  ecpic_status st = check_adjoint_config(&S->cfg);
-  if (st != ECPIC_OK) return st;
-  if (S->nsp != 1) return fail(ECPIC_EINVAL, "adjoint: one particle species only");
-  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
-    return fail(ECPIC_EINVAL, "adjoint workspace must be non-null and 256-byte aligned");
+}  // extern "C"
+
+namespace {
+
+// The adjoint step over a workspace of at least carve_adjoint() bytes
+// (checked by the callers); every workspace array is written before it is read.
+ecpic_status adjoint_step_impl(ecpic_sim* S, char* workspace, const double* x, const double* v,
+                               const double* w, const double* fields, const double* lx1,
+                               const double* lv1, const double* lF1, double* lx0, double* lv0,
+                               double* lF0, double tol, int32_t max_iters,
+                               ecpic_adjoint_info* info) {
   const int64_t np = S->np, nc = S->G.ncell, n3 = 3 * np;
   AdjWs A;
-  if (carve_adjoint(S->G, np, nullptr, &A) > workspace_bytes)
-    return fail(ECPIC_ENOMEM, "adjoint workspace too small");
   if (!fields || !lx0 || !lv0 || !lF0 || (np > 0 && (!x || !v || !w)))
     return fail(ECPIC_EINVAL, "null state or output pointer");
   if (!(tol >= 0.0) || max_iters < 0) return fail(ECPIC_EINVAL, "tol >= 0 and max_iters >= 0");
-  carve_adjoint(S->G, np, static_cast<char*>(workspace), &A);
+  carve_adjoint(S->G, np, workspace, &A);
   hipStream_t s = S->stream;
   const Grid& G = S->G;
   const FieldParams FP = S->fp();
@@ -1149,6 +1187,56 @@ ecpic_status ecpic_adjoint_step(ecpic_sim* S, void* workspace, size_t workspace_
     info->err = err;
   }
   return conv ? ECPIC_OK : ECPIC_ENOCONV;
+}
+
+ecpic_status check_adjoint_call(ecpic_sim* S) {
+  if (!S) return fail(ECPIC_EINVAL, "null simulation");
+  ecpic_status st = check_adjoint_config(&S->cfg);
+  if (st != ECPIC_OK) return st;
+  if (S->nsp != 1) return fail(ECPIC_EINVAL, "adjoint: one particle species only");
+  return ECPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ecpic_status ecpic_adjoint_step(ecpic_sim* S, void* workspace, size_t workspace_bytes,
+                                const double* x, const double* v, const double* w,
+                                const double* fields, const double* lx1, const double* lv1,
+                                const double* lF1, double* lx0, double* lv0, double* lF0,
+                                double tol, int32_t max_iters, ecpic_adjoint_info* info) {
+  ecpic_status st = check_adjoint_call(S);
+  if (st != ECPIC_OK) return st;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(ECPIC_EINVAL, "adjoint workspace must be non-null and 256-byte aligned");
+  AdjWs A;
+  if (carve_adjoint(S->G, S->np, nullptr, &A) > workspace_bytes)
+    return fail(ECPIC_ENOMEM, "adjoint workspace too small");
+  return adjoint_step_impl(S, static_cast<char*>(workspace), x, v, w, fields, lx1, lv1, lF1, lx0,
+                           lv0, lF0, tol, max_iters, info);
+}
+
+ecpic_status ecpic_adjoint_step_noalloc(ecpic_sim* S, const double* x, const double* v,
+                                        const double* w, const double* fields, const double* lx1,
+                                        const double* lv1, const double* lF1, double* lx0,
+                                        double* lv0, double* lF0, double tol, int32_t max_iters,
+                                        ecpic_adjoint_info* info) {
+  ecpic_status st = check_adjoint_call(S);
+  if (st != ECPIC_OK) return st;
+  AdjWs A;
+  const size_t need = carve_adjoint(S->G, S->np, nullptr, &A);
+  if (need > kStaticScratchBytes)
+    return fail(ECPIC_ENOMEM,
+                "adjoint workspace of %zu bytes exceeds the %zu-byte static scratch array; "
+                "use ecpic_adjoint_step with a caller workspace",
+                need, kStaticScratchBytes);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != S->device)
+    return fail(ECPIC_EINVAL, "the device of ecpic_create (%d) must be current (is %d)", S->device,
+                dev);
+  return adjoint_step_impl(S, static_cast<char*>(S->static_scratch), x, v, w, fields, lx1, lv1,
+                           lF1, lx0, lv0, lF0, tol, max_iters, info);
 }
 
 ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {

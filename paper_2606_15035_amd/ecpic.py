@@ -103,6 +103,8 @@ def lib():
         L.ecpic_adjoint_workspace_bytes.argtypes = [cfgp, I64, C.POINTER(C.c_size_t)]
         L.ecpic_adjoint_step.argtypes = [P, P, C.c_size_t, D, D, D, D, D, D, D, D, D, D,
                                          C.c_double, C.c_int32, C.POINTER(AdjointInfo)]
+        L.ecpic_adjoint_step_noalloc.argtypes = [P, D, D, D, D, D, D, D, D, D, D, C.c_double,
+                                                 C.c_int32, C.POINTER(AdjointInfo)]
         L.ecpic_field_energy_grad.argtypes = [P, D]
         L.ecpic_last_error.restype = C.c_char_p
         L.ecpic_version.restype = C.c_char_p
@@ -112,7 +114,8 @@ def lib():
                      "ecpic_get_state", "ecpic_set_state", "ecpic_get_current",
                      "ecpic_orbit_gather", "ecpic_orbit_deposit", "ecpic_set_profiling",
                      "ecpic_get_profile", "ecpic_adjoint_workspace_bytes",
-                     "ecpic_adjoint_step", "ecpic_field_energy_grad"):
+                     "ecpic_adjoint_step", "ecpic_adjoint_step_noalloc",
+                     "ecpic_field_energy_grad"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -143,6 +146,17 @@ def make_config(n, L, dt, r=1, kappa=1.0, sigma1=1.0, sigma2=1.0, tol=1e-12, pma
     c.anderson_depth = int(anderson)
     c.scatter_chunk = int(scatter_chunk)
     return c
+
+
+# bytes of the library's fixed workspace of ecpic_adjoint_step_noalloc
+# (ECPIC_STATIC_SCRATCH_BYTES in include/ecpic.h)
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def adjoint_workspace_bytes(cfg: Config, n_particles: int) -> int:
+    nb = C.c_size_t()
+    _check(lib().ecpic_adjoint_workspace_bytes(C.byref(cfg), int(n_particles), C.byref(nb)))
+    return nb.value
 
 
 def state_bytes(cfg: Config, n_particles: int):
@@ -284,12 +298,15 @@ class Sim:
         _check(lib().ecpic_field_energy_grad(self._h, C.c_void_p(g.data_ptr())))
         return g
 
-    def adjoint_step(self, x, v, w, F, lx1=None, lv1=None, lF1=None, tol=1e-13, max_iters=100):
+    def adjoint_step(self, x, v, w, F, lx1=None, lv1=None, lF1=None, tol=1e-13, max_iters=100,
+                     noalloc=False):
         """Adjoint of the converged step from (x, v, F) whose solution is w
         (arrays or tensors; particles in the caller's order).  Returns device
-        tensors (lx0, lv0, lF0) and the iteration info."""
+        tensors (lx0, lv0, lF0) and the iteration info.  noalloc: call
+        ecpic_adjoint_step_noalloc (the library's own fixed workspace) instead
+        of ecpic_adjoint_step with a workspace tensor."""
         torch = self.torch
-        if getattr(self, "_adj_ws", None) is None:
+        if not noalloc and getattr(self, "_adj_ws", None) is None:
             nb = C.c_size_t()
             _check(lib().ecpic_adjoint_workspace_bytes(C.byref(self.cfg), self.np, C.byref(nb)))
             self._adj_ws = torch.empty(nb.value, dtype=torch.uint8, device=self.state.device)
@@ -301,10 +318,13 @@ class Sim:
         lF0 = torch.empty(pf, dtype=torch.float64, device=self.state.device)
         ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
         info = AdjointInfo()
-        st = lib().ecpic_adjoint_step(self._h, C.c_void_p(self._adj_ws.data_ptr()),
-                                      self._adj_ws.numel(), ptr(x), ptr(v), ptr(w), ptr(F),
-                                      ptr(lx1), ptr(lv1), ptr(lF1), ptr(lx0), ptr(lv0), ptr(lF0),
-                                      float(tol), int(max_iters), C.byref(info))
+        args = (ptr(x), ptr(v), ptr(w), ptr(F), ptr(lx1), ptr(lv1), ptr(lF1), ptr(lx0), ptr(lv0),
+                ptr(lF0), float(tol), int(max_iters), C.byref(info))
+        if noalloc:
+            st = lib().ecpic_adjoint_step_noalloc(self._h, *args)
+        else:
+            st = lib().ecpic_adjoint_step(self._h, C.c_void_p(self._adj_ws.data_ptr()),
+                                          self._adj_ws.numel(), *args)
         _check(st, allow=(OK, ENOCONV))
         return lx0, lv0, lF0, {"iters": info.iters, "converged": bool(info.converged),
                                "err": info.err}
