@@ -234,11 +234,15 @@ ecpic_status ecpic_orbit_deposit(const ecpic_config* cfg, int64_t n, const doubl
    level 0 turns timing off; other levels are ECPIC_EINVAL.
    pieces: total orbit pieces summed over particles and gather launches, so
    that pieces / (np * launches[2]) is the mean number of pieces per orbit.
+   scatter_chunk: particles per block the current scatter uses now (set at
+   every level, 0 included; see ecpic_config.scatter_chunk).
    Setting a level resets the counters. */
 typedef struct {
   double ms[8];
   int64_t launches[8];
   double pieces;
+  int32_t scatter_chunk;
+  int32_t reserved;
 } ecpic_profile;
 
 ecpic_status ecpic_set_profiling(ecpic_sim* sim, int32_t level);

@@ -1063,6 +1063,7 @@ ecpic_status ecpic_set_profiling(ecpic_sim* S, int32_t enable) {
 ecpic_status ecpic_get_profile(ecpic_sim* S, ecpic_profile* out) {
   if (!S || !out) return fail(ECPIC_EINVAL, "null argument");
   *out = S->prof;
+  out->scatter_chunk = S->pp().chunk;
   return ECPIC_OK;
 }
 

@@ -58,13 +58,15 @@ class Energy(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("pieces", C.c_double)]
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("pieces", C.c_double),
+                ("scatter_chunk", C.c_int32), ("reserved", C.c_int32)]
 
     PHASES = ("scatter", "field_solve", "gather_push", "sweep", "finalize", "step")
 
     def as_dict(self):
         return {name: {"ms": self.ms[i], "launches": self.launches[i]}
-                for i, name in enumerate(self.PHASES)} | {"pieces": self.pieces}
+                for i, name in enumerate(self.PHASES)} | {"pieces": self.pieces,
+                                                           "scatter_chunk": self.scatter_chunk}
 
 
 class AdjointInfo(C.Structure):
@@ -256,6 +258,12 @@ class Sim:
         f = np.zeros((9,) + self.n)
         _check(lib().ecpic_get_state(self._h, _hp(x), _hp(v), _hp(vp), _hp(f)))
         return {"x": x, "v": v, "vprev": vp, "fields": f}
+
+    def get_fields(self):
+        """Real-space mesh fields only (9,) + n: phi, psi, A, U, rho."""
+        f = np.zeros((9,) + self.n)
+        _check(lib().ecpic_get_state(self._h, None, None, None, _hp(f)))
+        return f
 
     def set_state(self, x=None, v=None, vprev=None, fields=None, q=None, m=None):
         """Replace parts of the state.  With q and m every particle becomes of

@@ -92,8 +92,17 @@ def _quiet_3d_lattice(n, L, sub):
     return np.stack([x.ravel(), y.ravel(), z.ravel()])
 
 
-def two_stream(name: str) -> Workload:
+def two_stream(name: str, mesh: tuple | None = None) -> Workload:
     """The named two-stream workload.
+
+    mesh: if given, the workload's physics on another mesh with the same
+    cell size (the box is mesh x H): the same particles per cell at the same
+    places within each cell, the same drift, perturbation, shape, dt and
+    tolerance.  For c1, c2, c3 and c5 the x extent must stay (the
+    perturbation is periodic in L_x); since every cell holds the same
+    pattern and the perturbation depends on x alone, a slab with fewer
+    y, z cells evolves exactly as the full box does, up to rounding.  c4's
+    thermal velocities are drawn per particle for the mesh given.
 
     c1  16x4x4 mesh, 8 particles per cell per beam (4096), linear shape, FP64,
         1e-3 sin(k1 x) velocity perturbation, dt = 0.1, 100 steps, tol 1e-12
@@ -143,6 +152,21 @@ def two_stream(name: str) -> Workload:
         desc = "two-stream 64^3, 4^3 lattice/cell/beam, quadratic, thermal 0.01"
     else:
         raise KeyError(name)
+    if mesh is not None:
+        mesh = tuple(int(k) for k in mesh)
+        if name != "c4" and mesh[0] != n[0]:
+            raise ValueError(f"{name}: the perturbation needs the x extent of {n[0]} cells")
+        H = L[0] / n[0]
+        n = mesh
+        L = tuple(k * H for k in mesh)
+        pos = _quiet_3d_lattice(n, L, 4) if name == "c4" else _quiet_x_lattice(n, L, ppb)
+        if name == "c2":
+            pert = sum(eps[m] * np.sin((m + 1) * K1 * pos[0] + th[m]) for m in range(4))
+        elif name == "c5":
+            pert = sum(1e-3 * np.sin((m + 1) * K1 * pos[0]) for m in range(8))
+        elif name in ("c1", "c3"):
+            pert = 1e-3 * np.sin(K1 * pos[0])
+        desc = desc + " on a {}x{}x{} mesh".format(*mesh)
 
     k = pos.shape[1] // int(np.prod(n))  # points per cell per beam
     ncell = int(np.prod(n))

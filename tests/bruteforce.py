@@ -183,3 +183,44 @@ def orbit_gather(r, x0, d, n, L, F):
         x = [x0[c] + s * d[c] for c in range(3)]
         return point_values(r, x, n, L, F)
     return orbit_integral(f, r, x0, d, n, L)
+
+
+# --------------------------------------------------------------------------
+# the unsplit comparison rule (Sec. 4.7, Tables 1-2): one n_q-point
+# Gauss-Legendre rule over the whole orbit s in [0, 1], each point weighted
+# by the true B-spline values (and gradients) at its own position, i.e. the
+# stencil of the cell the point lies in
+# --------------------------------------------------------------------------
+def unsplit_points(nq):
+    """numpy's Gauss-Legendre rule mapped to [0, 1]: (s_q, w_q)."""
+    z, w = np.polynomial.legendre.leggauss(nq)
+    return 0.5 * (1.0 + z), 0.5 * w
+
+
+def unsplit_sbar(r, x0, d, n, L, nq):
+    """{node: sum_q w_q S_g(x(s_q))}."""
+    acc = {}
+    for s, w in zip(*unsplit_points(nq)):
+        x = [x0[c] + s * d[c] for c in range(3)]
+        for g, v in shape_weights(r, x, n, L).items():
+            acc[g] = acc.get(g, 0.0) + v * w
+    return acc
+
+
+def unsplit_gather(r, x0, d, n, L, F, nq):
+    """sum_q w_q F_h(x(s_q))."""
+    out = np.zeros(F.shape[0])
+    for s, w in zip(*unsplit_points(nq)):
+        out += w * point_values(r, [x0[c] + s * d[c] for c in range(3)], n, L, F)
+    return out
+
+
+def unsplit_D(r, x0, d, n, L, A0, A1, nq):
+    """sum_q w_q [(1 - s_q) grad A0_h + s_q grad A1_h](x(s_q))."""
+    out = np.zeros((A0.shape[0], 3))
+    for s, w in zip(*unsplit_points(nq)):
+        x = [x0[c] + s * d[c] for c in range(3)]
+        _, g0 = point_values(r, x, n, L, A0, deriv=True)
+        _, g1 = point_values(r, x, n, L, A1, deriv=True)
+        out += w * ((1.0 - s) * g0 + s * g1)
+    return out

@@ -1,0 +1,361 @@
+"""The two-stream workloads run as specified on the GPU, through the C ABI.
+
+  c2  32^3, 2,097,152 particles, quadratic shape, FP64, dt 0.1, 200 steps,
+      tol 1e-10: every step converges; energy, Gauss and gauge residuals and
+      the chain rule stay at roundoff; the linear growth rate of the x-mode-1
+      field matches the cold-beam dispersion relation (Sec. 5.4; shape-
+      corrected 0.351759, bare 0.353392); and the whole history follows the
+      oracle's run of the same workload on a 32x4x4 slab, which evolves as
+      the full box does up to rounding (tests/golden/c2_slab_trajectory.txt,
+      written by the oracle alone).
+  c4  64^3, 33,554,432 particles, quadratic, mixed, dt 0.2, 100 steps,
+      tol 1e-8 (too large for the oracle): invariants every step until the
+      grid-scale mode that its thermal noise seeds stops the Picard iteration
+      from converging (see test_c4_run_as_specified).
+  c1  16x4x4, 4096 particles, linear shape, FP64, 100 steps, tol 1e-12:
+      side by side with the oracle, every step.
+  c4 physics on a 64x4x4 slab (131,072 particles: the same lattice per
+      cell, thermal spread, dt and tolerance, ~2.4 orbit pieces): the energy
+      history through the growth of that mode against the oracle's
+      (tests/golden/c4_slab_trajectory.txt), and single steps against the
+      oracle in FP64 and in the mixed form, with both scatter chunk lengths.
+"""
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from mixed_storage import check_mixed_step, to_storage
+from paper_2606_15035_amd import workloads as W
+from test_gpu_parity import field_scales
+
+pytestmark = pytest.mark.gpu
+
+E = pytest.importorskip("paper_2606_15035_amd.ecpic")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "c2_slab_trajectory.txt")
+GOLDEN_C4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "c4_slab_trajectory.txt")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    E.lib()
+    return torch
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def cfg_of(wl, precision=None, **kw):
+    args = dict(n=wl.n, L=wl.L, dt=wl.dt, r=wl.r, kappa=wl.kappa, sigma1=wl.sigma1,
+                sigma2=wl.sigma2, tol=wl.tol, pmax=wl.pmax,
+                precision=E.MIXED if (precision or wl.precision) == "mixed" else E.FP64)
+    args.update(kw)
+    return E.make_config(**args)
+
+
+def growth_rate(a, wp2):
+    """Cold symmetric beams, (w^2 - a^2)^2 = wp^2 (w^2 + a^2): Im w of the
+    unstable root."""
+    X = ((2 * a * a + wp2) - math.sqrt(wp2 * wp2 + 8 * a * a * wp2)) / 2.0
+    return math.sqrt(-X)
+
+
+def mode1_Ex(fields, n):
+    """x-mode-1 Fourier coefficient of E_x = -d phi/dx - U_x averaged over y
+    and z, normalised by n_x."""
+    ph = np.fft.fft(fields[0].mean(axis=(1, 2)))
+    ux = np.fft.fft(fields[5].mean(axis=(1, 2)))
+    return -(1j * W.K1 * ph[1] + ux[1]) / n[0]
+
+
+def exponents(y, dt, M):
+    """Matrix-pencil estimate of the M exponents lambda_j of a sampled sum
+    y(t_k) = sum_j c_j exp(lambda_j t_k) (Hua and Sarkar 1990)."""
+    N = len(y)
+    L = N // 2
+    Y = np.array([y[i:i + L + 1] for i in range(N - L)])
+    U, s, Vh = np.linalg.svd(Y[:, :-1], full_matrices=False)
+    U, s, Vh = U[:, :M], s[:M], Vh[:M]
+    Z = np.diag(1.0 / s) @ U.conj().T @ Y[:, 1:] @ Vh.conj().T
+    return np.log(np.linalg.eigvals(Z)) / dt
+
+
+def test_c2_run_as_specified():
+    wl = W.two_stream("c2")
+    vol = float(np.prod(wl.L))
+    t0 = time.time()
+    sim = E.Sim(cfg_of(wl, diagnostics=True), wl.np)
+    sim.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
+    e = sim.energy_diagnostics()
+    E0 = e["E_total"]
+    rows = [(0, 0, e["K"] / vol, e["W"] / vol, E0 / vol, mode1_Ex(sim.get_fields(), wl.n))]
+    worst = dict(R_total=0.0, RA=0.0, pou=0.0, gauge=0.0, gauss=0.0)
+    for k in range(1, wl.steps + 1):
+        info = sim.picard_step()
+        assert info["converged"], (k, info)
+        e = sim.energy_diagnostics()
+        f = sim.get_fields()
+        rows.append((k, info["iters"], e["K"] / vol, e["W"] / vol, e["E_total"] / vol,
+                     mode1_Ex(f, wl.n)))
+        worst["R_total"] = max(worst["R_total"], abs(e["R_total"]) / e["E_total"])
+        worst["RA"] = max(worst["RA"], e["RA_max"] / max(np.abs(f[2:5]).max(), 1e-300))
+        worst["pou"] = max(worst["pou"], e["pou_max"])
+        worst["gauge"] = max(worst["gauge"], e["gauge_max"])
+        worst["gauss"] = max(worst["gauss"], e["gauss_max"])
+    drift = abs(rows[-1][4] * vol - E0) / E0
+    passes = np.array([r[1] for r in rows[1:]])
+    log(f"c2: {wl.steps} steps in {time.time() - t0:.1f}s, passes {passes.mean():.2f} "
+        f"(max {passes.max()}), drift {drift:.2e}, " +
+        ", ".join(f"max {k} {v:.2e}" for k, v in worst.items()))
+    # the energy error of a step is the Picard truncation at tau = 1e-10
+    # weighted by the step's velocity change (the closed form of R_total)
+    assert drift <= 1e-12
+    assert worst["R_total"] <= 1e-12
+    assert worst["RA"] <= 1e-13 and worst["pou"] <= 1e-14
+    assert worst["gauge"] <= 1e-12 and worst["gauss"] <= 1e-10
+
+    # growth rate: the x-mode-1 field is a sum of the growing and decaying
+    # roots and the stable oscillating pair; the matrix pencil separates them
+    # over the linear phase t <= 10 (the beams trap near t = 13)
+    t = wl.dt * np.array([r[0] for r in rows])
+    c = np.array([r[5] for r in rows])
+    lam = exponents(c[t <= 10.0 + 1e-9], wl.dt, 4)
+    grow = lam[np.argmax(lam.real)]
+    a = W.K1 * W.V0
+    H = wl.L[0] / wl.n[0]
+    sinc = math.sin(W.K1 * H / 2) / (W.K1 * H / 2)
+    g0 = growth_rate(a, 1.0)
+    gs = growth_rate(a, sinc ** (2 * (wl.r + 1)))
+    log(f"c2 exponents {np.round(lam, 5)}; gamma {grow.real:.6f} vs shape-corrected "
+        f"{gs:.6f} ({grow.real / gs - 1:+.2%}), bare {g0:.6f} ({grow.real / g0 - 1:+.2%})")
+    assert abs(gs - 0.351759) < 1e-6 and abs(g0 - 0.353392) < 1e-6
+    assert abs(grow.imag) < 0.02
+    assert abs(grow.real - gs) <= 0.01 * gs and abs(grow.real - g0) <= 0.03 * g0
+
+    # the oracle's slab run of the same workload, step by step: through the
+    # linear phase the slab and the full box evolve alike up to rounding;
+    # after the beams trap, the full box's transverse modes (seeded by
+    # rounding, absent from a 4x4 slab) change K and W, not E_total
+    gold = np.loadtxt(GOLDEN)
+    assert gold.shape[0] == wl.steps + 1
+    Eg = gold[0, 4]
+    gpu = np.array([[r[2], r[3], r[4]] for r in rows])
+    dKWE = np.abs(gpu - gold[:, 2:5]) / Eg
+    cg = gold[:, 5] + 1j * gold[:, 6]
+    dc = np.abs(c - cg) / np.abs(cg).max()
+    lin = t <= 10.0 + 1e-9
+    apart = t[np.argmax(dKWE[:, 1] > 1e-9)] if np.any(dKWE[:, 1] > 1e-9) else None
+    same = float(np.mean(passes == gold[1:, 1]))
+    log(f"c2 vs oracle slab: linear phase max |dK|, |dW|, |dE| / E0 = "
+        + ", ".join(f"{x:.2e}" for x in dKWE[lin].max(axis=0))
+        + f", mode-1 field {dc[lin].max():.2e} of its max; whole run |dE|/E0 "
+        f"{dKWE[:, 2].max():.2e}; W apart by 1e-9 E0 from t = {apart}; "
+        f"passes equal on {same:.0%} of steps")
+    assert abs(rows[0][4] - Eg) <= 1e-13 * Eg
+    assert dKWE[lin].max() <= 1e-12 and dc[lin].max() <= 1e-12
+    assert dKWE[:, 2].max() <= 1e-12
+    assert np.all(np.abs(passes[lin[1:]] - gold[1:, 1][lin[1:]]) <= 1)
+
+
+def test_c4_run_as_specified():
+    """The 64^3 workload's 100 steps.  Its thermal noise (128 particles per
+    cell, Debye length 0.6 H) seeds a grid-scale mode of the counter-streaming
+    beams that grows at about 2 omega_p, far above the largest rate of the
+    cold-beam dispersion relation (0.354 omega_p); the oracle shows the same
+    on a slab of this workload (test_c4_physics_on_a_slab_matches_oracle).
+    Once the field energy reaches a few percent of the total, the Picard
+    iteration contracts too slowly for p_max = 16 and Algorithm 1 accepts the
+    last iterate (ECPIC_ENOCONV); the heating that follows lengthens the
+    orbits (slow passes, scatter chunks overflowing their tiles) until an orbit
+    crosses more than 63 knots in one step (ECPIC_EINVAL; step 51 of 100 when
+    measured).  The test stops four steps after the first unconverged one and
+    checks: every converged step keeps the energy within the FP32 rounding of
+    the accepted velocities, the chain rule and the partition of unity at
+    roundoff; every step, converged or not, keeps the Gauss and gauge
+    residuals at roundoff (Theorem 1 holds for any current); the first
+    unconverged step comes only after the field energy has grown past 1% of
+    the total; the growth rate of the field energy; the settled scatter chunk."""
+    wl = W.two_stream("c4")
+    x, v = to_storage(wl, wl.x, wl.v)
+    t0 = time.time()
+    sim = E.Sim(cfg_of(wl, diagnostics=True), wl.np)
+    sim.init_particles(x, v, wl.q, wl.m, wl.n0)
+    del x, v
+    E0 = sim.energy_diagnostics()["E_total"]
+    kmax = np.pi * max(wl.n[a] / wl.L[a] for a in range(3))
+    worst = dict(R_total=0.0, RA=0.0, pou=0.0, gauss=0.0, gauge=0.0)
+    passes, WE, first_unconverged, stop = [], [], None, None
+    sim.set_profiling(2)
+    pieces_lin = None
+    for k in range(1, wl.steps + 1):
+        if k == 6:  # orbit pieces of the linear phase (the heating lengthens orbits)
+            p = sim.get_profile()
+            pieces_lin = p["pieces"] / (wl.np * p["gather_push"]["launches"])
+        if first_unconverged is not None and k > first_unconverged[0] + 4:
+            break  # the heated phase: slow passes with long orbits, then the knot limit
+        try:
+            info = sim.picard_step()
+        except E.EcpicError as err:
+            stop = (k, err)
+            break
+        passes.append(info["iters"])
+        e = sim.energy_diagnostics()
+        WE.append(e["W"] / e["E_total"])
+        f = sim.get_fields()
+        rho, A, psi = np.abs(f[8]).max(), np.abs(f[2:5]).max(), np.abs(f[1]).max()
+        worst["gauss"] = max(worst["gauss"], e["gauss_max"] / rho)
+        worst["gauge"] = max(worst["gauge"], e["gauge_max"] / max(psi, kmax * A))
+        if info["converged"] and first_unconverged is None:
+            worst["R_total"] = max(worst["R_total"], abs(e["R_total"]) / e["E_total"])
+            worst["RA"] = max(worst["RA"], e["RA_max"] / A)
+            worst["pou"] = max(worst["pou"], e["pou_max"])
+        elif not info["converged"] and first_unconverged is None:
+            first_unconverged = (k, info, WE[-1])
+        if k % 10 == 0:
+            log(f"c4 step {k}: {passes[-10:]} passes, W/E {WE[-1]:.3e}, {time.time() - t0:.1f}s")
+    p = sim.get_profile()
+    WE = np.array(WE)
+    t = wl.dt * np.arange(1, len(WE) + 1)
+    sel = (WE > 1e-4) & (WE < 1e-2)
+    rate = 0.5 * np.polyfit(t[sel], np.log(WE[sel]), 1)[0] if sel.sum() >= 3 else float("nan")
+    log(f"c4: {len(passes)} steps in {time.time() - t0:.1f}s, passes {np.mean(passes):.2f}; "
+        f"first unconverged step {first_unconverged}; stopped {stop}; field growth rate "
+        f"{rate:.2f} omega_p; pieces per orbit {pieces_lin:.3f} (steps 1-5), scatter chunk "
+        f"{p['scatter_chunk']}; "
+        + ", ".join(f"max {k} {v:.2e}" for k, v in worst.items()))
+    assert worst["R_total"] <= 2.0 ** -23
+    assert worst["RA"] <= 1e-12 and worst["pou"] < 1e-14
+    assert worst["gauss"] <= 1e-11 and worst["gauge"] <= 1e-11
+    assert first_unconverged is None or first_unconverged[2] > 1e-2
+    assert sel.sum() >= 3 and rate > 1.0  # the grid-scale mode, not the two-stream's <= 0.354
+    assert stop is None or (stop[1].status == E.EINVAL and "knots" in str(stop[1]))
+    assert 2.2 < pieces_lin < 2.7 and p["scatter_chunk"] == 2048
+
+
+def test_c4_physics_on_a_slab_matches_oracle():
+    """The 64^3 workload's physics on a 64x4x4 slab (same cell size, 4x4x4
+    lattice per cell per beam, thermal spread 0.01, dt 0.2, quadratic, FP64;
+    131,072 particles): the GPU's field energy, kinetic energy and Picard
+    passes over the first 18 steps follow the oracle's run of the same slab
+    (tests/golden/c4_slab_trajectory.txt) through the growth of the grid-scale
+    mode from 1e-6 to over 5% of the energy, to within the rounding that
+    the mode amplifies."""
+    wl = W.two_stream("c4", mesh=(64, 4, 4))
+    vol = float(np.prod(wl.L))
+    gold = np.loadtxt(GOLDEN_C4)
+    g = E.Sim(cfg_of(wl, precision="fp64"), wl.np)
+    g.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
+    e = g.energy_diagnostics()
+    rows = [(0, 0, 1, e["K"] / vol, e["W"] / vol, e["E_total"] / vol)]
+    for k in range(1, gold.shape[0]):
+        info = g.picard_step()
+        e = g.energy_diagnostics()
+        rows.append((k, info["iters"], int(info["converged"]), e["K"] / vol, e["W"] / vol,
+                     e["E_total"] / vol))
+    got = np.array(rows, dtype=float)
+    E0 = gold[0, 5]
+    dK = np.abs(got[:, 3] - gold[:, 3]) / E0
+    dW = np.abs(got[:, 4] - gold[:, 4]) / np.maximum(gold[:, 4], 1e-12 * E0)
+    for k in range(0, gold.shape[0], 3):
+        log(f"[c4 slab] step {k}: passes {int(got[k, 1])}/{int(gold[k, 1])}, W/E {gold[k, 4] / gold[k, 5]:.3e}, "
+            f"|dW|/W {dW[k]:.2e}, |dK|/E0 {dK[k]:.2e}")
+    assert gold[-1, 4] / gold[-1, 5] > 0.05  # the mode really grew
+    assert dK.max() <= 1e-12 and dW.max() <= 1e-12
+    assert np.all(np.abs(got[1:, 1] - gold[1:, 1]) <= 1)
+
+
+@pytest.mark.parametrize("precision,chunk,after", [("fp64", 4096, 1), ("fp64", 2048, 14),
+                                                    ("mixed", 2048, 1), ("mixed", 4096, 14)])
+def test_c4_physics_step_matches_oracle(precision, chunk, after):
+    """One step of the 64^3 workload's physics on the 64x4x4 slab (~2.4 orbit
+    pieces, both scatter chunk lengths), compared with the oracle's step from
+    the same state: after 1 step, and after 14 steps when the grid-scale mode
+    carries about 1% of the energy.  FP64 element by element at 1e-12; the
+    mixed form from its own (storage-exact) state by mixed_storage."""
+    wl = W.two_stream("c4", mesh=(64, 4, 4))
+    x, v = (to_storage(wl, wl.x, wl.v) if precision == "mixed" else (wl.x, wl.v))
+    g = E.Sim(cfg_of(wl, precision=precision, scatter_chunk=chunk), wl.np)
+    g.init_particles(x, v, wl.q, wl.m, wl.n0)
+    g.set_profiling(2)
+    for _ in range(after):
+        g.picard_step()
+    p = g.get_profile()
+    pieces = p["pieces"] / (wl.np * p["gather_push"]["launches"])
+    s1 = g.get_state()
+    e1 = g.energy_diagnostics()
+    log(f"[c4 slab {precision} chunk {chunk}] after {after} steps: W/E "
+        f"{e1['W'] / e1['E_total']:.2e}, pieces per orbit {pieces:.3f}")
+    assert 2.2 < pieces < 2.9 and p["scatter_chunk"] == chunk
+    o = O.OracleSim(O.make_cfg(**{**wl.cfg_kwargs(), "tol": 0.0, "pmax": 3}), wl.np)
+    o.init_particles(s1["x"], s1["v"], wl.q, wl.m, wl.n0)
+    o.set_state(s1["x"], s1["v"], s1["vprev"], None, s1["fields"], wl.q, wl.m)
+    o.rebuild_P()
+    g2 = E.Sim(cfg_of(wl, precision=precision, tol=0.0, pmax=3, scatter_chunk=chunk), wl.np)
+    g2.init_particles(s1["x"], s1["v"], wl.q, wl.m, wl.n0)
+    g2.set_state(s1["x"], s1["v"], s1["vprev"], s1["fields"], wl.q, wl.m)
+    ig, io = g2.picard_step(), o.step()
+    assert ig["iters"] == io["iters"] == 4
+    sg, so = g2.get_state(), o.get_state()
+    if precision == "mixed":
+        check_mixed_step(wl, s1["x"], s1["v"], sg, so, g2.get_current(), o.current(), log,
+                         f"c4 slab mixed chunk {chunk} after {after}", pieces=6)
+        return
+    vs = np.abs(so["v"]).max()
+    dv = np.abs(sg["v"] - so["v"]).max() / vs
+    d = sg["x"] - so["x"]
+    for a in range(3):
+        d[a] -= wl.L[a] * np.round(d[a] / wl.L[a])
+    dx = np.abs(d).max() / (vs * wl.dt)
+    Jg, Jo = g2.get_current(), o.current()
+    Js = abs(wl.q) * np.abs(so["v"]).max(axis=0).sum() / np.prod(wl.L)
+    dJ = np.abs(Jg - Jo).max() / Js
+    msgs = []
+    for nm, ks, scale in field_scales(wl, so["fields"], so["v"]):
+        err = np.abs(sg["fields"][ks] - so["fields"][ks]).max() / scale
+        msgs.append(f"{nm} {err:.1e}")
+        assert err <= 1e-12, (nm, err)
+    log(f"[c4 slab fp64 chunk {chunk} after {after}] max|dv|/|v| {dv:.2e}, max|dx|/(|v| dt) "
+        f"{dx:.2e}, max|dJ|/J_s {dJ:.2e}, fields " + ", ".join(msgs))
+    assert dv <= 1e-12 and dx <= 1e-12 and dJ <= 1e-12
+
+
+def test_c1_run_as_specified_against_the_oracle():
+    wl = W.two_stream("c1")
+    g = E.Sim(cfg_of(wl, diagnostics=True), wl.np)
+    g.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
+    o = O.OracleSim(O.make_cfg(**wl.cfg_kwargs()), wl.np)
+    o.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
+    E0 = o.energy()["E_total"]
+    dE = 0.0
+    same = 0
+    for k in range(1, wl.steps + 1):
+        ig, io = g.picard_step(), o.step()
+        assert ig["converged"] and io["converged"], (k, ig, io)
+        assert abs(ig["iters"] - io["iters"]) <= 1
+        same += ig["iters"] == io["iters"]
+        eg, eo = g.energy_diagnostics(), o.energy()
+        for key in ("K", "W", "E_total"):
+            dE = max(dE, abs(eg[key] - eo[key]) / E0)
+        assert abs(eg["R_total"]) <= 1e-14 * E0 and abs(eg["E_total"] - E0) <= 1e-12 * E0
+        assert eg["RA_max"] < 1e-15 and eg["gauge_max"] < 1e-13 and eg["gauss_max"] < 1e-10
+    sg, so = g.get_state(), o.get_state()
+    dv = np.abs(sg["v"] - so["v"]).max() / np.abs(so["v"]).max()
+    df = {nm: np.abs(sg["fields"][ks] - so["fields"][ks]).max() / scale
+          for nm, ks, scale in field_scales(wl, so["fields"], so["v"])}
+    log(f"c1: {wl.steps} steps, passes equal on {same} steps; max energy difference "
+        f"{dE:.2e} E0; final max|dv|/|v| {dv:.2e}, fields "
+        + ", ".join(f"{k} {v:.1e}" for k, v in df.items()))
+    # 100 steps of an unstable trajectory (growth ~e^{0.35 t}, t = 10): the
+    # step-by-step rounding differences grow by ~30 and stay far below 1e-12
+    assert dE <= 1e-13
+    assert dv <= 1e-12 and max(df.values()) <= 1e-12

@@ -267,6 +267,46 @@ def test_static_1d_field_gives_discrete_gradient_quotient(r):
 
 
 # --------------------------------------------------------------------------
+# the unsplit rule by value (Sec. 4.7, the comparison runs of Sec. 5.4)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("r,nq", [(1, 2), (1, 16), (2, 4), (2, 7), (3, 5), (3, 16)])
+def test_unsplit_rule_matches_bruteforce(r, nq):
+    """Without splitting, Sbar, D, the gathers, the end-point interpolants and
+    sum_g Sbar equal one numpy Gauss-Legendre rule over [0, 1] whose points
+    each use the true B-spline at their own position (the stencil of their
+    own cell).  Orbits of up to 1.8 cells cross several knots, so a rule that
+    keeps one stencil for all points, or drops the (1 - s), s weights of
+    A^n, A^{n+1}, fails here."""
+    S = sim(r, split=False, analytic=False, nq=nq)
+    rng = np.random.default_rng(70 + 3 * r + nq)
+    A0 = W.random_fields(N, 3, seed=71)
+    A1 = A0 + 0.4 * W.random_fields(N, 3, seed=72)
+    gphi = W.random_fields(N, 3, seed=73)
+    U = W.random_fields(N, 3, seed=74)
+    x0s, ds = rand_orbits(rng, 8, scale_cells=1.8)
+    out = S.orbit_gather(x0s, ds, gphi, U, A0, A1)
+    dV = H[0] * H[1] * H[2]
+    crossed = 0
+    for i, (x0, d) in enumerate(zip(x0s, ds)):
+        crossed += len(B.knot_crossings(r, x0, d, N, L)) > 0
+        D = B.unsplit_D(r, x0, d, N, L, A0, A1, nq)
+        np.testing.assert_allclose(out["D"][i], D, rtol=0, atol=1e-14 * np.abs(D).max())
+        np.testing.assert_allclose(out["gphibar"][i], B.unsplit_gather(r, x0, d, N, L, gphi, nq),
+                                   rtol=0, atol=1e-14)
+        np.testing.assert_allclose(out["Ubar"][i], B.unsplit_gather(r, x0, d, N, L, U, nq),
+                                   rtol=0, atol=1e-14)
+        np.testing.assert_allclose(out["A1_end"][i], B.point_values(r, x0 + d, N, L, A1), atol=1e-14)
+        np.testing.assert_allclose(out["A0_start"][i], B.point_values(r, x0, N, L, A0), atol=1e-14)
+        assert abs(out["pou"][i] - 1.0) < 1e-14  # the points' own shapes each sum to 1
+        J = S.orbit_deposit(x0[None], d[None], np.array([[1.0, 0.0, 0.0]]))
+        want = np.zeros(N)
+        for g, v in B.unsplit_sbar(r, x0, d, N, L, nq).items():
+            want[g] += v
+        np.testing.assert_allclose(J[0] * dV, want, rtol=0, atol=1e-15)
+    assert crossed >= 6  # most orbits cross at least one knot
+
+
+# --------------------------------------------------------------------------
 # split versus unsplit quadrature (Sec. 4.7, Tables 1-2 trend)
 # --------------------------------------------------------------------------
 def one_d_residual(r, crossing, split):
