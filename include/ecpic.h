@@ -197,9 +197,26 @@ ecpic_status ecpic_get_state(ecpic_sim* sim, double* x, double* v, double* vprev
 /* Replace the state from host buffers (same layout as ecpic_get_state; any may
    be NULL to keep the current value).  m > 0: every particle gets charge q and
    mass m (one species); m = 0: every particle keeps its species (q ignored;
-   ECPIC_ESTATE before the first initialisation). */
+   ECPIC_ESTATE before the first initialisation).  The fields pass through
+   real space, so a state read and written back differs from the original at
+   rounding level.  The balance terms of the last step (R_*, JE_mesh,
+   work_particle, RA_*, pou_max) are cleared; the step counter, which sets the
+   sort schedule, is kept. */
 ecpic_status ecpic_set_state(ecpic_sim* sim, const double* x, const double* v,
                              const double* vprev, const double* fields, double q, double m);
+
+/* Checkpoint and restart: a byte-exact copy of the simulation's state (the
+   caller's state buffer, the live arrangement of its particle stores, the
+   step counter and energy bookkeeping) in a host buffer of
+   ecpic_checkpoint_bytes() bytes, owned by the caller.  A simulation created
+   with the same configuration and particle count (and this library version)
+   and restored from it continues exactly as the saved one would: bitwise in
+   the mixed form, whose current is an exact integer sum, and up to the order
+   of the FP64 atomic additions in the FP64 form.  Restore: ECPIC_EINVAL for a
+   buffer that is not a checkpoint of this configuration and version. */
+ecpic_status ecpic_checkpoint_bytes(ecpic_sim* sim, size_t* bytes);
+ecpic_status ecpic_checkpoint_save(ecpic_sim* sim, void* host_dst);
+ecpic_status ecpic_checkpoint_restore(ecpic_sim* sim, const void* host_src);
 
 /* Orbit current J^{n+1/2} (3*ncell) of the last accepted step, to host. */
 ecpic_status ecpic_get_current(ecpic_sim* sim, double* J);

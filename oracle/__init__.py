@@ -27,10 +27,16 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ecpic_oracle.c")
-_LIB = os.path.join(_HERE, "libecpic_oracle.so")
+# ECPIC_ORACLE_SANITIZE=1: a separate build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (load it with libasan preloaded into python)
+_SANITIZE = os.environ.get("ECPIC_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libecpic_oracle_san.so" if _SANITIZE else "libecpic_oracle.so")
 
-GCC_CMD = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-Wall", "-shared", "-fPIC",
-           "-ffp-contract=off", "-fno-fast-math", _SRC, "-o", _LIB, "-lm"]
+GCC_CMD = (["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-Wall", "-shared", "-fPIC",
+            "-ffp-contract=off", "-fno-fast-math"]
+           + (["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=all"] if _SANITIZE else [])
+           + [_SRC, "-o", _LIB, "-lm"])
 
 
 def build() -> str:

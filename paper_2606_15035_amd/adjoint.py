@@ -15,6 +15,7 @@ between the library and torch tensors.
 """
 from __future__ import annotations
 
+import time
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -34,7 +35,9 @@ class Run:
     checkpoint_every: int = 10
     adjoint_tol: float = 1e-13
     adjoint_max_iters: int = 100
-    log: list = field(default_factory=list)  # per step: ("fwd"|"adj", step, iterations)
+    # per step: ("fwd", step, Picard passes) or ("adj", step, transposed
+    # iterations, seconds of the ecpic_adjoint_step call)
+    log: list = field(default_factory=list)
 
     def sim(self) -> E.Sim:
         if getattr(self, "_sim", None) is None:
@@ -87,11 +90,12 @@ def _backward(run: Run, checkpoints, lF):
         for k in range(e - 1, s - 1, -1):
             xk, vk, Fk = states[k - s]
             w = states[k - s + 1][1]
-            lx, lv, lF, info = sim.adjoint_step(
-                torch.as_tensor(xk, device=dev), torch.as_tensor(vk, device=dev),
-                torch.as_tensor(w, device=dev), torch.as_tensor(Fk, device=dev),
-                lx, lv, lF, tol=run.adjoint_tol, max_iters=run.adjoint_max_iters)
-            run.log.append(("adj", k, info["iters"]))
+            args = [torch.as_tensor(a, device=dev) for a in (xk, vk, w, Fk)]
+            torch.cuda.synchronize(dev)
+            t0 = time.perf_counter()  # the call returns after its stream is synchronised
+            lx, lv, lF, info = sim.adjoint_step(*args, lx, lv, lF, tol=run.adjoint_tol,
+                                                max_iters=run.adjoint_max_iters)
+            run.log.append(("adj", k, info["iters"], time.perf_counter() - t0))
             if not info["converged"]:
                 raise RuntimeError(f"adjoint of step {k} did not converge ({info['err']:.2e})")
     return lv

@@ -41,9 +41,38 @@ struct Axis2 {
   }
 };
 
+// weight and first and second derivative (physical units) of stencil node k
+// (0..2) of degree 2 along one axis at cell coordinate t
+__device__ __forceinline__ void axis_node(int k, double t, double invH, double& w, double& dw,
+                                          double& ddw) {
+  Spline<2>::wk(k, t, w, dw);
+  dw *= invH;
+  ddw = (k == 1 ? -2.0 : 1.0) * invH * invH;
+}
+
+// Particle i of the thread.  With SPREAD the 64 lanes of a wavefront take
+// particles np / 64 apart (wavefront w, lane l: particle l * ceil(np / 64) + w),
+// so that in a cell-ordered set they sit in different cells and their
+// atomics to the mesh adjoints rarely meet on one address.
+// Threads beyond the 64 ceil(np / 64) that the spread covers (the last block's
+// padding) get np, i.e. no particle.
+template <bool SPREAD>
+__device__ __forceinline__ int64_t adjoint_particle(int64_t np) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if constexpr (!SPREAD) return t;
+  const int64_t stride = (np + kWave - 1) / kWave;
+  if (t / kWave >= stride) return np;
+  return (t % kWave) * stride + t / kWave;
+}
+
+// Node by node: each stencil node's mesh values are read once per piece and
+// its quadrature sums Sbar = sum_q w_q S, T0 = sum_q w_q (1 - s_q) eta.grad S,
+// T1 = sum_q w_q s_q eta.grad S give its nine mesh-adjoint contributions of
+// the piece with one atomic each (dL/dgphi_l = -dt eta_l Sbar,
+// dL/dA0_l = dt vbar_l T0, dL/dA1_l = dt vbar_l T1).
 template <bool ETA, bool MU>
 __global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = adjoint_particle<ETA>(P.np);
   if (i >= P.np) return;
   const Grid& G = P.G;
   const int64_t np = P.np, nc = G.ncell;
@@ -63,63 +92,81 @@ __global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) 
     int first[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) first[a] = to_int_clamped(base[a]) + Spline<2>::first_off;
+    double sq[4], wq[4], tq[4][3];  // points, weights, stencil coordinates
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const double s = s0 + 0.5 * h * (1.0 + Gauss<4>::x(q));
-      const double wt = 0.5 * h * Gauss<4>::w(q);
-      Axis2 X, Y, Z;
-      X.at((x0[0] + s * d[0]) * G.invH[0] - base[0], G.invH[0]);
-      Y.at((x0[1] + s * d[1]) * G.invH[1] - base[1], G.invH[1]);
-      Z.at((x0[2] + s * d[2]) * G.invH[2] - base[2], G.invH[2]);
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-          for (int c = 0; c < 3; ++c) {
-            const int64_t g = node_index(G, first[0] + a, first[1] + b, first[2] + c);
-            const double S = X.w[a] * Y.w[b] * Z.w[c];
-            const double dS[3] = {X.dw[a] * Y.w[b] * Z.w[c], X.w[a] * Y.dw[b] * Z.w[c],
-                                  X.w[a] * Y.w[b] * Z.dw[c]};
-            if constexpr (ETA) {
-              const double Hs[3][3] = {
-                  {X.ddw[a] * Y.w[b] * Z.w[c], X.dw[a] * Y.dw[b] * Z.w[c], X.dw[a] * Y.w[b] * Z.dw[c]},
-                  {X.dw[a] * Y.dw[b] * Z.w[c], X.w[a] * Y.ddw[b] * Z.w[c], X.w[a] * Y.dw[b] * Z.dw[c]},
-                  {X.dw[a] * Y.w[b] * Z.dw[c], X.w[a] * Y.dw[b] * Z.dw[c], X.w[a] * Y.w[b] * Z.ddw[c]}};
-              double Ag[3], bg = 0.0, edS = 0.0, eg = 0.0;
+      sq[q] = s0 + 0.5 * h * (1.0 + Gauss<4>::x(q));
+      wq[q] = 0.5 * h * Gauss<4>::w(q);
 #pragma unroll
-              for (int l = 0; l < 3; ++l) {
-                Ag[l] = (1.0 - s) * P.A0[l * nc + g] + s * P.A1[l * nc + g];
-                bg += vb[l] * Ag[l];
-                edS += eta[l] * dS[l];
-                eg += eta[l] * P.gphi[l * nc + g];
-              }
-              const double c1 = P.dt * wt;
+      for (int a = 0; a < 3; ++a) tq[q][a] = (x0[a] + sq[q] * d[a]) * G.invH[a] - base[a];
+    }
+#pragma unroll 1
+    for (int n = 0; n < 27; ++n) {
+      const int a = n / 9, b = (n / 3) % 3, c = n % 3;
+      const int64_t g = node_index(G, first[0] + a, first[1] + b, first[2] + c);
+      double A0g[3] = {0.0, 0.0, 0.0}, A1g[3] = {0.0, 0.0, 0.0}, mug[3] = {0.0, 0.0, 0.0};
+      double b0 = 0.0, b1 = 0.0, eg = 0.0, vm = 0.0;
 #pragma unroll
-              for (int kk = 0; kk < 3; ++kk) {
-                const double eH = eta[0] * Hs[0][kk] + eta[1] * Hs[1][kk] + eta[2] * Hs[2][kk];
-                lx[kk] += c1 * (bg * eH - eg * dS[kk]);        // (D A)^T vbar, -gphibar
-                ld[kk] += c1 * s * (bg * eH - eg * dS[kk]);
-                lvb[kk] += c1 * Ag[kk] * edS;
-              }
+      for (int l = 0; l < 3; ++l) {
+        if constexpr (ETA) {
+          A0g[l] = P.A0[l * nc + g];
+          A1g[l] = P.A1[l * nc + g];
+          b0 += vb[l] * A0g[l];
+          b1 += vb[l] * A1g[l];
+          eg += eta[l] * P.gphi[l * nc + g];
+        }
+        if constexpr (MU) {
+          mug[l] = P.mu[l * nc + g];
+          vm += vb[l] * mug[l];
+        }
+      }
+      double Sbar = 0.0, T0 = 0.0, T1 = 0.0;
 #pragma unroll
-              for (int l = 0; l < 3; ++l) {
-                unsafeAtomicAdd(P.lgphi + l * nc + g, -c1 * eta[l] * S);
-                unsafeAtomicAdd(P.lA0 + l * nc + g, c1 * (1.0 - s) * vb[l] * edS);
-                unsafeAtomicAdd(P.lA1 + l * nc + g, c1 * s * vb[l] * edS);
-              }
-            }
-            if constexpr (MU) {
-              double vm = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        double wx, dwx, ddwx, wy, dwy, ddwy, wz, dwz, ddwz;
+        axis_node(a, tq[q][0], G.invH[0], wx, dwx, ddwx);
+        axis_node(b, tq[q][1], G.invH[1], wy, dwy, ddwy);
+        axis_node(c, tq[q][2], G.invH[2], wz, dwz, ddwz);
+        const double s = sq[q], wt = wq[q];
+        const double S = wx * wy * wz;
+        const double dS[3] = {dwx * wy * wz, wx * dwy * wz, wx * wy * dwz};
+        if constexpr (ETA) {
+          const double Hs[3][3] = {{ddwx * wy * wz, dwx * dwy * wz, dwx * wy * dwz},
+                                   {dwx * dwy * wz, wx * ddwy * wz, wx * dwy * dwz},
+                                   {dwx * wy * dwz, wx * dwy * dwz, wx * wy * ddwz}};
+          const double bg = (1.0 - s) * b0 + s * b1;  // vbar . A_g(s)
+          const double edS = eta[0] * dS[0] + eta[1] * dS[1] + eta[2] * dS[2];
+          const double c1 = P.dt * wt;
 #pragma unroll
-              for (int l = 0; l < 3; ++l) {
-                const double m = P.mu[l * nc + g];
-                lvb[l] += wt * m * S;
-                vm += vb[l] * m;
-              }
-#pragma unroll
-              for (int kk = 0; kk < 3; ++kk) {
-                lx[kk] += wt * vm * dS[kk];
-                ld[kk] += wt * s * vm * dS[kk];
-              }
-            }
+          for (int kk = 0; kk < 3; ++kk) {
+            const double eH = eta[0] * Hs[0][kk] + eta[1] * Hs[1][kk] + eta[2] * Hs[2][kk];
+            const double f = c1 * (bg * eH - eg * dS[kk]);  // (D A)^T vbar, -gphibar
+            lx[kk] += f;
+            ld[kk] += s * f;
+            lvb[kk] += c1 * ((1.0 - s) * A0g[kk] + s * A1g[kk]) * edS;
           }
+          Sbar += wt * S;
+          T0 += wt * (1.0 - s) * edS;
+          T1 += wt * s * edS;
+        }
+        if constexpr (MU) {
+#pragma unroll
+          for (int l = 0; l < 3; ++l) lvb[l] += wt * mug[l] * S;
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk) {
+            lx[kk] += wt * vm * dS[kk];
+            ld[kk] += wt * s * vm * dS[kk];
+          }
+        }
+      }
+      if constexpr (ETA) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          unsafeAtomicAdd(P.lgphi + l * nc + g, -P.dt * eta[l] * Sbar);
+          unsafeAtomicAdd(P.lA0 + l * nc + g, P.dt * vb[l] * T0);
+          unsafeAtomicAdd(P.lA1 + l * nc + g, P.dt * vb[l] * T1);
+        }
+      }
     }
   });
   if constexpr (ETA) {  // + A0_h(x0) - A1_h(x0 + d), end point wrapped
@@ -232,10 +279,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_out(int64_t n3, const double
 
 void launch_particle_adjoint(hipStream_t s, const AdjParticleArgs& P, bool eta, bool mu) {
   if (P.np <= 0) return;
+  // the spread lanes of the scattering kernels cover 64 ceil(np / 64) threads
+  const unsigned spread = blocks_for(kWave * ((P.np + kWave - 1) / kWave));
   if (eta && mu)
-    k_particle_adjoint<true, true><<<blocks_for(P.np), kBlock, 0, s>>>(P);
+    k_particle_adjoint<true, true><<<spread, kBlock, 0, s>>>(P);
   else if (eta)
-    k_particle_adjoint<true, false><<<blocks_for(P.np), kBlock, 0, s>>>(P);
+    k_particle_adjoint<true, false><<<spread, kBlock, 0, s>>>(P);
   else if (mu)
     k_particle_adjoint<false, true><<<blocks_for(P.np), kBlock, 0, s>>>(P);
 }

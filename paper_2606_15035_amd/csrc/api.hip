@@ -199,6 +199,8 @@ struct ecpic_sim {
   hipStream_t stream;
   int device = -1;                 // the device current at ecpic_create
   void* static_scratch = nullptr;  // address of `scratch` on that device
+  char* state_base = nullptr;      // the caller's state buffer and its carved size
+  size_t state_size = 0;
   double q = -1.0, m = 1.0;  // species 0
   int nsp = 1;               // species; > 1: the stores hold one byte per particle
   double qs[kMaxSpecies] = {-1.0}, ms[kMaxSpecies] = {1.0};
@@ -496,6 +498,8 @@ ecpic_status ecpic_create(const ecpic_config* cfg, int64_t n_particles, void* st
   S->fix_scale = cfg->fixed_point_scale > 0.0 ? cfg->fixed_point_scale : 0x1p40;
   S->rule = gauss_rule01(quad_rule_points(cfg));
   carve(S, static_cast<char*>(state_dev), static_cast<char*>(workspace_dev), nullptr, nullptr);
+  S->state_base = static_cast<char*>(state_dev);
+  S->state_size = need_s;
   if (hipHostMalloc(reinterpret_cast<void**>(&S->host), sizeof(double) * S_NSLOTS,
                     hipHostMallocDefault) != hipSuccess) {
     delete S;
@@ -1007,6 +1011,11 @@ ecpic_status ecpic_set_state(ecpic_sim* S, const double* x, const double* v, con
   }
   HIPCHK(hipGetLastError());
   S->initialized = true;
+  // the balance terms of the last step no longer describe the state; the step
+  // counter (and with it the sort schedule) is kept
+  const int64_t step = S->en.step;
+  S->en = ecpic_energy{};
+  S->en.step = step;
   ecpic_status st = update_level_energies(S);
   if (st != ECPIC_OK) return st;
   return ECPIC_OK;
@@ -1064,6 +1073,134 @@ ecpic_status ecpic_get_profile(ecpic_sim* S, ecpic_profile* out) {
   if (!S || !out) return fail(ECPIC_EINVAL, "null argument");
   *out = S->prof;
   out->scatter_chunk = S->pp().chunk;
+  return ECPIC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Header of a checkpoint: what identifies the simulation, where the live
+// buffers of the state sit (the sort swaps the two particle stores and id
+// arrays), and the host-side bookkeeping; the state buffer follows.
+struct CheckpointHeader {
+  uint64_t magic;
+  char version[32];
+  ecpic_config cfg;
+  int64_t np;
+  size_t state_size;
+  int64_t off_f64[2][4];  // x, v, vp, sp of each FP64 store (byte offsets, -1 = none)
+  int64_t off_mx[2][5];   // cell, off, v, vp, sp of each mixed store
+  int64_t off_id, off_id2;
+  int32_t cur, jlast, jclean, chunk, nsp, initialized;
+  double q, m, qs[kMaxSpecies], ms[kMaxSpecies], K, W;
+  ecpic_energy en;
+};
+constexpr uint64_t kCheckpointMagic = 0x3143505443504345ull;  // "ECPCTPC1"
+constexpr size_t kCheckpointHeaderBytes = (sizeof(CheckpointHeader) + 255) & ~size_t(255);
+
+int64_t offset_in(const ecpic_sim* S, const void* p) {
+  return p ? (int64_t)(static_cast<const char*>(p) - S->state_base) : -1;
+}
+template <class T>
+T* at_offset(ecpic_sim* S, int64_t off) {
+  return off < 0 ? nullptr : reinterpret_cast<T*>(S->state_base + off);
+}
+
+}  // namespace
+
+extern "C" {
+
+ecpic_status ecpic_checkpoint_bytes(ecpic_sim* S, size_t* bytes) {
+  if (!S || !bytes) return fail(ECPIC_EINVAL, "null argument");
+  *bytes = kCheckpointHeaderBytes + S->state_size;
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_checkpoint_save(ecpic_sim* S, void* dst) {
+  if (!S || !dst) return fail(ECPIC_EINVAL, "null argument");
+  if (!S->initialized) return fail(ECPIC_ESTATE, "checkpoint before init_particles/set_state");
+  CheckpointHeader h{};
+  h.magic = kCheckpointMagic;
+  std::snprintf(h.version, sizeof(h.version), "%s", ecpic_version());
+  h.cfg = S->cfg;
+  h.np = S->np;
+  h.state_size = S->state_size;
+  for (int k = 0; k < 2; ++k) {
+    const Fp64Store& f = S->f64[k];
+    const MixedStore& m = S->mx[k];
+    const void* fp[4] = {f.x, f.v, f.vp, f.sp};
+    const void* mp[5] = {m.cell, m.off, m.v, m.vp, m.sp};
+    for (int j = 0; j < 4; ++j) h.off_f64[k][j] = offset_in(S, fp[j]);
+    for (int j = 0; j < 5; ++j) h.off_mx[k][j] = offset_in(S, mp[j]);
+  }
+  h.off_id = offset_in(S, S->id);
+  h.off_id2 = offset_in(S, S->id2);
+  h.cur = S->cur;
+  h.jlast = S->jlast;
+  h.jclean = S->jclean ? 1 : 0;
+  h.chunk = S->chunk;
+  h.nsp = S->nsp;
+  h.initialized = 1;
+  h.q = S->q;
+  h.m = S->m;
+  for (int k = 0; k < kMaxSpecies; ++k) {
+    h.qs[k] = S->qs[k];
+    h.ms[k] = S->ms[k];
+  }
+  h.K = S->K;
+  h.W = S->W;
+  h.en = S->en;
+  std::memcpy(dst, &h, sizeof(h));
+  HIPCHK(hipMemcpyAsync(static_cast<char*>(dst) + kCheckpointHeaderBytes, S->state_base,
+                        S->state_size, hipMemcpyDeviceToHost, S->stream));
+  HIPCHK(hipStreamSynchronize(S->stream));
+  return ECPIC_OK;
+}
+
+ecpic_status ecpic_checkpoint_restore(ecpic_sim* S, const void* src) {
+  if (!S || !src) return fail(ECPIC_EINVAL, "null argument");
+  CheckpointHeader h;
+  std::memcpy(&h, src, sizeof(h));
+  if (h.magic != kCheckpointMagic) return fail(ECPIC_EINVAL, "not an ecpic checkpoint");
+  if (std::strncmp(h.version, ecpic_version(), sizeof(h.version)) != 0)
+    return fail(ECPIC_EINVAL, "checkpoint of library %.32s, this is %s", h.version, ecpic_version());
+  if (std::memcmp(&h.cfg, &S->cfg, sizeof(ecpic_config)) != 0 || h.np != S->np ||
+      h.state_size != S->state_size)
+    return fail(ECPIC_EINVAL, "checkpoint of another configuration or particle count");
+  HIPCHK(hipMemcpyAsync(S->state_base, static_cast<const char*>(src) + kCheckpointHeaderBytes,
+                        S->state_size, hipMemcpyHostToDevice, S->stream));
+  HIPCHK(hipStreamSynchronize(S->stream));
+  for (int k = 0; k < 2; ++k) {
+    Fp64Store& f = S->f64[k];
+    MixedStore& m = S->mx[k];
+    f.x = at_offset<double>(S, h.off_f64[k][0]);
+    f.v = at_offset<double>(S, h.off_f64[k][1]);
+    f.vp = at_offset<double>(S, h.off_f64[k][2]);
+    f.sp = at_offset<uint8_t>(S, h.off_f64[k][3]);
+    m.cell = at_offset<int>(S, h.off_mx[k][0]);
+    m.off = at_offset<float>(S, h.off_mx[k][1]);
+    m.v = at_offset<float>(S, h.off_mx[k][2]);
+    m.vp = at_offset<float>(S, h.off_mx[k][3]);
+    m.sp = at_offset<uint8_t>(S, h.off_mx[k][4]);
+  }
+  S->id = at_offset<int>(S, h.off_id);
+  S->id2 = at_offset<int>(S, h.off_id2);
+  S->cur = h.cur;
+  S->jlast = h.jlast;
+  S->jclean = h.jclean != 0;
+  S->chunk = h.chunk;
+  S->nsp = h.nsp;
+  S->q = h.q;
+  S->m = h.m;
+  for (int k = 0; k < kMaxSpecies; ++k) {
+    S->qs[k] = h.qs[k];
+    S->ms[k] = h.ms[k];
+  }
+  S->K = h.K;
+  S->W = h.W;
+  S->en = h.en;
+  S->initialized = true;
   return ECPIC_OK;
 }
 
@@ -1262,6 +1399,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.15"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.16"; }
 
 }  // extern "C"

@@ -107,6 +107,9 @@ def lib():
                                          C.c_double, C.c_int32, C.POINTER(AdjointInfo)]
         L.ecpic_adjoint_step_noalloc.argtypes = [P, D, D, D, D, D, D, D, D, D, D, C.c_double,
                                                  C.c_int32, C.POINTER(AdjointInfo)]
+        L.ecpic_checkpoint_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.ecpic_checkpoint_save.argtypes = [P, P]
+        L.ecpic_checkpoint_restore.argtypes = [P, P]
         L.ecpic_field_energy_grad.argtypes = [P, D]
         L.ecpic_last_error.restype = C.c_char_p
         L.ecpic_version.restype = C.c_char_p
@@ -117,7 +120,8 @@ def lib():
                      "ecpic_orbit_gather", "ecpic_orbit_deposit", "ecpic_set_profiling",
                      "ecpic_get_profile", "ecpic_adjoint_workspace_bytes",
                      "ecpic_adjoint_step", "ecpic_adjoint_step_noalloc",
-                     "ecpic_field_energy_grad"):
+                     "ecpic_checkpoint_bytes", "ecpic_checkpoint_save",
+                     "ecpic_checkpoint_restore", "ecpic_field_energy_grad"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -275,6 +279,19 @@ class Sim:
             q, m = float(q), float(m)
             self.q, self.m = q, m
         _check(lib().ecpic_set_state(self._h, *[_hp(a) for a in args], q, m))
+
+    def checkpoint(self) -> np.ndarray:
+        """The simulation's state as a host byte array (ecpic_checkpoint_save)."""
+        nb = C.c_size_t()
+        _check(lib().ecpic_checkpoint_bytes(self._h, C.byref(nb)))
+        buf = np.empty(nb.value, dtype=np.uint8)
+        _check(lib().ecpic_checkpoint_save(self._h, buf.ctypes.data_as(C.c_void_p)))
+        return buf
+
+    def restore(self, buf: np.ndarray):
+        """Continue from a checkpoint of a simulation of the same configuration."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().ecpic_checkpoint_restore(self._h, buf.ctypes.data_as(C.c_void_p)))
 
     def set_profiling(self, level=1):
         """0 off, 1 (or True) every phase, 2 the gather phase only."""

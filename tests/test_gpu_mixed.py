@@ -112,11 +112,34 @@ def test_mixed_two_stream_energy_and_constraints():
     log(f"mixed: max|R_total|/E per step {step_g:.2e}, drift {drift_g:.2e}; "
         f"FP64 oracle: {step_o:.2e}, {drift_o:.2e}")
     # Storing the accepted v in FP32 changes K by sum_i m v_i dv_i with
-    # |dv_i| <= ulp32(v_i) / 2 <= 2^-24 |v_i|, i.e. by at most 2^-23 K: the
-    # bound per step (independent roundings would give ~2^-24 / sqrt(N_p);
-    # the two beams round alike, so the errors partly add up).
-    assert step_g <= 2.0 ** -23 and drift_g <= wl.steps * 2.0 ** -23
+    # |dv_i| <= ulp32(v_i) / 2 <= 2^-24 |v_i|, i.e. by at most 2^-23 K per
+    # step.  Independent roundings would give ~2^-24 / sqrt(N_p); the lattice
+    # beams' particles carry nearly equal velocities, so they round alike and
+    # the errors add up: measured 1.0e-8 per step and 5.1e-8 over the run.
+    # Pinned at three to four times those figures (the bound 2^-23 = 1.2e-7
+    # would let a real regression through).
+    assert step_g <= 3e-8 and drift_g <= 2e-7
     assert step_o < 1e-13
+
+
+def test_mixed_32cubed_energy_error_per_step():
+    """The 32^3 workload in the mixed form, 20 steps: |R_total| / E per step
+    (measured 1.7e-9: the FP32 rounding of the accepted velocities of the
+    lattice beams, which round alike) and the Gauss and gauge residuals."""
+    wl = W.two_stream("c2")
+    x, v = to_storage(wl, wl.x, wl.v)
+    g = E.Sim(mixed_cfg(wl), wl.np)
+    g.init_particles(x, v, wl.q, wl.m, wl.n0)
+    E0 = g.energy_diagnostics()["E_total"]
+    worst = 0.0
+    for _ in range(20):
+        assert g.picard_step()["converged"]
+        e = g.energy_diagnostics()
+        worst = max(worst, abs(e["R_total"]) / e["E_total"])
+        assert e["gauge_max"] < 1e-15 and e["gauss_max"] < 1e-14
+    drift = abs(e["E_total"] - E0) / E0
+    log(f"c2 mixed: max |R_total|/E per step {worst:.2e}, drift over 20 steps {drift:.2e}")
+    assert worst <= 5e-9 and drift <= 2e-8
 
 
 def test_contribution_beyond_the_fixed_point_range_is_an_error():
@@ -164,7 +187,8 @@ def test_full_size_64cubed_mixed_steps_keep_the_invariants():
             f"RA_max {e['RA_max']:.2e}, pou {e['pou_max']:.2e}, gauss {e['gauss_max']:.2e} "
             f"(rho {rho:.2e}), gauge {e['gauge_max']:.2e} (psi {psi:.2e}, A {A:.2e})")
         assert info["converged"]
-        assert abs(e["R_total"]) <= 2.0 ** -23 * e["E_total"]
+        # measured 7.4e-12 at most: the thermal spread decorrelates the roundings
+        assert abs(e["R_total"]) <= 5e-11 * e["E_total"]
         assert e["RA_max"] <= 1e-12 * A and e["pou_max"] < 1e-14
         # Theorem 1: the residuals are rounding of the spectral sums
         assert e["gauss_max"] <= 1e-11 * rho

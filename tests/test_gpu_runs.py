@@ -233,7 +233,9 @@ def test_c4_run_as_specified():
         f"{rate:.2f} omega_p; pieces per orbit {pieces_lin:.3f} (steps 1-5), scatter chunk "
         f"{p['scatter_chunk']}; "
         + ", ".join(f"max {k} {v:.2e}" for k, v in worst.items()))
-    assert worst["R_total"] <= 2.0 ** -23
+    # FP32 rounding of the accepted velocities, decorrelated by the thermal
+    # spread: measured 2.1e-11 at most (2^-23 = 1.2e-7 bounds it)
+    assert worst["R_total"] <= 1e-10
     assert worst["RA"] <= 1e-12 and worst["pou"] < 1e-14
     assert worst["gauss"] <= 1e-11 and worst["gauge"] <= 1e-11
     assert first_unconverged is None or first_unconverged[2] > 1e-2
