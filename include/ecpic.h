@@ -78,7 +78,15 @@ typedef struct {
                                    are polynomial, so every rule with at least that many
                                    points gives the same integrals and the smallest one is
                                    used; without splitting the given rule is used as is */
-  int32_t precision;            /* ecpic_precision */
+  int32_t precision;            /* ecpic_precision.  ECPIC_MIXED stores the particle state in
+                                   FP32 (the cell of x^n and the FP32 offset inside it, v^n,
+                                   v^{n-1}); iterates, orbit, field and energy arithmetic stay
+                                   FP64, and the current is summed as int64 quanta.  The
+                                   accepted velocity is rounded to one of its two neighbouring
+                                   FP32 values without bias (up with probability equal to its
+                                   distance from the lower one), from a counter-based generator
+                                   keyed by the particle's stored state and the step, so a run
+                                   is deterministic and independent of the particle order */
   double fixed_point_scale;     /* mixed precision: current quantum is 1/fixed_point_scale of
                                    the per-particle charge unit (0 = 2^40) */
   int32_t diagnostics;          /* 1: after each accepted step run the consistency sweep

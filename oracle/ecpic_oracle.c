@@ -42,7 +42,10 @@
  *   - the first-derivative Fourier symbol is zero on the Nyquist index and the
  *     Laplacian symbol is -|k~|^2 with that same k~ (keeps curl curl =
  *     grad div - Laplacian exact);
- *   - the stencil of a split segment is the one of its midpoint;
+ *   - the stencil of a split segment is the one of the knot interval it lies
+ *     in, found from x0's side of the knots along the motion and the knots
+ *     crossed so far (not from a rounded midpoint); along a still axis, the
+ *     interval holding x0, closed below;
  *   - the initial charge is also zeroed on every mode where k~ = 0;
  *   - v^{n-1} := v^0 at the first step;
  *   - Picard errors: e_v = max|v^{p+1}-v^p| / max|v^{p+1}|,
@@ -279,6 +282,44 @@ static int orbit_breakpoints(const grid* G, int r, const double x0[3], const dou
   return m;
 }
 
+/* Base node per axis of the stencil of the piece of x(s) = x0 + s d that
+   starts at the breakpoint s0 (Sec. 4.7): the piece lies inside one knot
+   interval per axis, and the stencil is that interval's.  Along a moving axis
+   the orbit enters, from x0 and in its direction of motion, the interval
+   behind the first knot xi_k = (k + off) H with xi_k ahead of x0 (decided by
+   comparing the two positions, so an orbit that starts on a knot takes the
+   side it moves to however short its step), then one interval further for
+   every knot of that axis crossed at a breakpoint (xi_k - x0) / d <= s0 (the
+   values orbit_breakpoints produces).  A still axis takes the interval holding
+   x0, closed below: the one behind the first knot above x0. */
+static void piece_bases(const grid* G, int r, const double x0[3], const double d[3], double s0,
+                        long base[3]) {
+  double off = (r == 2) ? 0.5 : 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double H = G->H[a];
+    long k = (long)floor(x0[a] / H - off);
+    long b;
+    int dir;
+    if (d[a] >= 0.0) { /* first knot above x0; the interval below it */
+      k -= 2;
+      while (((double)k + off) * H <= x0[a]) ++k;
+      b = spline_base(r, (double)k - 0.5 + off);
+      dir = 1;
+    } else { /* first knot below x0; the interval above it */
+      k += 3;
+      while (((double)k + off) * H >= x0[a]) --k;
+      b = spline_base(r, (double)k + 0.5 + off);
+      dir = -1;
+    }
+    for (long j = k; d[a] != 0.0; j += dir) {
+      double sk = (((double)j + off) * H - x0[a]) / d[a];
+      if (!(sk <= s0)) break;
+      b += dir;
+    }
+    base[a] = b;
+  }
+}
+
 /* Integrals of one orbit piece against its stencil (at most 4x4x4 nodes):
      Iw[nu]   = int S_nu(x(s)) ds
      X[j][nu] = int d_j S_nu(x(s)) ds
@@ -298,15 +339,14 @@ static int pidx(int w, int i, int j, int k) { return (i * w + j) * w + k; }
 
 /* App. A and App. B closed forms for degree 1 on the segment [s0, s1] */
 static void piece_r1_analytic(const grid* G, const double x0[3], const double d[3], double s0,
-                              double s1, piece* o) {
+                              double s1, const long pb[3], piece* o) {
   double h = s1 - s0;
-  double smid = 0.5 * (s0 + s1);
   double lam[3][2], mu[3][2];
   o->w = 2;
   o->s0 = s0;
   for (int a = 0; a < 3; ++a) {
     double H = G->H[a];
-    long base = spline_base(1, (x0[a] + smid * d[a]) / H);
+    long base = pb[a];
     o->first[a] = spline_first(1, base);
     double rm = (x0[a] + s0 * d[a]) / H - (double)base; /* r_{alpha,m} */
     double beta = d[a] / H;                             /* beta_alpha  */
@@ -392,7 +432,7 @@ static void piece_gauss(const grid* G, int r, const double x0[3], const double d
 }
 
 /* All pieces of one orbit.  With splitting: one piece per segment, its stencil
-   taken at the segment midpoint.  Without splitting: the n_q-point rule over
+   that of the knot interval the segment lies in (piece_bases).  Without splitting: the n_q-point rule over
    [0,1], each quadrature point with the stencil of its own cell (one piece per
    point, written relative to s = 0).  Returns the number of pieces (or -1). */
 static int orbit_pieces(const orc_sim* S, const double x0[3], const double d[3], piece* out,
@@ -418,14 +458,12 @@ static int orbit_pieces(const orc_sim* S, const double x0[3], const double d[3],
     double s0 = s[m], s1 = s[m + 1];
     if (!(s1 > s0)) continue; /* zero-length pieces contribute nothing */
     if (n >= cap) return -1;
-    if (r == 1 && S->c.analytic) {
-      piece_r1_analytic(G, x0, d, s0, s1, &out[n]);
-    } else {
-      double smid = 0.5 * (s0 + s1);
-      long base[3];
-      for (int a = 0; a < 3; ++a) base[a] = spline_base(r, (x0[a] + smid * d[a]) / G->H[a]);
+    long base[3];
+    piece_bases(G, r, x0, d, s0, base);
+    if (r == 1 && S->c.analytic)
+      piece_r1_analytic(G, x0, d, s0, s1, base, &out[n]);
+    else
       piece_gauss(G, r, x0, d, s0, s1, base, S->nq, S->gx, S->gw, &out[n]);
-    }
     ++n;
   }
   return n;
@@ -1498,12 +1536,10 @@ static int particle_adjoint(const orc_sim* S, const double x0[3], const double v
   for (int m = 0; m + 1 < nb; ++m) {
     double s0 = sb[m], s1 = sb[m + 1];
     if (!(s1 > s0)) continue;
-    double smid = 0.5 * (s0 + s1), h = s1 - s0;
+    double h = s1 - s0;
     long base[3], first[3];
-    for (int a = 0; a < 3; ++a) {
-      base[a] = spline_base(2, (x0[a] + smid * d[a]) / G->H[a]);
-      first[a] = spline_first(2, base[a]);
-    }
+    piece_bases(G, 2, x0, d, s0, base);
+    for (int a = 0; a < 3; ++a) first[a] = spline_first(2, base[a]);
     for (int iq = 0; iq < S->nq; ++iq) {
       double s = s0 + 0.5 * h * (1.0 + S->gx[iq]);
       double wt = 0.5 * h * S->gw[iq];

@@ -85,10 +85,8 @@ __global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) 
     if constexpr (ETA) eta[a] = P.qm * P.xi[a * np + i];
   }
   double lx[3] = {0.0, 0.0, 0.0}, ld[3] = {0.0, 0.0, 0.0}, lvb[3] = {0.0, 0.0, 0.0};
-  const bool ok = for_each_piece<2>(x0, d, G, [&](double s0, double s1) {
+  const bool ok = for_each_piece<2>(x0, d, G, [&](double s0, double s1, const double* base) {
     const double h = s1 - s0;
-    double base[3];
-    piece_base<2>(x0, d, 0.5 * (s0 + s1), G, base);
     int first[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) first[a] = to_int_clamped(base[a]) + Spline<2>::first_off;

@@ -826,7 +826,9 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   }
   if (prof) HIPCHK(hipEventRecord(S->ev[1], s));
   // accept: x^{n+1} = x^n + dt vbar^p, v^{n-1} <- v^n, v^n <- v^{n+1,p+1}; fields of pass p
-  on_store(S, [&](auto& st, auto&) { launch_finalize(s, P, st, S->vit, S->vnew, S->sc); });
+  on_store(S, [&](auto& st, auto&) {
+    launch_finalize(s, P, st, S->vit, S->vnew, (uint64_t)S->en.step, S->sc);
+  });
   if (S->np <= 0) {
     launch_reset_slots(s, S->sc, S_K, 2);
     launch_reset_slots(s, S->sc, S_WORK, 2);
@@ -1399,6 +1401,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.16"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.17"; }
 
 }  // extern "C"

@@ -180,9 +180,11 @@ void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
 template <class PS>
 void launch_sweep(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
                   const double* gbuf, const double* Uhalf, Scratch sc);
+// step: the step being accepted (part of the key of the store's rounding of
+// the accepted velocity)
 template <class PS>
 void launch_finalize(hipStream_t s, const StepParams& P, const PS& st, const double* vit,
-                     const double* vnew, Scratch sc);
+                     const double* vnew, uint64_t step, Scratch sc);
 template <class PS>
 void launch_kinetic(hipStream_t s, const StepParams& P, const PS& st, Scratch sc);
 // rho^0 of the point shapes: FP64 adds into out.J (ncell); mixed adds

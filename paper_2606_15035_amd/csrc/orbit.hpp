@@ -13,8 +13,8 @@
 // crossing sequences are each monotone in s, so they are merged on the fly
 // (no list is stored) and equal values from different axes collapse into one
 // breakpoint.  Every piece between breakpoints is integrated with an n_q-point
-// Gauss-Legendre rule against the polynomial pieces of the stencil found at
-// the piece midpoint; 2 n_q - 1 >= 3 r makes this exact (Sec. 4.7).
+// Gauss-Legendre rule against the polynomial pieces of the stencil of the
+// knot interval it lies in; 2 n_q - 1 >= 3 r makes this exact (Sec. 4.7).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -207,31 +207,57 @@ struct Gauss<5> {
 };
 
 // Streaming merge of the three per-axis knot-crossing sequences of an orbit.
-// Along axis a the crossings are equally spaced in s, H_a / |d_a| apart: the
-// first one is found from its knot, the later ones by adding that spacing
-// (a few ulp from the quotient of each knot; pieces only need their midpoint
-// inside the right cell, so the ends may move by that much).
+// Along axis a the crossings are equally spaced in s, H_a / |d_a| apart.  The
+// first one is the breakpoint of its knot as defined, (xi_k - x0) / d with
+// xi_k = (k + knot_off) H_a, taken over the knots ahead of x0 until it is
+// positive, so that an orbit starting exactly on a knot (a quiet start at cell
+// centres for r = 2) has no crossing there whatever the size of d; the later
+// ones follow by adding the spacing (a few ulp from the quotient of each knot;
+// pieces only need to be told apart by their knot intervals, so the ends may
+// move by that much).
+//
+// The stencil of a piece is the one of the knot interval its interior lies in
+// (Sec. 4.7).  Per axis that is the interval behind the first knot ahead, then
+// one interval further along the motion at every crossing of that axis, so
+// the choice never rests on a rounded midpoint: an orbit that leaves a knot
+// by less than the rounding of x0 still takes the interval on the side it
+// moves to.  An axis along which the orbit does not move takes the interval
+// holding x0, closed below.  (Keeping the next crossing and the spacing per axis costs
+// fewer registers in the gather kernel than recomputing each crossing from
+// its knot and 1 / d_a.)
 template <int R>
 struct Crossings {
   double sn[3];    // next crossing parameter per axis (>= 2 when exhausted)
-  double step[3];  // spacing of the crossings of that axis
+  double step[3];  // spacing of the crossings of that axis, with the sign of d_a
+  int base[3];     // base node of the current piece's stencil per axis
 
   __device__ __forceinline__ void init(const double* x0, const double* d, const Grid& G) {
+    // xi_k - x0 rounded once from the rounded xi_k: a contracted multiply-add
+    // would leave the rounding error of k H_a for an orbit that starts on a
+    // knot, and a random-signed sliver piece with it
+#pragma clang fp contract(off)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      sn[a] = 2.0;
-      step[a] = 2.0;
-      if (d[a] != 0.0) {
-        const double inv = 1.0 / d[a];
-        const double u0 = x0[a] * G.invH[a];
-        const double off = Spline<R>::knot_off;
-        const double knot = d[a] > 0.0 ? floor(u0 - off) - 1.0 + off : floor(u0 - off) + 1.0 + off;
-        const double st = G.H[a] * fabs(inv);
-        double s = (knot * G.H[a] - x0[a]) * inv;
-        for (int it = 0; it < 4 && !(s > 0.0); ++it) s += st;
-        sn[a] = (s > 0.0 && s < 1.0) ? s : 2.0;
-        step[a] = st;
+      // a still axis is searched as if it moved up: its interval is the one
+      // behind the first knot above x0 (closed below)
+      const bool moves = d[a] != 0.0;
+      const bool up = !(d[a] < 0.0);
+      const double inv = 1.0 / (moves ? d[a] : 1.0);
+      const double dir = up ? 1.0 : -1.0;
+      // the knot at or below the rounded u0; the first knot ahead of x0 along
+      // the motion is at most two knots further (x0 differs from u0 H_a by a
+      // few ulp), decided by the sign of (xi_k - x0) / d
+      double knot = floor(x0[a] * G.invH[a] - Spline<R>::knot_off) + Spline<R>::knot_off;
+      double s = (knot * G.H[a] - x0[a]) * inv;
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const bool behind = !(s > 0.0);
+        knot = behind ? knot + dir : knot;
+        s = behind ? (knot * G.H[a] - x0[a]) * inv : s;
       }
+      sn[a] = (moves && s < 1.0) ? s : 2.0;
+      step[a] = moves ? G.H[a] * inv : 2.0;
+      base[a] = to_int_clamped(knot + Spline<R>::base_off - (up ? 1.0 : 0.0));
     }
   }
 
@@ -239,22 +265,26 @@ struct Crossings {
     return fmin(fmin(sn[0], sn[1]), fmin(sn[2], 1.0));
   }
 
+  // advance every axis that crosses at s1 (selects, no branches: the piece
+  // loop is the inner loop of the particle kernels)
   __device__ __forceinline__ void consume(double s1) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if (sn[a] == s1) {
-        const double s = sn[a] + step[a];
-        sn[a] = (s > sn[a] && s < 1.0) ? s : 2.0;
-      }
+      const bool hit = sn[a] == s1;
+      const double s = sn[a] + fabs(step[a]);
+      const double adv = (s > sn[a] && s < 1.0) ? s : 2.0;
+      sn[a] = hit ? adv : sn[a];
+      base[a] += hit ? (step[a] > 0.0 ? 1 : -1) : 0;
     }
   }
 };
 
 constexpr int kMaxPieces = 64;
 
-// Calls f(s0, s1) for every piece [s0, s1] of positive length, in order.
-// Returns false if the orbit had more than kMaxPieces pieces (the rest is
-// skipped; the caller flags the particle).
+// Calls f(s0, s1, base) for every piece [s0, s1] of positive length, in
+// order, with the base node of the piece's stencil per axis.  Returns false
+// if the orbit had more than kMaxPieces pieces (the rest is skipped; the
+// caller flags the particle).
 template <int R, class F>
 __device__ __forceinline__ bool for_each_piece(const double* x0, const double* d, const Grid& G,
                                                F&& f) {
@@ -263,7 +293,10 @@ __device__ __forceinline__ bool for_each_piece(const double* x0, const double* d
   double s0 = 0.0;
   for (int k = 0; k < kMaxPieces; ++k) {
     const double s1 = c.next();
-    if (s1 > s0) f(s0, s1);
+    if (s1 > s0) {
+      const double base[3] = {(double)c.base[0], (double)c.base[1], (double)c.base[2]};
+      f(s0, s1, base);
+    }
     if (s1 >= 1.0) return true;
     c.consume(s1);
     s0 = s1;
@@ -271,7 +304,8 @@ __device__ __forceinline__ bool for_each_piece(const double* x0, const double* d
   return false;
 }
 
-// Base node of the stencil of a piece, from its midpoint.
+// Base node of the stencil of the point at s (the rule over the whole orbit
+// without splitting, where every point takes the stencil of its own cell).
 template <int R>
 __device__ __forceinline__ void piece_base(const double* x0, const double* d, double smid,
                                            const Grid& G, double* base) {

@@ -134,14 +134,11 @@ __device__ __forceinline__ void sbar_points(const Grid& G, const double* x0, con
   for (int a = 0; a < 3; ++a) first[a] = to_int_clamped(base[a]) + Spline<R>::first_off;
 }
 
-// the n_q-point rule of a piece [s0, s1] and the stencil of its midpoint
+// the n_q-point rule of a piece [s0, s1] (its stencil comes with the piece)
 template <int R>
-__device__ __forceinline__ void piece_rule(const Grid& G, const double* x0, const double* d,
-                                           double s0, double s1, double* base, double* sq,
-                                           double* wq) {
+__device__ __forceinline__ void piece_rule(double s0, double s1, double* sq, double* wq) {
   constexpr int NQ = Quad<R>::NQ;
   const double h = s1 - s0;
-  piece_base<R>(x0, d, 0.5 * (s0 + s1), G, base);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     sq[q] = s0 + 0.5 * h * (1.0 + Gauss<NQ>::x(q));
@@ -162,11 +159,11 @@ __device__ __forceinline__ void unsplit_point(const Grid& G, const QuadRule& rul
 
 template <int R>
 __device__ __forceinline__ void piece_sbar(const Grid& G, const double* x0, const double* d,
-                                           double s0, double s1, double (&Iw)[R + 1][R + 1][R + 1],
-                                           int* first) {
+                                           double s0, double s1, const double* base,
+                                           double (&Iw)[R + 1][R + 1][R + 1], int* first) {
   constexpr int NQ = Quad<R>::NQ;
-  double base[3], sq[NQ], wq[NQ];
-  piece_rule<R>(G, x0, d, s0, s1, base, sq, wq);
+  double sq[NQ], wq[NQ];
+  piece_rule<R>(s0, s1, sq, wq);
   sbar_points<R, NQ>(G, x0, d, base, sq, wq, Iw, first);
 }
 
@@ -174,12 +171,12 @@ __device__ __forceinline__ void piece_sbar(const Grid& G, const double* x0, cons
 // (eq. orbit-current, split form)
 template <int R>
 __device__ __forceinline__ void scatter_piece(const Grid& G, const double* x0, const double* d,
-                                              double s0, double s1, const double* c3,
-                                              double* __restrict__ J) {
+                                              double s0, double s1, const double* base,
+                                              const double* c3, double* __restrict__ J) {
   constexpr int W = R + 1;
   double Iw[W][W][W];
   int f[3];
-  piece_sbar<R>(G, x0, d, s0, s1, Iw, f);
+  piece_sbar<R>(G, x0, d, s0, s1, base, Iw, f);
   const int64_t nc = G.ncell;
 #pragma unroll
   for (int a = 0; a < W; ++a) {
@@ -287,12 +284,12 @@ __device__ __forceinline__ void gather_points(const Grid& G, const double* x0, c
 
 template <int R, bool WITH_U, class Acc>
 __device__ __forceinline__ void gather_piece(const Grid& G, const double* x0, const double* d,
-                                             double s0, double s1, const Acc& acc,
-                                             const double* __restrict__ Uh, double* gp,
-                                             double (*D)[3], double* Ub, double& pou) {
+                                             double s0, double s1, const double* base,
+                                             const Acc& acc, const double* __restrict__ Uh,
+                                             double* gp, double (*D)[3], double* Ub, double& pou) {
   constexpr int NQ = Quad<R>::NQ;
-  double base[3], sq[NQ], wq[NQ];
-  piece_rule<R>(G, x0, d, s0, s1, base, sq, wq);
+  double sq[NQ], wq[NQ];
+  piece_rule<R>(s0, s1, sq, wq);
   gather_points<R, NQ, WITH_U>(G, x0, d, base, sq, wq, acc, Uh, gp, D, Ub, pou);
 }
 
@@ -379,11 +376,12 @@ __device__ __forceinline__ void push_points(const Grid& G, const double* x0, con
 
 template <int R, class Acc>
 __device__ __forceinline__ void push_piece(const Grid& G, const double* x0, const double* d,
-                                           double s0, double s1, const double* vb,
-                                           const Acc& acc, double* gp, double* dtv) {
+                                           double s0, double s1, const double* base,
+                                           const double* vb, const Acc& acc, double* gp,
+                                           double* dtv) {
   constexpr int NQ = Quad<R>::NQ;
-  double base[3], sq[NQ], wq[NQ];
-  piece_rule<R>(G, x0, d, s0, s1, base, sq, wq);
+  double sq[NQ], wq[NQ];
+  piece_rule<R>(s0, s1, sq, wq);
   push_points<R, NQ>(G, x0, d, base, sq, wq, vb, acc, gp, dtv);
 }
 
@@ -775,11 +773,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((
     };
     bool ok = true;
     if constexpr (SPLIT && R >= 3) {
-      ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
+      ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1, const double* base) {
         constexpr int NQ = Quad<R>::NQ;
-        double base[3], sq[NQ], wq[NQ], X[NQ][W], Y[NQ][W], Z[NQ][W];
+        double sq[NQ], wq[NQ], X[NQ][W], Y[NQ][W], Z[NQ][W];
         int f[3];
-        piece_rule<R>(P.G, x0, d, s0, s1, base, sq, wq);
+        piece_rule<R>(s0, s1, sq, wq);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const double sv = sq[q];
@@ -794,10 +792,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         deposit_factored(X, Y, Z, f);
       });
     } else if constexpr (SPLIT) {
-      ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
+      ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1, const double* base) {
         double Iw[W][W][W];
         int f[3];
-        piece_sbar<R>(P.G, x0, d, s0, s1, Iw, f);
+        piece_sbar<R>(P.G, x0, d, s0, s1, base, Iw, f);
         deposit(Iw, f);
       });
     } else {
@@ -847,19 +845,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   }
 }
 
-// Gather + push of one particle through accessor acc: grad phi-bar and
-// (D A)^T vbar over the orbit pieces, then P^{n+1,p} and v^{n+1,p+1}.
-template <int R, bool SPLIT, class Acc>
-__device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& acc,
-                                                const double* x0, const double* d,
-                                                const double* vb, const double* va, double qi,
-                                                double mi, double* vn, double& npieces,
-                                                double& bad) {
+// Gather + push of one particle (index i of store st) through accessor acc:
+// grad phi-bar and (D A)^T vbar over the orbit pieces, then P^{n+1,p} and
+// v^{n+1,p+1}.  v^n is read again after the orbit loop rather than kept in
+// registers through it (the loop sets the kernel's register count).
+template <int R, bool SPLIT, class Acc, class PS>
+__device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& acc, const PS& st,
+                                                int64_t i, const double* x0, const double* d,
+                                                const double* vb, double qi, double mi,
+                                                double* vn, double& npieces, double& bad) {
   double gp[3] = {0.0, 0.0, 0.0};
   double dtv[3] = {0.0, 0.0, 0.0};  // H_j ((D A)^T vbar)_j until the pieces are summed
   if constexpr (SPLIT) {
-    const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
-      push_piece<R>(P.G, x0, d, s0, s1, vb, acc, gp, dtv);
+    const bool ok = for_each_piece<R>(x0, d, P.G, [&](double s0, double s1, const double* base) {
+      push_piece<R>(P.G, x0, d, s0, s1, base, vb, acc, gp, dtv);
       npieces += 1.0;
     });
     if (!ok) bad = 1.0;
@@ -873,6 +872,9 @@ __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& 
   }
   // A_h^n(x^n) rebuilds P^n = m v^n + q A_h^n(x^n) (eq. discrete-canonical-relation);
   // A_h^{n+1}(x^{n+1}) at the wrapped end point closes the velocity (eq. orbit-v-update).
+  double va[3];
+  asm volatile("" ::: "memory");  // a fresh load, not the value from before the loop
+  st.v_of(P.np, i, va);
   double x1[3], A0s[3], A1e[3];
   int zero[3] = {0, 0, 0}, sh1[3];
 #pragma unroll
@@ -993,15 +995,19 @@ __device__ __forceinline__ void gather_block(const StepParams& P, const PS& st,
       acc.oz = shift[2] - s_ref[2] - tlo[2];
       acc.dy = dim[1];
       acc.dz = dim[2];
-      gather_push_one<R, SPLIT>(P, acc, x0, d, vb, va, qi, mi, vn, npieces[0], bad);
+      gather_push_one<R, SPLIT>(P, acc, st, i, x0, d, vb, qi, mi, vn, npieces[0], bad);
     }
   } else {
     if (active) {
       GlobalGather acc{F.g, P.G.mask[0], P.G.mask[1], P.G.mask[2], P.G.shx, P.G.shy};
-      gather_push_one<R, SPLIT>(P, acc, x0, d, vb, va, qi, mi, vn, npieces[0], bad);
+      gather_push_one<R, SPLIT>(P, acc, st, i, x0, d, vb, qi, mi, vn, npieces[0], bad);
     }
   }
   if (active) {
+    // v^n and v^{n+1,p} again (see gather_push_one)
+    asm volatile("" ::: "memory");
+    st.v_of(P.np, i, va);
+    load3(vit, P.np, i, vi);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       vnew[j * P.np + i] = vn[j];
@@ -1044,8 +1050,17 @@ __device__ __forceinline__ void gather_block(const StepParams& P, const PS& st,
   }
 }
 
+// Two waves per SIMD for the tiled quadratic gather: its orbit loop fits 256
+// registers, and asking for the occupancy makes the compiler keep it (it would
+// otherwise go to one wave and twice the registers for a few more values).
+// The global-memory kernel, which only takes blocks whose box overflows the
+// tile, is left to the compiler's choice.
+template <int R, bool TILED>
+constexpr int kGatherWavesPerSimd = (R == 2 && TILED) ? 2 : 1;
+
 template <int R, bool TILED, class PS, bool SPLIT>
-__global__ __launch_bounds__(kBlock) void k_gather_push(StepParams P, PS st,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    kGatherWavesPerSimd<R, TILED>))) void k_gather_push(StepParams P, PS st,
                                                        const double* __restrict__ vit,
                                                        double* __restrict__ vnew,
                                                        double* __restrict__ vbar_out, AosFields F,
@@ -1093,8 +1108,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, PS st,
     double D[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     double pou = 0.0;
     if constexpr (SPLIT) {
-      for_each_piece<R>(x0, d, P.G, [&](double s0, double s1) {
-        gather_piece<R, true>(P.G, x0, d, s0, s1, F, Uh, gp, D, Ub, pou);
+      for_each_piece<R>(x0, d, P.G, [&](double s0, double s1, const double* base) {
+        gather_piece<R, true>(P.G, x0, d, s0, s1, base, F, Uh, gp, D, Ub, pou);
       });
     } else {
       for (int q = 0; q < P.rule.n; ++q) {
@@ -1125,30 +1140,35 @@ __global__ __launch_bounds__(kBlock) void k_sweep(StepParams P, PS st,
 }
 
 // Accept the step: x^{n+1} = x^n + dt vbar^p (wrapped), v^{n-1} <- v^n,
-// v^n <- v^{n+1,p+1}.  The kinetic energies are those of the stored values.
+// v^n <- v^{n+1,p+1} (with the store's rounding, keyed by the particle's
+// stored state and the step).  The kinetic energies are those of the stored
+// values.
 template <class PS>
 __global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, PS st,
                                                     const double* __restrict__ vit,
-                                                    const double* __restrict__ vnew, Scratch sc) {
+                                                    const double* __restrict__ vnew, uint64_t step,
+                                                    Scratch sc) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double s[2] = {0.0, 0.0};  // K^{n+1}, K^{n+1} - K^n
   if (i < P.np) {
-    double x0[3], vo[3], vi[3], vn[3], x1[3];
+    double x0[3], vo[3], vi[3], vn[3], x1[3], w[3];
     const double mi = species_value(P.ms, st.species(i));
     st.x_of(P.G, P.np, i, x0);
     st.v_of(P.np, i, vo);
     load3(vit, P.np, i, vi);
     load3(vnew, P.np, i, vn);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < 3; ++a)
       x1[a] = wrap_pos(x0[a] + P.dt * 0.5 * (vi[a] + vo[a]), P.G.L[a], P.G.invL[a]);
-      const double w = PS::stored(vn[a]);
-      s[0] += 0.5 * mi * w * w;
-      s[1] += 0.5 * mi * (w - vo[a]) * (w + vo[a]);
-    }
+    const uint64_t key = splitmix64(st.state_key(P.np, i) ^ (step * 0xd1b54a32d192ed03ull));
     st.set_x(P.G, P.np, i, x1);
     st.set_vp(P.np, i, vo);
-    st.set_v(P.np, i, vn);
+    st.accept_v(P.np, i, vn, key, w);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      s[0] += 0.5 * mi * w[a] * w[a];
+      s[1] += 0.5 * mi * (w[a] - vo[a]) * (w[a] + vo[a]);
+    }
   }
   block_partials<2>(s, sc.region(P_K));  // -> S_K, S_DK
 }
@@ -1264,8 +1284,8 @@ __global__ __launch_bounds__(kBlock) void k_orbit_gather_soa(QuadRule rule, Grid
   int pieces = 0;
   bool ok = true;
   if constexpr (SPLIT) {
-    ok = for_each_piece<R>(x0, d, G, [&](double s0, double s1) {
-      gather_piece<R, true>(G, x0, d, s0, s1, F, Uh, gp, D, Ub, pou);
+    ok = for_each_piece<R>(x0, d, G, [&](double s0, double s1, const double* base) {
+      gather_piece<R, true>(G, x0, d, s0, s1, base, F, Uh, gp, D, Ub, pou);
       ++pieces;
     });
   } else {
@@ -1311,8 +1331,8 @@ __global__ __launch_bounds__(kBlock) void k_orbit_deposit_soa(QuadRule rule, Gri
 #pragma unroll
   for (int a = 0; a < 3; ++a) c3[a] /= G.dV;
   if constexpr (SPLIT) {
-    for_each_piece<R>(x0, d, G, [&](double s0, double s1) {
-      scatter_piece<R>(G, x0, d, s0, s1, c3, J);
+    for_each_piece<R>(x0, d, G, [&](double s0, double s1, const double* base) {
+      scatter_piece<R>(G, x0, d, s0, s1, base, c3, J);
     });
   } else {
     constexpr int W = R + 1;
@@ -1434,9 +1454,9 @@ void launch_sweep(hipStream_t s, int r, const StepParams& P, const PS& st, const
 
 template <class PS>
 void launch_finalize(hipStream_t s, const StepParams& P, const PS& st, const double* vit,
-                     const double* vnew, Scratch sc) {
+                     const double* vnew, uint64_t step, Scratch sc) {
   if (P.np <= 0) return;
-  k_finalize<PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, vnew, sc);
+  k_finalize<PS><<<blocks_for(P.np), kBlock, 0, s>>>(P, st, vit, vnew, step, sc);
 }
 
 template <class PS>
@@ -1481,7 +1501,7 @@ void launch_fixed_current(hipStream_t s, int64_t n, unsigned long long* Jfix, do
   template void launch_sweep<PS>(hipStream_t, int, const StepParams&, const PS&, const double*,  \
                                  const double*, const double*, Scratch);                         \
   template void launch_finalize<PS>(hipStream_t, const StepParams&, const PS&, const double*,     \
-                                    const double*, Scratch);                                     \
+                                    const double*, uint64_t, Scratch);                           \
   template void launch_kinetic<PS>(hipStream_t, const StepParams&, const PS&, Scratch);          \
   template void launch_deposit_rho<PS>(hipStream_t, int, const StepParams&, const PS&,          \
                                        CurrentOut);                                              \

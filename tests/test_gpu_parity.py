@@ -187,6 +187,38 @@ def test_kernel_orbit_deposit_matches_oracle(r):
     assert err <= 1e-13 * scale
 
 
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_orbits_starting_on_knots_have_the_oracles_pieces(r):
+    """Quiet-start positions lie on knots in y and z (cell centres for r = 2,
+    nodes otherwise); with transverse steps of either sign and any size down
+    to 1e-15 of a cell an orbit leaves the knot at s = 0 and crosses nothing
+    there (Sec. 4.7, breakpoints strictly inside (0, 1)): the piece counts
+    equal the oracle's, and the integrals agree."""
+    rng = np.random.default_rng(400 + r)
+    k = 6000
+    h = [LB[a] / N[a] for a in range(3)]
+    off = 0.5 if r == 2 else 0.0
+    x0 = np.stack([rng.uniform(0, LB[0], size=k)] +
+                  [(rng.integers(0, N[a], size=k) + off) * h[a] for a in (1, 2)], axis=1)
+    mag = 10.0 ** rng.uniform(-15, -1, size=(k, 2))
+    d = np.concatenate([rng.uniform(-1.8, 1.8, size=(k, 1)) * h[0],
+                        mag * rng.choice([-1.0, 1.0], size=(k, 2)) * np.array(h[1:])], axis=1)
+    A0, A1, gphi, U = (W.random_fields(N, 3, seed=s) for s in (11, 12, 13, 14))
+    cfg = E.make_config(N, LB, 0.1, r=r)
+    o = O.OracleSim(O.make_cfg(n=N, L=LB, dt=0.1, r=r), 1)
+    got = E.orbit_gather(cfg, x0, d, gphi, U, A0, A1)
+    ref = o.orbit_gather(x0, d, gphi, U, A0, A1)
+    np.testing.assert_array_equal(got["npieces"], ref["npieces"])
+    # only the x motion crosses knots
+    ux0, ux1 = x0[:, 0] / h[0] - off, (x0[:, 0] + d[:, 0]) / h[0] - off
+    assert np.array_equal(ref["npieces"], 1 + np.abs(np.floor(ux1) - np.floor(ux0)).astype(int))
+    for key, scale in (("gphibar", np.abs(gphi).max()), ("Ubar", np.abs(U).max()),
+                       ("D", np.abs(ref["D"]).max()), ("pou", 1.0)):
+        err = np.abs(got[key] - ref[key]).max()
+        assert err <= 1e-13 * scale, (key, err, scale)
+    log(f"r={r}: {k} orbits from knots, pieces equal (mean {ref['npieces'].mean():.2f})")
+
+
 @pytest.mark.parametrize("r,nq", [(1, 0), (1, 16), (2, 0), (2, 7), (3, 0), (3, 9)])
 def test_kernel_unsplit_orbit_integrals_match_oracle(r, nq):
     """The unsplit comparison path: one Gauss rule over the whole orbit, each

@@ -112,6 +112,43 @@ def test_breakpoints_static_axis_and_exact_knot_start():
     np.testing.assert_array_equal(s, [0.0, 1.0])
 
 
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_orbit_leaving_a_knot_takes_the_side_it_moves_to(r):
+    """An orbit starting on a y knot that moves off it by less than the
+    rounding of its position (|d_y| = 1e-20, 1e-17 H) is integrated with the
+    stencil of the interval it moves into (Sec. 4.7: every piece lies inside
+    one knot interval).  Pinned against brute force at d_y = +-1e-6 H, whose
+    quadrature points sit clearly inside that interval: the integrals move by
+    O(|d_y|) in between, so both agree to 1e-5.  For r = 1 the gradient jumps
+    at the knot and the two directions differ at O(1), which a side chosen by
+    rounding gets wrong for one of them."""
+    S = sim(r)
+    off = 0.5 if r == 2 else 0.0
+    A0 = W.random_fields(N, 3, seed=31)
+    A1 = A0 + 0.3 * W.random_fields(N, 3, seed=32)
+    gphi = W.random_fields(N, 3, seed=33)
+    U = W.random_fields(N, 3, seed=34)
+    rng = np.random.default_rng(50 + r)
+    x0 = np.array([rng.uniform(0, L[0]), (3 + off) * H[1], rng.uniform(0, L[2])])
+    Dy = {}
+    for sign in (1.0, -1.0):
+        dref = np.array([0.4 * H[0], sign * 1e-6 * H[1], -0.3 * H[2]])
+        Dref = B.orbit_D(r, x0, dref, N, L, A0, A1)
+        gref = B.orbit_gather(r, x0, dref, N, L, gphi)
+        Uref = B.orbit_gather(r, x0, dref, N, L, U)
+        for eps in (1e-20, 1e-17):
+            d = dref.copy()
+            d[1] = sign * eps * H[1]
+            assert x0[1] + d[1] == x0[1]  # the step is lost to rounding
+            out = S.orbit_gather(x0[None], d[None], gphi, U, A0, A1)
+            np.testing.assert_allclose(out["D"][0], Dref, atol=1e-5 * np.abs(Dref).max())
+            np.testing.assert_allclose(out["gphibar"][0], gref, atol=1e-5 * np.abs(gphi).max())
+            np.testing.assert_allclose(out["Ubar"][0], Uref, atol=1e-5 * np.abs(U).max())
+        Dy[sign] = Dref[:, 1]
+    if r == 1:
+        assert np.abs(Dy[1.0] - Dy[-1.0]).max() > 0.1 * np.abs(Dy[1.0]).max()
+
+
 # --------------------------------------------------------------------------
 # orbit weights and D versus brute force
 # --------------------------------------------------------------------------
