@@ -894,8 +894,11 @@ __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& 
 }
 
 // One block = 256 cell-sorted particles.  TILED = true: the block finds the
-// box of nodes its orbits touch (one node of margin per side against rounding
-// of piece midpoints), copies the gather fields of that box into LDS, and
+// box of nodes its orbits touch from the rounded u0 and u1 of each orbit, with
+// one node of margin per side (a piece's knot interval, decided against the
+// knot positions, differs from the interval of a rounded end point only
+// within rounding of a knot, and then by one), copies the gather fields of
+// that box into LDS, and
 // every stencil read of the node loop then comes from LDS; a block whose box
 // does not fit the tile appends its index to a work list (work[0] = count,
 // work[1..] = block indices).  TILED = false: the blocks on that list (all
