@@ -276,6 +276,59 @@ def test_step_parity_fixed_iterations(r, pmax):
         compare_states(wl, g, o, f"r={r} pmax={pmax} step {step}")
 
 
+def knot_edge_plasma(r, seed=17):
+    """small_random with orbits at knots: in the first step of a single-pass
+    Picard iteration vbar = v^0 (v^{-1} := v^0), so d = dt v^0 exactly.  A
+    third of the particles get an end point x0 + d exactly on a knot along
+    randomly chosen axes (x0 moved by ulps until the double sum is the knot
+    position (k + knot_off) H); a third start exactly on a knot along
+    randomly chosen axes with steps of 1e-15 .. 1e-2 of a cell of either
+    sign there."""
+    wl = small_random(r, seed=seed)
+    rng = np.random.default_rng(seed)
+    h = [wl.L[a] / wl.n[a] for a in range(3)]
+    off = 0.5 if r == 2 else 0.0
+    x, v = wl.x.copy(), wl.v.copy()
+    npart = x.shape[1]
+    for i in range(npart):
+        kind = i % 3
+        if kind == 2:
+            continue
+        for a in range(3):
+            if rng.random() < 0.4:
+                continue
+            k = int(rng.integers(1, wl.n[a] - 1))
+            knot = (k + off) * h[a]
+            if kind == 0:
+                d = wl.dt * v[a, i]
+                x0 = knot - d
+                for _ in range(8):
+                    if x0 + d == knot:
+                        break
+                    x0 = np.nextafter(x0, np.inf if x0 + d < knot else -np.inf)
+                if x0 + d == knot and 0.0 <= x0 < wl.L[a]:
+                    x[a, i] = x0
+            else:
+                x[a, i] = knot
+                v[a, i] = rng.choice([-1.0, 1.0]) * 10.0 ** rng.uniform(-15, -2) * h[a] / wl.dt
+    wl.x, wl.v = x, v
+    return wl
+
+
+@pytest.mark.parametrize("r,chunk", [(1, 2048), (2, 4096), (2, 2048), (3, 2048)])
+def test_orbits_ending_or_starting_on_knots_step_parity(r, chunk):
+    """Orbits that end exactly on a knot (the crossing parameter there is 1
+    up to rounding, and the kernel's and the oracle's crossing counts may
+    differ by a sliver piece at the end) and orbits that leave a knot by
+    less than a cell's rounding: the tiled scatter and gather take every
+    such piece's stencil inside their node boxes, and the step agrees with
+    the oracle at 1e-12."""
+    wl = knot_edge_plasma(r)
+    g, o = both(wl, tol=0.0, pmax=0, scatter_chunk=chunk)
+    assert g.picard_step()["iters"] == o.step()["iters"] == 1
+    compare_states(wl, g, o, f"knot edges r={r} chunk={chunk}")
+
+
 @pytest.mark.parametrize("r,chunk", [(1, 2048), (2, 2048), (2, 4096), (3, 2048)])
 def test_step_parity_with_each_scatter_chunk(r, chunk):
     """Each scatter chunk length and tile size, forced (the automatic choice
