@@ -65,15 +65,47 @@ __device__ __forceinline__ int64_t adjoint_particle(int64_t np) {
   return (t % kWave) * stride + t / kWave;
 }
 
+// Where the push's mesh adjoints go (nine values per node: component l of
+// grad phi, A^n and A^{n+1} as 0 + l, 3 + l and 6 + l).  add() takes the node
+// in the particle's unwrapped frame (ix, iy, iz) and its flat index g.
+struct GlobalAdjSink {
+  const AdjParticleArgs* P;
+  __device__ __forceinline__ double* target(int comp) const {
+    double* base = comp < 3 ? P->lgphi : (comp < 6 ? P->lA0 : P->lA1);
+    return base + (int64_t)(comp % 3) * P->G.ncell;
+  }
+  __device__ __forceinline__ void add(int comp, int, int, int, int64_t g, double v) const {
+    unsafeAtomicAdd(target(comp) + g, v);
+  }
+};
+
+// The block's LDS tile over its chunk's node box (nine doubles per node);
+// o[] takes the particle's frame to the tile's.  A node outside the box
+// (not expected: the box has a node of margin per side) goes to global
+// memory.
+struct TileAdjSink {
+  GlobalAdjSink glob;
+  double* tile;
+  int o[3], dim[3];
+  bool use;
+  __device__ __forceinline__ void add(int comp, int ix, int iy, int iz, int64_t g,
+                                      double v) const {
+    const int tx = ix + o[0], ty = iy + o[1], tz = iz + o[2];
+    if (use && tx >= 0 && ty >= 0 && tz >= 0 && tx < dim[0] && ty < dim[1] && tz < dim[2])
+      atomicAdd(&tile[9 * ((tx * dim[1] + ty) * dim[2] + tz) + comp], v);
+    else
+      glob.add(comp, ix, iy, iz, g, v);
+  }
+};
+
 // Node by node: each stencil node's mesh values are read once per piece and
 // its quadrature sums Sbar = sum_q w_q S, T0 = sum_q w_q (1 - s_q) eta.grad S,
 // T1 = sum_q w_q s_q eta.grad S give its nine mesh-adjoint contributions of
-// the piece with one atomic each (dL/dgphi_l = -dt eta_l Sbar,
-// dL/dA0_l = dt vbar_l T0, dL/dA1_l = dt vbar_l T1).
-template <bool ETA, bool MU>
-__global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) {
-  const int64_t i = adjoint_particle<ETA>(P.np);
-  if (i >= P.np) return;
+// the piece (dL/dgphi_l = -dt eta_l Sbar, dL/dA0_l = dt vbar_l T0,
+// dL/dA1_l = dt vbar_l T1), handed to the sink.
+template <bool ETA, bool MU, class Sink>
+__device__ __forceinline__ void particle_adjoint(const AdjParticleArgs& P, int64_t i,
+                                                 const Sink& sink) {
   const Grid& G = P.G;
   const int64_t np = P.np, nc = G.ncell;
   double x0[3], vb[3], d[3], eta[3] = {0.0, 0.0, 0.0};
@@ -158,11 +190,12 @@ __global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) 
         }
       }
       if constexpr (ETA) {
+        const int ix = first[0] + a, iy = first[1] + b, iz = first[2] + c;
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
-          unsafeAtomicAdd(P.lgphi + l * nc + g, -P.dt * eta[l] * Sbar);
-          unsafeAtomicAdd(P.lA0 + l * nc + g, P.dt * vb[l] * T0);
-          unsafeAtomicAdd(P.lA1 + l * nc + g, P.dt * vb[l] * T1);
+          sink.add(l, ix, iy, iz, g, -P.dt * eta[l] * Sbar);
+          sink.add(3 + l, ix, iy, iz, g, P.dt * vb[l] * T0);
+          sink.add(6 + l, ix, iy, iz, g, P.dt * vb[l] * T1);
         }
       }
     }
@@ -172,9 +205,8 @@ __global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) 
     for (int e = 0; e < 2; ++e) {
       const double sgn = e == 0 ? 1.0 : -1.0;
       const double* F = e == 0 ? P.A0 : P.A1;
-      double* lF = e == 0 ? P.lA0 : P.lA1;
       double base[3];
-      int first[3];
+      int first[3], sh[3];
       Axis2 ax[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -183,6 +215,8 @@ __global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) 
         base[a] = floor(u + Spline<2>::base_off);
         first[a] = to_int_clamped(base[a]) + Spline<2>::first_off;
         ax[a].at(u - base[a], G.invH[a]);
+        // periods between the wrapped end point and the unwrapped orbit end
+        sh[a] = e == 0 ? 0 : (int)rint((x0[a] + d[a] - xp) * G.invL[a]) * G.n[a];
       }
       for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
@@ -196,7 +230,8 @@ __global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) 
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
               eF += eta[l] * F[l * nc + g];
-              unsafeAtomicAdd(lF + l * nc + g, sgn * eta[l] * S);
+              sink.add((e == 0 ? 3 : 6) + l, first[0] + a + sh[0], first[1] + b + sh[1],
+                       first[2] + c + sh[2], g, sgn * eta[l] * S);
             }
 #pragma unroll
             for (int kk = 0; kk < 3; ++kk) {
@@ -212,6 +247,109 @@ __global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) 
     P.lx[a * np + i] += lx[a];
     P.ld[a * np + i] += ld[a];
     P.lvb[a * np + i] += lvb[a];
+  }
+}
+
+template <bool ETA, bool MU>
+__global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) {
+  const int64_t i = adjoint_particle<ETA>(P.np);
+  if (i >= P.np) return;
+  particle_adjoint<ETA, MU>(P, i, GlobalAdjSink{&P});
+}
+
+// The push terms over cell-sorted particles, one block per chunk of kAdjChunk
+// particles whose wavefronts' lanes sit kAdjChunk / 64 particles apart (one
+// cell apart at 64 particles per cell), as in the current scatter: the block
+// finds the node box of its chunk's orbits and end points (one node of
+// margin per side), sums the nine mesh adjoints of its particles in an LDS
+// tile over that box, and adds the tile to global memory once.  A chunk
+// whose box exceeds the tile adds straight to global memory.  The kernel
+// runs at one wavefront per SIMD (its registers), so one block per CU loses
+// nothing to the 144 KB tile.
+constexpr int kAdjChunk = 4096;
+constexpr int kAdjTileNodes = 2048;
+
+__device__ __forceinline__ int64_t adj_chunk_particle(int64_t base, int k) {
+  return base + (int64_t)(threadIdx.x % kWave) * (kAdjChunk / kWave) + threadIdx.x / kWave +
+         (int64_t)(kBlock / kWave) * k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_push_adjoint_tiled(AdjParticleArgs P) {
+  constexpr int kPerThread = kAdjChunk / kBlock;
+  __shared__ double tile[9 * kAdjTileNodes];
+  __shared__ int s_ref[3];
+  const Grid& G = P.G;
+  const int64_t base = (int64_t)blockIdx.x * kAdjChunk;
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      s_ref[a] = to_int_clamped(floor(P.x[a * P.np + base] * G.invH[a] + Spline<2>::base_off));
+  __syncthreads();
+  // node box of the chunk: the orbits from x0 to x0 + d (unwrapped), which
+  // also hold both end points' stencils
+  int rmin[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff};
+  int rmax[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t i = adj_chunk_particle(base, k);
+    if (i >= P.np) continue;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double x0 = P.x[a * P.np + i], d = P.dt * P.vb[a * P.np + i];
+      const double u0 = x0 * G.invH[a], u1 = (x0 + d) * G.invH[a];
+      const int lo = to_int_clamped(floor(fmin(u0, u1) + Spline<2>::base_off)) +
+                     Spline<2>::first_off - 1;
+      const int hi = to_int_clamped(floor(fmax(u0, u1) + Spline<2>::base_off)) +
+                     Spline<2>::first_off + 3;
+      const int rel = min_image(lo - s_ref[a], G.n[a]);
+      rmin[a] = min(rmin[a], rel);
+      rmax[a] = max(rmax[a], rel + (hi - lo));
+    }
+  }
+  int tlo[3], dim[3];
+  {
+    int mv[6] = {rmin[0], rmin[1], rmin[2], -rmax[0], -rmax[1], -rmax[2]};
+    block_min_ints<6>(mv);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      tlo[a] = mv[a];
+      dim[a] = -mv[3 + a] - tlo[a] + 1;
+    }
+  }
+  // block-uniform; each extent is bounded first so that the product cannot overflow
+  const bool use_tile = dim[0] > 0 && dim[0] <= kAdjTileNodes && dim[1] <= kAdjTileNodes &&
+                        dim[2] <= kAdjTileNodes &&
+                        (int64_t)dim[0] * dim[1] * dim[2] <= kAdjTileNodes;
+  const int nt = use_tile ? dim[0] * dim[1] * dim[2] : 0;
+  for (int t = threadIdx.x; t < 9 * nt; t += kBlock) tile[t] = 0.0;
+  __syncthreads();
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t i = adj_chunk_particle(base, k);
+    if (i >= P.np) break;
+    TileAdjSink sink{GlobalAdjSink{&P}, tile, {0, 0, 0}, {dim[0], dim[1], dim[2]}, use_tile};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double x0 = P.x[a * P.np + i], d = P.dt * P.vb[a * P.np + i];
+      const double u0 = x0 * G.invH[a], u1 = (x0 + d) * G.invH[a];
+      const int lo = to_int_clamped(floor(fmin(u0, u1) + Spline<2>::base_off)) +
+                     Spline<2>::first_off - 1;
+      const int raw = lo - s_ref[a];
+      // particle frame -> chunk frame -> tile
+      sink.o[a] = min_image(raw, G.n[a]) - raw - s_ref[a] - tlo[a];
+    }
+    particle_adjoint<true, false>(P, i, sink);
+  }
+  __syncthreads();
+  if (!use_tile) return;
+  const GlobalAdjSink glob{&P};
+  for (int t = threadIdx.x; t < nt; t += kBlock) {
+    const int cz = t % dim[2], cy = (t / dim[2]) % dim[1], cx = t / (dim[1] * dim[2]);
+    const int64_t g = node_index(G, s_ref[0] + tlo[0] + cx, s_ref[1] + tlo[1] + cy,
+                                 s_ref[2] + tlo[2] + cz);
+#pragma unroll
+    for (int comp = 0; comp < 9; ++comp) {
+      const double val = tile[9 * t + comp];
+      if (val != 0.0) unsafeAtomicAdd(glob.target(comp) + g, val);
+    }
   }
 }
 
@@ -282,7 +420,7 @@ void launch_particle_adjoint(hipStream_t s, const AdjParticleArgs& P, bool eta, 
   if (eta && mu)
     k_particle_adjoint<true, true><<<spread, kBlock, 0, s>>>(P);
   else if (eta)
-    k_particle_adjoint<true, false><<<spread, kBlock, 0, s>>>(P);
+    k_push_adjoint_tiled<<<(unsigned)((P.np + kAdjChunk - 1) / kAdjChunk), kBlock, 0, s>>>(P);
   else if (mu)
     k_particle_adjoint<false, true><<<blocks_for(P.np), kBlock, 0, s>>>(P);
 }

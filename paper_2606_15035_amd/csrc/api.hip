@@ -411,6 +411,11 @@ namespace {
 // Device workspace of the adjoint step (caller-owned).
 struct AdjWs {
   double *vb, *xi, *xn, *b, *lxacc, *lx, *ld, *lvb;  // 3 x np each
+  // the step's particles in cell order (x, v, w, and the adjoints lx1, lv1
+  // in and lx0, lv0 out; 3 x np each); id: cell order -> caller order
+  double *xs, *vs, *ws, *lx1s, *lv1s, *lx0s, *lv0s;
+  int *id, *id2;
+  SortScratch sb;
   double *J, *gfield, *lg_r, *mu;                     // 3, 6, 9, 3 x ncell (real)
   double2 *Fh, *F1h, *Jh, *inv, *l1, *lg, *lcur, *lJh;  // 9, 9, 3, 6, 9, 9, 9, 3 x ncell
   double* red;                                        // [max|dxi|, max|xi|, bad]
@@ -420,8 +425,17 @@ size_t carve_adjoint(const Grid& G, int64_t np, char* base, AdjWs* A) {
   const size_t n3 = (size_t)3 * (np > 0 ? np : 1);
   const int64_t nc = G.ncell;
   Carver c{base};
-  double** pv[8] = {&A->vb, &A->xi, &A->xn, &A->b, &A->lxacc, &A->lx, &A->ld, &A->lvb};
+  double** pv[15] = {&A->vb,  &A->xi, &A->xn, &A->b,    &A->lxacc, &A->lx,   &A->ld,  &A->lvb,
+                     &A->xs,  &A->vs, &A->ws, &A->lx1s, &A->lv1s,  &A->lx0s, &A->lv0s};
   for (double** q : pv) *q = c.take<double>(n3);
+  const size_t n1 = (size_t)(np > 0 ? np : 1);
+  A->id = c.take<int>(n1);
+  A->id2 = c.take<int>(n1);
+  A->sb.key = c.take<int>(n1);
+  A->sb.count = c.take<int>(8 * nc);
+  A->sb.offset = c.take<int>(8 * nc + 1);
+  A->sb.cursor = c.take<int>(8 * nc);
+  A->sb.scan_totals = c.take<int>(sort_scan_blocks(nc));
   A->J = c.take<double>(3 * nc);
   A->gfield = c.take<double>(6 * nc);
   A->lg_r = c.take<double>(9 * nc);
@@ -1243,6 +1257,30 @@ ecpic_status adjoint_step_impl(ecpic_sim* S, char* workspace, const double* x, c
   StepParams P = S->pp();
   const double dt = S->cfg.dt;
 
+  // The step's particles in cell order for the whole adjoint (x, v and w move
+  // together; the particle kernels then work on local chunks), the caller's
+  // order restored for lx0 and lv0 at the end.
+  if (np > 0) {
+    launch_iota(s, np, A.id);
+    int* id = A.id;
+    int* id2 = A.id2;
+    Fp64Store cur{const_cast<double*>(x), const_cast<double*>(v), const_cast<double*>(w)};
+    Fp64Store alt{A.xs, A.vs, A.ws};
+    launch_sort(s, G, np, cur, alt, id, id2, A.sb);
+    A.id = id;  // the ids of the sorted copies (cur now views A.xs, A.vs, A.ws)
+    x = cur.x;
+    v = cur.v;
+    w = cur.vp;
+    if (lx1) {
+      launch_from_caller(s, np, A.id, lx1, A.lx1s);
+      lx1 = A.lx1s;
+    }
+    if (lv1) {
+      launch_from_caller(s, np, A.id, lv1, A.lv1s);
+      lv1 = A.lv1s;
+    }
+  }
+
   // forward quantities of the converged iterate: J, the level n+1 spectra,
   // grad_h phi^{n+1/2} and A^{n+1} (A^n is the fields' A rows)
   launch_vbar(s, n3, w, v, A.vb);
@@ -1312,7 +1350,9 @@ ecpic_status adjoint_step_impl(ecpic_sim* S, char* workspace, const double* x, c
     if (conv || it == max_iters + 1) {
       // the inputs' adjoints from this xi: the push's mesh share of level n
       launch_cn_adjoint(s, FP, nullptr, A.lg, A.lcur, A.lJh);
-      launch_adjoint_out(s, n3, A.lxacc, A.lx, A.xi, lv1, lx0, lv0);
+      launch_adjoint_out(s, n3, A.lxacc, A.lx, A.xi, lv1, A.lx0s, A.lv0s);
+      launch_to_caller(s, np, A.id, A.lx0s, lx0);
+      launch_to_caller(s, np, A.id, A.lv0s, lv0);
       RealIO fo = soa_io(lF0, nc, 9);
       fft3_inverse(s, G, 9, A.lcur, &fo, twp(S));
       break;

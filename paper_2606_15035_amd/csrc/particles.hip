@@ -502,40 +502,11 @@ struct ScatterChunk {
   static constexpr int kWavesPerSimd = (CH == 2048 && R < 3) ? 3 : 1;  // minimum asked for
 };
 
-__device__ __forceinline__ int min_image(int raw, int n) {
-  int r = raw % n;
-  if (2 * r > n) r -= n;
-  if (2 * r < -n) r += n;
-  return r;
-}
-
 // t / d for 0 <= t < 2^22 and d >= 1, with inv_d = 1.0f / d: (t + 1/2) / d
 // lies at least 1/(2d) away from an integer, further than the float rounding
 // error (t + 1/2) 2^-23 / d, so the truncation is exact (no integer division)
 __device__ __forceinline__ int div_small(int t, float inv_d) {
   return (int)(((float)t + 0.5f) * inv_d);
-}
-
-// block-wide minimum of M ints at once (one barrier pair for all of them)
-template <int M>
-__device__ __forceinline__ void block_min_ints(int (&v)[M]) {
-  __shared__ int lds_i[M][kBlock / kWave];
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v[m] = min(v[m], __shfl_xor(v[m], o, kWave));
-    if (lane == 0) lds_i[m][wid] = v[m];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-    int r = lds_i[m][0];
-#pragma unroll
-    for (int w = 1; w < kBlock / kWave; ++w) r = min(r, lds_i[m][w]);
-    v[m] = r;
-  }
-  __syncthreads();
 }
 
 template <int CH>

@@ -133,4 +133,35 @@ __device__ __forceinline__ void block_partials(double (&v)[M], double* region) {
     for (int m = 0; m < M; ++m) region[(size_t)m * gridDim.x + blockIdx.x] = v[m];
 }
 
+// Periodic minimum image of a node-index difference: raw mod n in
+// [-n/2, n/2].
+__device__ __forceinline__ int min_image(int raw, int n) {
+  int r = raw % n;
+  if (2 * r > n) r -= n;
+  if (2 * r < -n) r += n;
+  return r;
+}
+
+// block-wide minimum of M ints at once (one barrier pair for all of them)
+template <int M>
+__device__ __forceinline__ void block_min_ints(int (&v)[M]) {
+  __shared__ int lds_i[M][kBlock / kWave];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v[m] = min(v[m], __shfl_xor(v[m], o, kWave));
+    if (lane == 0) lds_i[m][wid] = v[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    int r = lds_i[m][0];
+#pragma unroll
+    for (int w = 1; w < kBlock / kWave; ++w) r = min(r, lds_i[m][w]);
+    v[m] = r;
+  }
+  __syncthreads();
+}
+
 }  // namespace ecpic
