@@ -197,13 +197,15 @@ ecpic_status ecpic_field_solve(ecpic_sim* sim, const double* J_dev);
    diagnostics = 1 in the configuration (they are zero otherwise). */
 ecpic_status ecpic_energy_diagnostics(ecpic_sim* sim, ecpic_energy* out);
 
-/* Copy state to host buffers (any may be NULL): x, v, v^{n-1} (3*np each) and
-   real-space mesh fields (9*ncell: phi, psi, Ax, Ay, Az, Ux, Uy, Uz, rho). */
+/* Copy state to caller buffers (any may be NULL): x, v, v^{n-1} (3*np each) and
+   real-space mesh fields (9*ncell: phi, psi, Ax, Ay, Az, Ux, Uy, Uz, rho).
+   Host or device memory: the copy direction follows from the pointers
+   (unified addressing).  Returns after the copies are complete. */
 ecpic_status ecpic_get_state(ecpic_sim* sim, double* x, double* v, double* vprev,
                              double* fields);
 
-/* Replace the state from host buffers (same layout as ecpic_get_state; any may
-   be NULL to keep the current value).  m > 0: every particle gets charge q and
+/* Replace the state from caller buffers, host or device (same layout as
+   ecpic_get_state; any may be NULL to keep the current value).  m > 0: every particle gets charge q and
    mass m (one species); m = 0: every particle keeps its species (q ignored;
    ECPIC_ESTATE before the first initialisation).  The fields pass through
    real space, so a state read and written back differs from the original at

@@ -46,7 +46,7 @@ class Run:
 
 
 def _state(sim):
-    s = sim.get_state()
+    s = sim.get_state(device=True)  # checkpoints and recomputed states stay in HBM
     return s["x"], s["v"], s["vprev"], s["fields"]
 
 
@@ -90,7 +90,7 @@ def _backward(run: Run, checkpoints, lF):
         for k in range(e - 1, s - 1, -1):
             xk, vk, Fk = states[k - s]
             w = states[k - s + 1][1]
-            args = [torch.as_tensor(a, device=dev) for a in (xk, vk, w, Fk)]
+            args = (xk, vk, w, Fk)
             torch.cuda.synchronize(dev)
             t0 = time.perf_counter()  # the call returns after its stream is synchronised
             lx, lv, lF, info = sim.adjoint_step(*args, lx, lv, lF, tol=run.adjoint_tol,

@@ -16,6 +16,8 @@
 // 2, so no end-point terms arise.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.hpp"
 #include "orbit.hpp"
 #include "reduce.hpp"
@@ -385,13 +387,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_update(int64_t n3, double dt
                                                           const double* __restrict__ xi,
                                                           double* __restrict__ xn,
                                                           double* __restrict__ red) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double dm = 0.0, xm = 0.0;
-  if (i < n3) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n3;
+       i += (int64_t)gridDim.x * kBlock) {
     const double x = b[i] + 0.5 * (lvb[i] + dt * ld[i]);
     xn[i] = x;
-    dm = fabs(x - xi[i]);
-    xm = fabs(x);
+    dm = fmax(dm, fabs(x - xi[i]));
+    xm = fmax(xm, fabs(x));
     if (!isfinite(x)) dm = INFINITY;
   }
   block_max_to(dm, red);
@@ -438,7 +440,11 @@ void launch_adjoint_rhs(hipStream_t s, int64_t n3, double dt, const double* lx1,
 void launch_adjoint_update(hipStream_t s, int64_t n3, double dt, const double* b,
                            const double* lvb, const double* ld, const double* xi, double* xn,
                            double* red) {
-  if (n3 > 0) k_adjoint_update<<<blocks_for(n3), kBlock, 0, s>>>(n3, dt, b, lvb, ld, xi, xn, red);
+  // a grid of at most 1024 blocks: every block adds its two maxima to the
+  // same two words, so fewer blocks mean fewer contended atomics
+  if (n3 > 0)
+    k_adjoint_update<<<std::min(blocks_for(n3), 1024u), kBlock, 0, s>>>(n3, dt, b, lvb, ld, xi, xn,
+                                                                        red);
 }
 
 void launch_adjoint_out(hipStream_t s, int64_t n3, const double* lxacc, const double* lx,

@@ -978,7 +978,7 @@ ecpic_status ecpic_get_state(ecpic_sim* S, double* x, double* v, double* vprev, 
       on_store(S, [&](auto& st, auto&) { launch_export(s, S->pp(), st, k, S->vnew); });
       launch_to_caller(s, np, S->id, S->vnew, S->vit);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(dst[k], S->vit, sizeof(double) * 3 * np, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(dst[k], S->vit, sizeof(double) * 3 * np, hipMemcpyDefault, s));
       HIPCHK(hipStreamSynchronize(s));
     }
   }
@@ -987,7 +987,7 @@ ecpic_status ecpic_get_state(ecpic_sim* S, double* x, double* v, double* vprev, 
     RealIO o = soa_io(S->realbuf, nc, 9);
     fft3_inverse(s, S->G, 9, S->batch, &o, twp(S));
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(fields, S->realbuf, sizeof(double) * 9 * nc, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(fields, S->realbuf, sizeof(double) * 9 * nc, hipMemcpyDefault, s));
   }
   HIPCHK(hipStreamSynchronize(s));
   return ECPIC_OK;
@@ -1007,14 +1007,14 @@ ecpic_status ecpic_set_state(ecpic_sim* S, const double* x, const double* v, con
     const double* src[3] = {x, v, vprev};
     for (int k = 0; k < 3; ++k) {
       if (!src[k]) continue;
-      HIPCHK(hipMemcpyAsync(S->vit, src[k], sizeof(double) * 3 * np, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(S->vit, src[k], sizeof(double) * 3 * np, hipMemcpyDefault, s));
       launch_from_caller(s, np, S->id, S->vit, S->vnew);
       on_store(S, [&](auto& st, auto&) { launch_import(s, S->pp(), st, k, S->vnew); });
       HIPCHK(hipGetLastError());
     }
   }
   if (fields) {
-    HIPCHK(hipMemcpyAsync(S->realbuf, fields, sizeof(double) * 9 * nc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(S->realbuf, fields, sizeof(double) * 9 * nc, hipMemcpyDefault, s));
     ecpic_status st = load_fields_from_realbuf(S);
     if (st != ECPIC_OK) return st;
   } else if (!S->initialized) {

@@ -255,13 +255,22 @@ class Sim:
         _check(lib().ecpic_energy_diagnostics(self._h, C.byref(e)))
         return e.as_dict()
 
-    def get_state(self):
-        x = np.zeros((3, self.np))
-        v = np.zeros((3, self.np))
-        vp = np.zeros((3, self.np))
-        f = np.zeros((9,) + self.n)
-        _check(lib().ecpic_get_state(self._h, _hp(x), _hp(v), _hp(vp), _hp(f)))
-        return {"x": x, "v": v, "vprev": vp, "fields": f}
+    def get_state(self, device=False):
+        """x, v, v^{n-1} (3, np) in the caller's order and the real-space fields
+        (9,) + n: host arrays, or with device=True float64 tensors on the
+        simulation's device (no trip through host memory)."""
+        shapes = {"x": (3, self.np), "v": (3, self.np), "vprev": (3, self.np),
+                  "fields": (9,) + self.n}
+        if device:
+            torch = self.torch
+            out = {k: torch.empty(sh, dtype=torch.float64, device=self.state.device)
+                   for k, sh in shapes.items()}
+            ptrs = [C.c_void_p(out[k].data_ptr()) for k in shapes]
+        else:
+            out = {k: np.zeros(sh) for k, sh in shapes.items()}
+            ptrs = [_hp(out[k]) for k in shapes]
+        _check(lib().ecpic_get_state(self._h, *ptrs))
+        return out
 
     def get_fields(self):
         """Real-space mesh fields only (9,) + n: phi, psi, A, U, rho."""
@@ -272,13 +281,25 @@ class Sim:
     def set_state(self, x=None, v=None, vprev=None, fields=None, q=None, m=None):
         """Replace parts of the state.  With q and m every particle becomes of
         that one species; without them every particle keeps its species."""
-        args = [None if a is None else _host(a) for a in (x, v, vprev, fields)]
+        args = [self._any(a) for a in (x, v, vprev, fields)]  # host arrays or device tensors
         if m is None:
             q, m = 0.0, 0.0
         else:
             q, m = float(q), float(m)
             self.q, self.m = q, m
-        _check(lib().ecpic_set_state(self._h, *[_hp(a) for a in args], q, m))
+        _check(lib().ecpic_set_state(self._h, *[p for _, p in args], q, m))
+
+    def _any(self, a):
+        """(kept object, pointer) for a host array or a device tensor (float64,
+        contiguous); (None, None) for None."""
+        if a is None:
+            return None, None
+        torch = self.torch
+        if isinstance(a, torch.Tensor) and a.is_cuda:
+            t = a.to(dtype=torch.float64).contiguous()
+            return t, C.c_void_p(t.data_ptr())
+        h = _host(a)
+        return h, _hp(h)
 
     def checkpoint(self) -> np.ndarray:
         """The simulation's state as a host byte array (ecpic_checkpoint_save)."""
