@@ -8,8 +8,8 @@
 // (eqs. orbit-push, split-Sbar, split-DA), and the current
 //   J_g = (q/dV) sum_i vbar_i Sbar_ig   (eq. orbit-current).
 // For a particle with push adjoint eta = (q/m) xi and current adjoint
-// mu = (q/dV) lambda_J, this kernel adds the derivatives with respect to
-// x, d and vbar, and scatters the push's mesh adjoints of gphi, A0 and A1.
+// mu = (q/dV) lambda_J, the kernels below add the derivatives with respect
+// to x, d and vbar, and scatter the push's mesh adjoints of gphi, A0 and A1.
 // Inside each split piece the integrands are polynomials of degree <= 6 in s
 // (4-point Gauss-Legendre is exact); the piece ends move with x and d, but
 // the integrands b_g d_j S_g and S_g are continuous across knots for degree
@@ -28,44 +28,16 @@ namespace {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// weights, first and second derivatives (physical units) of the three
-// degree-2 stencil nodes along one axis
+// weights and first derivatives (physical units) of the three degree-2
+// stencil nodes along one axis
 struct Axis2 {
-  double w[3], dw[3], ddw[3];
+  double w[3], dw[3];
   __device__ __forceinline__ void at(double t, double invH) {
     Spline<2>::wd(t, w, dw);
-    const double i2 = invH * invH;
 #pragma unroll
     for (int o = 0; o < 3; ++o) dw[o] *= invH;
-    ddw[0] = i2;
-    ddw[1] = -2.0 * i2;
-    ddw[2] = i2;
   }
 };
-
-// weight and first and second derivative (physical units) of stencil node k
-// (0..2) of degree 2 along one axis at cell coordinate t
-__device__ __forceinline__ void axis_node(int k, double t, double invH, double& w, double& dw,
-                                          double& ddw) {
-  Spline<2>::wk(k, t, w, dw);
-  dw *= invH;
-  ddw = (k == 1 ? -2.0 : 1.0) * invH * invH;
-}
-
-// Particle i of the thread.  With SPREAD the 64 lanes of a wavefront take
-// particles np / 64 apart (wavefront w, lane l: particle l * ceil(np / 64) + w),
-// so that in a cell-ordered set they sit in different cells and their
-// atomics to the mesh adjoints rarely meet on one address.
-// Threads beyond the 64 ceil(np / 64) that the spread covers (the last block's
-// padding) get np, i.e. no particle.
-template <bool SPREAD>
-__device__ __forceinline__ int64_t adjoint_particle(int64_t np) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if constexpr (!SPREAD) return t;
-  const int64_t stride = (np + kWave - 1) / kWave;
-  if (t / kWave >= stride) return np;
-  return (t % kWave) * stride + t / kWave;
-}
 
 // Where the push's mesh adjoints go (nine values per node: component l of
 // grad phi, A^n and A^{n+1} as 0 + l, 3 + l and 6 + l).  add() takes the node
@@ -100,148 +72,180 @@ struct TileAdjSink {
   }
 };
 
-// Node by node: each stencil node's mesh values are read once per piece and
-// its quadrature sums Sbar = sum_q w_q S, T0 = sum_q w_q (1 - s_q) eta.grad S,
-// T1 = sum_q w_q s_q eta.grad S give its nine mesh-adjoint contributions of
-// the piece (dL/dgphi_l = -dt eta_l Sbar, dL/dA0_l = dt vbar_l T0,
-// dL/dA1_l = dt vbar_l T1), handed to the sink.
-template <bool ETA, bool MU, class Sink>
-__device__ __forceinline__ void particle_adjoint(const AdjParticleArgs& P, int64_t i,
-                                                 const Sink& sink) {
+// The push terms of particle i (eta = (q/m) xi) in tensor-product form.
+// With eta'_j = eta_j / H_j and derivatives per unit of cell coordinate
+// (S_g = X_a Y_b Z_c; the degree-2 second derivatives are 1, -2, 1):
+//  - per node, three point sums feed the mesh adjoints and the vbar adjoint:
+//      Sbar = sum_q w S,  T0 = sum_q w (1 - s) eta'.grad S,  T1 = sum_q w s eta'.grad S
+//    (dL/dgphi_l = -dt eta_l Sbar, dL/dA0_l = dt vbar_l T0, dL/dA1_l = dt vbar_l T1;
+//    lvbar += dt (A0_g T0 + A1_g T1));
+//  - the x and d adjoints, dt / H_k sum_g sum_q w_q (1, s) [b_g(s_q) (eta'.grad)(d_k S_g)
+//    - (eta.gphi_g) d_k S_g] with b_g(s) = (1 - s) vbar.A0_g + s vbar.A1_g, need
+//    per stencil row only the z-column sums of b0 = vbar.A0, b1 = vbar.A1 and
+//    eg = eta.gphi against Z and Z' at each point (and against Z'', the same at
+//    every point); the row's x and y factors then give the Hessian terms.
+// The same sums as a node-by-node evaluation, with about a quarter of its
+// arithmetic.
+template <class Sink>
+__device__ __forceinline__ void push_adjoint(const AdjParticleArgs& P, int64_t i,
+                                             const Sink& sink) {
   const Grid& G = P.G;
   const int64_t np = P.np, nc = G.ncell;
-  double x0[3], vb[3], d[3], eta[3] = {0.0, 0.0, 0.0};
+  double x0[3], vb[3], d[3], eta[3], ep[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     x0[a] = P.x[a * np + i];
     vb[a] = P.vb[a * np + i];
     d[a] = P.dt * vb[a];
-    if constexpr (ETA) eta[a] = P.qm * P.xi[a * np + i];
+    eta[a] = P.qm * P.xi[a * np + i];
+    ep[a] = eta[a] * G.invH[a];
   }
+  // piece terms of lx and ld per unit of cell coordinate (times dt / H_k below)
   double lx[3] = {0.0, 0.0, 0.0}, ld[3] = {0.0, 0.0, 0.0}, lvb[3] = {0.0, 0.0, 0.0};
   const bool ok = for_each_piece<2>(x0, d, G, [&](double s0, double s1, const double* base) {
     const double h = s1 - s0;
-    int first[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) first[a] = to_int_clamped(base[a]) + Spline<2>::first_off;
-    double sq[4], wq[4], tq[4][3];  // points, weights, stencil coordinates
+    double sq[4], wq[4], tx[4], ty[4], Z[4][3], dZ[4][3];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       sq[q] = s0 + 0.5 * h * (1.0 + Gauss<4>::x(q));
       wq[q] = 0.5 * h * Gauss<4>::w(q);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) tq[q][a] = (x0[a] + sq[q] * d[a]) * G.invH[a] - base[a];
+      tx[q] = (x0[0] + sq[q] * d[0]) * G.invH[0] - base[0];
+      ty[q] = (x0[1] + sq[q] * d[1]) * G.invH[1] - base[1];
+      Spline<2>::wd((x0[2] + sq[q] * d[2]) * G.invH[2] - base[2], Z[q], dZ[q]);
     }
+    const int fx = to_int_clamped(base[0]) + Spline<2>::first_off;
+    const int fy = to_int_clamped(base[1]) + Spline<2>::first_off;
+    const int fz = to_int_clamped(base[2]) + Spline<2>::first_off;
 #pragma unroll 1
-    for (int n = 0; n < 27; ++n) {
-      const int a = n / 9, b = (n / 3) % 3, c = n % 3;
-      const int64_t g = node_index(G, first[0] + a, first[1] + b, first[2] + c);
-      double A0g[3] = {0.0, 0.0, 0.0}, A1g[3] = {0.0, 0.0, 0.0}, mug[3] = {0.0, 0.0, 0.0};
-      double b0 = 0.0, b1 = 0.0, eg = 0.0, vm = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double ddX = a == 1 ? -2.0 : 1.0;
+      double Xq[4], dXq[4];
 #pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        if constexpr (ETA) {
-          A0g[l] = P.A0[l * nc + g];
-          A1g[l] = P.A1[l * nc + g];
-          b0 += vb[l] * A0g[l];
-          b1 += vb[l] * A1g[l];
-          eg += eta[l] * P.gphi[l * nc + g];
+      for (int q = 0; q < 4; ++q) Spline<2>::wk(a, tx[q], Xq[q], dXq[q]);
+#pragma unroll 1
+      for (int b = 0; b < 3; ++b) {
+        const double ddY = b == 1 ? -2.0 : 1.0;
+        double Yq[4], dYq[4], xy[4], dxy[4], xdy[4], pe[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          Spline<2>::wk(b, ty[q], Yq[q], dYq[q]);
+          xy[q] = Xq[q] * Yq[q];
+          dxy[q] = dXq[q] * Yq[q];
+          xdy[q] = Xq[q] * dYq[q];
+          pe[q] = ep[0] * dxy[q] + ep[1] * xdy[q];  // (eta'_x d_x + eta'_y d_y)(X Y)
         }
-        if constexpr (MU) {
-          mug[l] = P.mu[l * nc + g];
-          vm += vb[l] * mug[l];
-        }
-      }
-      double Sbar = 0.0, T0 = 0.0, T1 = 0.0;
+        double C0[4], C0d[4], C1[4], C1d[4], Eg[4], Egd[4], C0dd = 0.0, C1dd = 0.0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double wx, dwx, ddwx, wy, dwy, ddwy, wz, dwz, ddwz;
-        axis_node(a, tq[q][0], G.invH[0], wx, dwx, ddwx);
-        axis_node(b, tq[q][1], G.invH[1], wy, dwy, ddwy);
-        axis_node(c, tq[q][2], G.invH[2], wz, dwz, ddwz);
-        const double s = sq[q], wt = wq[q];
-        const double S = wx * wy * wz;
-        const double dS[3] = {dwx * wy * wz, wx * dwy * wz, wx * wy * dwz};
-        if constexpr (ETA) {
-          const double Hs[3][3] = {{ddwx * wy * wz, dwx * dwy * wz, dwx * wy * dwz},
-                                   {dwx * dwy * wz, wx * ddwy * wz, wx * dwy * dwz},
-                                   {dwx * wy * dwz, wx * dwy * dwz, wx * wy * ddwz}};
-          const double bg = (1.0 - s) * b0 + s * b1;  // vbar . A_g(s)
-          const double edS = eta[0] * dS[0] + eta[1] * dS[1] + eta[2] * dS[2];
-          const double c1 = P.dt * wt;
+        for (int c = 0; c < 3; ++c) {
+          const double ddZ = c == 1 ? -2.0 : 1.0;
+          const int ix = fx + a, iy = fy + b, iz = fz + c;
+          const int64_t g = node_index(G, ix, iy, iz);
+          double A0g[3], A1g[3];
+          double b0 = 0.0, b1 = 0.0, eg = 0.0;
 #pragma unroll
-          for (int kk = 0; kk < 3; ++kk) {
-            const double eH = eta[0] * Hs[0][kk] + eta[1] * Hs[1][kk] + eta[2] * Hs[2][kk];
-            const double f = c1 * (bg * eH - eg * dS[kk]);  // (D A)^T vbar, -gphibar
-            lx[kk] += f;
-            ld[kk] += s * f;
-            lvb[kk] += c1 * ((1.0 - s) * A0g[kk] + s * A1g[kk]) * edS;
+          for (int l = 0; l < 3; ++l) {
+            A0g[l] = P.A0[l * nc + g];
+            A1g[l] = P.A1[l * nc + g];
+            b0 += vb[l] * A0g[l];
+            b1 += vb[l] * A1g[l];
+            eg += eta[l] * P.gphi[l * nc + g];
           }
-          Sbar += wt * S;
-          T0 += wt * (1.0 - s) * edS;
-          T1 += wt * s * edS;
-        }
-        if constexpr (MU) {
+          double Sbar = 0.0, T0 = 0.0, T1 = 0.0;
 #pragma unroll
-          for (int l = 0; l < 3; ++l) lvb[l] += wt * mug[l] * S;
+          for (int q = 0; q < 4; ++q) {
+            const double z = Z[q][c], dz = dZ[q][c];
+            C0[q] = c == 0 ? b0 * z : C0[q] + b0 * z;
+            C0d[q] = c == 0 ? b0 * dz : C0d[q] + b0 * dz;
+            C1[q] = c == 0 ? b1 * z : C1[q] + b1 * z;
+            C1d[q] = c == 0 ? b1 * dz : C1d[q] + b1 * dz;
+            Eg[q] = c == 0 ? eg * z : Eg[q] + eg * z;
+            Egd[q] = c == 0 ? eg * dz : Egd[q] + eg * dz;
+            const double edS = pe[q] * z + ep[2] * xy[q] * dz;  // eta'.grad S
+            Sbar += wq[q] * xy[q] * z;
+            T0 += wq[q] * (1.0 - sq[q]) * edS;
+            T1 += wq[q] * sq[q] * edS;
+          }
+          C0dd += b0 * ddZ;
+          C1dd += b1 * ddZ;
 #pragma unroll
-          for (int kk = 0; kk < 3; ++kk) {
-            lx[kk] += wt * vm * dS[kk];
-            ld[kk] += wt * s * vm * dS[kk];
+          for (int l = 0; l < 3; ++l) {
+            lvb[l] += P.dt * (A0g[l] * T0 + A1g[l] * T1);
+            sink.add(l, ix, iy, iz, g, -P.dt * eta[l] * Sbar);
+            sink.add(3 + l, ix, iy, iz, g, P.dt * vb[l] * T0);
+            sink.add(6 + l, ix, iy, iz, g, P.dt * vb[l] * T1);
           }
         }
-      }
-      if constexpr (ETA) {
-        const int ix = first[0] + a, iy = first[1] + b, iz = first[2] + c;
+        // the row's share of sum_g b (eta'.grad)(d_k S_g) (with b0 and b1) and
+        // of sum_g eg d_k S_g, per point
 #pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          sink.add(l, ix, iy, iz, g, -P.dt * eta[l] * Sbar);
-          sink.add(3 + l, ix, iy, iz, g, P.dt * vb[l] * T0);
-          sink.add(6 + l, ix, iy, iz, g, P.dt * vb[l] * T1);
+        for (int q = 0; q < 4; ++q) {
+          const double dxdy = dXq[q] * dYq[q];
+          // (eta'.grad)(d_k S) summed over the row against b0 and b1
+          const double hx = ep[0] * ddX * Yq[q] + ep[1] * dxdy;     // with Z
+          const double hy = ep[0] * dxdy + ep[1] * Xq[q] * ddY;     // with Z
+          const double u0x = hx * C0[q] + ep[2] * dxy[q] * C0d[q];
+          const double u0y = hy * C0[q] + ep[2] * xdy[q] * C0d[q];
+          const double u0z = pe[q] * C0d[q] + ep[2] * xy[q] * C0dd;
+          const double u1x = hx * C1[q] + ep[2] * dxy[q] * C1d[q];
+          const double u1y = hy * C1[q] + ep[2] * xdy[q] * C1d[q];
+          const double u1z = pe[q] * C1d[q] + ep[2] * xy[q] * C1dd;
+          // d_k S summed over the row against eg
+          const double vx = dxy[q] * Eg[q], vy = xdy[q] * Eg[q], vz = xy[q] * Egd[q];
+          const double q0 = wq[q] * (1.0 - sq[q]), q1 = wq[q] * sq[q];
+          lx[0] += q0 * u0x + q1 * u1x - wq[q] * vx;
+          lx[1] += q0 * u0y + q1 * u1y - wq[q] * vy;
+          lx[2] += q0 * u0z + q1 * u1z - wq[q] * vz;
+          ld[0] += sq[q] * (q0 * u0x + q1 * u1x - wq[q] * vx);
+          ld[1] += sq[q] * (q0 * u0y + q1 * u1y - wq[q] * vy);
+          ld[2] += sq[q] * (q0 * u0z + q1 * u1z - wq[q] * vz);
         }
       }
     }
   });
-  if constexpr (ETA) {  // + A0_h(x0) - A1_h(x0 + d), end point wrapped
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const double sgn = e == 0 ? 1.0 : -1.0;
-      const double* F = e == 0 ? P.A0 : P.A1;
-      double base[3];
-      int first[3], sh[3];
-      Axis2 ax[3];
+  for (int k = 0; k < 3; ++k) {
+    lx[k] *= P.dt * G.invH[k];
+    ld[k] *= P.dt * G.invH[k];
+  }
+  // + A0_h(x0) - A1_h(x0 + d), end point wrapped
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double xp = e == 0 ? x0[a] : wrap_pos(x0[a] + d[a], G.L[a], G.invL[a]);
-        const double u = xp * G.invH[a];
-        base[a] = floor(u + Spline<2>::base_off);
-        first[a] = to_int_clamped(base[a]) + Spline<2>::first_off;
-        ax[a].at(u - base[a], G.invH[a]);
-        // periods between the wrapped end point and the unwrapped orbit end
-        sh[a] = e == 0 ? 0 : (int)rint((x0[a] + d[a] - xp) * G.invL[a]) * G.n[a];
-      }
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-          for (int c = 0; c < 3; ++c) {
-            const int64_t g = node_index(G, first[0] + a, first[1] + b, first[2] + c);
-            const double S = ax[0].w[a] * ax[1].w[b] * ax[2].w[c];
-            const double dS[3] = {ax[0].dw[a] * ax[1].w[b] * ax[2].w[c],
-                                  ax[0].w[a] * ax[1].dw[b] * ax[2].w[c],
-                                  ax[0].w[a] * ax[1].w[b] * ax[2].dw[c]};
-            double eF = 0.0;
+  for (int e = 0; e < 2; ++e) {
+    const double sgn = e == 0 ? 1.0 : -1.0;
+    const double* F = e == 0 ? P.A0 : P.A1;
+    double base[3];
+    int first[3], sh[3];
+    Axis2 ax[3];
 #pragma unroll
-            for (int l = 0; l < 3; ++l) {
-              eF += eta[l] * F[l * nc + g];
-              sink.add((e == 0 ? 3 : 6) + l, first[0] + a + sh[0], first[1] + b + sh[1],
-                       first[2] + c + sh[2], g, sgn * eta[l] * S);
-            }
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) {
-              lx[kk] += sgn * eF * dS[kk];
-              if (e == 1) ld[kk] += sgn * eF * dS[kk];
-            }
-          }
+    for (int a = 0; a < 3; ++a) {
+      const double xp = e == 0 ? x0[a] : wrap_pos(x0[a] + d[a], G.L[a], G.invL[a]);
+      const double u = xp * G.invH[a];
+      base[a] = floor(u + Spline<2>::base_off);
+      first[a] = to_int_clamped(base[a]) + Spline<2>::first_off;
+      ax[a].at(u - base[a], G.invH[a]);
+      // periods between the wrapped end point and the unwrapped orbit end
+      sh[a] = e == 0 ? 0 : (int)rint((x0[a] + d[a] - xp) * G.invL[a]) * G.n[a];
     }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        for (int c = 0; c < 3; ++c) {
+          const int64_t g = node_index(G, first[0] + a, first[1] + b, first[2] + c);
+          const double S = ax[0].w[a] * ax[1].w[b] * ax[2].w[c];
+          const double dS[3] = {ax[0].dw[a] * ax[1].w[b] * ax[2].w[c],
+                                ax[0].w[a] * ax[1].dw[b] * ax[2].w[c],
+                                ax[0].w[a] * ax[1].w[b] * ax[2].dw[c]};
+          double eF = 0.0;
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            eF += eta[l] * F[l * nc + g];
+            sink.add((e == 0 ? 3 : 6) + l, first[0] + a + sh[0], first[1] + b + sh[1],
+                     first[2] + c + sh[2], g, sgn * eta[l] * S);
+          }
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk) {
+            lx[kk] += sgn * eF * dS[kk];
+            if (e == 1) ld[kk] += sgn * eF * dS[kk];
+          }
+        }
   }
   if (!ok) P.bad[0] = 1.0;
 #pragma unroll
@@ -252,11 +256,100 @@ __device__ __forceinline__ void particle_adjoint(const AdjParticleArgs& P, int64
   }
 }
 
-template <bool ETA, bool MU>
-__global__ __launch_bounds__(kBlock) void k_particle_adjoint(AdjParticleArgs P) {
-  const int64_t i = adjoint_particle<ETA>(P.np);
+// The current terms alone (eta = 0: the current's adjoint mu seen by one
+// particle), in the tensor-product form of the forward gather: per stencil
+// row (a, b) the x and y factors of every quadrature point are formed once,
+// and per node only the seven point sums
+//   I = sum_q w_q X Y Z,  I_k = sum_q w_q d_k(X Y Z),  I_k^s = sum_q w_q s_q d_k(X Y Z)
+// (derivatives per unit of cell coordinate, scaled by 1/H once per particle)
+// meet the node's mu:  lvbar += mu_g I,  lx += (vbar . mu_g) I_k,
+// ld += (vbar . mu_g) I_k^s.  The same sums as the node-by-node form above,
+// with about a third of its arithmetic.
+__global__ __launch_bounds__(kBlock) void k_current_adjoint(AdjParticleArgs P) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= P.np) return;
-  particle_adjoint<ETA, MU>(P, i, GlobalAdjSink{&P});
+  const Grid& G = P.G;
+  const int64_t np = P.np, nc = G.ncell;
+  double x0[3], vb[3], d[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    x0[a] = P.x[a * np + i];
+    vb[a] = P.vb[a * np + i];
+    d[a] = P.dt * vb[a];
+  }
+  double lx[3] = {0.0, 0.0, 0.0}, ld[3] = {0.0, 0.0, 0.0}, lvb[3] = {0.0, 0.0, 0.0};
+  const bool ok = for_each_piece<2>(x0, d, G, [&](double s0, double s1, const double* base) {
+    const double h = s1 - s0;
+    double sq[4], wq[4], tx[4], ty[4], Z[4][3], dZ[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sq[q] = s0 + 0.5 * h * (1.0 + Gauss<4>::x(q));
+      wq[q] = 0.5 * h * Gauss<4>::w(q);
+      tx[q] = (x0[0] + sq[q] * d[0]) * G.invH[0] - base[0];
+      ty[q] = (x0[1] + sq[q] * d[1]) * G.invH[1] - base[1];
+      Spline<2>::wd((x0[2] + sq[q] * d[2]) * G.invH[2] - base[2], Z[q], dZ[q]);
+    }
+    const int fx = to_int_clamped(base[0]) + Spline<2>::first_off;
+    const int fy = to_int_clamped(base[1]) + Spline<2>::first_off;
+    const int fz = to_int_clamped(base[2]) + Spline<2>::first_off;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double Xw[4], dXw[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double Xq, dXq;
+        Spline<2>::wk(a, tx[q], Xq, dXq);
+        Xw[q] = wq[q] * Xq;
+        dXw[q] = wq[q] * dXq;
+      }
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        double xyw[4], dxyw[4], xdyw[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double Yq, dYq;
+          Spline<2>::wk(b, ty[q], Yq, dYq);
+          xyw[q] = Xw[q] * Yq;
+          dxyw[q] = dXw[q] * Yq;
+          xdyw[q] = Xw[q] * dYq;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int64_t g = node_index(G, fx + a, fy + b, fz + c);
+          const double m0 = P.mu[g], m1 = P.mu[nc + g], m2 = P.mu[2 * nc + g];
+          const double vm = vb[0] * m0 + vb[1] * m1 + vb[2] * m2;
+          double I = 0.0, Ix = 0.0, Iy = 0.0, Iz = 0.0, Ixs = 0.0, Iys = 0.0, Izs = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double zx = dxyw[q] * Z[q][c], zy = xdyw[q] * Z[q][c], zz = xyw[q] * dZ[q][c];
+            I += xyw[q] * Z[q][c];
+            Ix += zx;
+            Iy += zy;
+            Iz += zz;
+            Ixs += sq[q] * zx;
+            Iys += sq[q] * zy;
+            Izs += sq[q] * zz;
+          }
+          lvb[0] += m0 * I;
+          lvb[1] += m1 * I;
+          lvb[2] += m2 * I;
+          lx[0] += vm * Ix;
+          lx[1] += vm * Iy;
+          lx[2] += vm * Iz;
+          ld[0] += vm * Ixs;
+          ld[1] += vm * Iys;
+          ld[2] += vm * Izs;
+        }
+      }
+    }
+  });
+  if (!ok) P.bad[0] = 1.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    P.lx[a * np + i] += lx[a] * G.invH[a];
+    P.ld[a * np + i] += ld[a] * G.invH[a];
+    P.lvb[a * np + i] += lvb[a];
+  }
 }
 
 // The push terms over cell-sorted particles, one block per chunk of kAdjChunk
@@ -338,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_push_adjoint_tiled(AdjParticleArgs P
       // particle frame -> chunk frame -> tile
       sink.o[a] = min_image(raw, G.n[a]) - raw - s_ref[a] - tlo[a];
     }
-    particle_adjoint<true, false>(P, i, sink);
+    push_adjoint(P, i, sink);
   }
   __syncthreads();
   if (!use_tile) return;
@@ -417,14 +510,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_out(int64_t n3, const double
 
 void launch_particle_adjoint(hipStream_t s, const AdjParticleArgs& P, bool eta, bool mu) {
   if (P.np <= 0) return;
-  // the spread lanes of the scattering kernels cover 64 ceil(np / 64) threads
-  const unsigned spread = blocks_for(kWave * ((P.np + kWave - 1) / kWave));
-  if (eta && mu)
-    k_particle_adjoint<true, true><<<spread, kBlock, 0, s>>>(P);
-  else if (eta)
+  if (eta)
     k_push_adjoint_tiled<<<(unsigned)((P.np + kAdjChunk - 1) / kAdjChunk), kBlock, 0, s>>>(P);
-  else if (mu)
-    k_particle_adjoint<false, true><<<blocks_for(P.np), kBlock, 0, s>>>(P);
+  if (mu) k_current_adjoint<<<blocks_for(P.np), kBlock, 0, s>>>(P);
 }
 
 void launch_vbar(hipStream_t s, int64_t n3, const double* w, const double* v, double* vb) {

@@ -309,7 +309,8 @@ struct AdjParticleArgs {
   double* lA1;
   double* bad;         // set to 1 if an orbit had too many pieces
 };
-// eta: push terms with xi; mu: current terms
+// eta: push terms with xi (fast for cell-ordered particles: local chunks fit
+// an LDS tile); mu: current terms
 void launch_particle_adjoint(hipStream_t s, const AdjParticleArgs& P, bool eta, bool mu);
 void launch_vbar(hipStream_t s, int64_t n3, const double* w, const double* v, double* vb);
 void launch_adjoint_rhs(hipStream_t s, int64_t n3, double dt, const double* lx1, const double* lv1,
