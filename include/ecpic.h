@@ -302,8 +302,10 @@ ecpic_status ecpic_get_profile(ecpic_sim* sim, ecpic_profile* out);
      tol          stop when max|xi^{k+1} - xi^k| <= tol max|xi^{k+1}|
      max_iters    iteration bound (ECPIC_ENOCONV if reached; outputs still set)
    workspace: caller-owned device buffer of ecpic_adjoint_workspace_bytes()
-   bytes (256-byte aligned).  The simulation's own state is not changed; its
-   scratch is reused. */
+   bytes (256-byte aligned; 372 B per particle plus the mesh arrays).
+   Inside the call the particles are sorted by cell (the kernels work on
+   local chunks); the outputs come back in the caller's order.  The
+   simulation's own state is not changed; its scratch is reused. */
 typedef struct {
   int32_t iters;     /* transposed Picard iterations */
   int32_t converged; /* 1 if tol was reached */
@@ -328,8 +330,8 @@ ecpic_status ecpic_adjoint_step(ecpic_sim* sim, void* workspace, size_t workspac
    The call allocates nothing (no hipMalloc, hipFree or allocating library
    routine).
      - ECPIC_ENOMEM if ecpic_adjoint_workspace_bytes() of this simulation
-       exceeds ECPIC_STATIC_SCRATCH_BYTES (about 150,000 particles on a 32^3
-       mesh, 300,000 on 16^3); nothing is run.
+       exceeds ECPIC_STATIC_SCRATCH_BYTES (about 76,000 particles on a 32^3
+       mesh, 167,000 on 16^3); nothing is run.
      - ECPIC_EINVAL if the device current at ecpic_create() is not current.
    Every call on one GPU uses that GPU's one array and leaves its contents
    behind (each call writes every part it reads before reading it): calls

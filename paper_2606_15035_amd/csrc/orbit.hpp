@@ -307,11 +307,11 @@ __device__ __forceinline__ bool for_each_piece(const double* x0, const double* d
 // Base node of the stencil of the point at s (the rule over the whole orbit
 // without splitting, where every point takes the stencil of its own cell).
 template <int R>
-__device__ __forceinline__ void piece_base(const double* x0, const double* d, double smid,
+__device__ __forceinline__ void point_base(const double* x0, const double* d, double s,
                                            const Grid& G, double* base) {
 #pragma unroll
   for (int a = 0; a < 3; ++a)
-    base[a] = floor((x0[a] + smid * d[a]) * G.invH[a] + Spline<R>::base_off);
+    base[a] = floor((x0[a] + s * d[a]) * G.invH[a] + Spline<R>::base_off);
 }
 
 }  // namespace ecpic

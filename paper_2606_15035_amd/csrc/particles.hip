@@ -154,7 +154,7 @@ __device__ __forceinline__ void unsplit_point(const Grid& G, const QuadRule& rul
                                               double& s, double& w) {
   s = rule.s[q];
   w = rule.w[q];
-  piece_base<R>(x0, d, s, G, base);
+  point_base<R>(x0, d, s, G, base);
 }
 
 template <int R>
