@@ -37,9 +37,9 @@ PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
 
-def survey_flops_per_push(r: int, pieces_per_orbit: float, nq: int | None = None) -> float:
+def algorithmic_flops_per_push(r: int, pieces_per_orbit: float, nq: int | None = None) -> float:
     """Algorithmic FP64 operations (an FMA counts 2) of the orbit gather + push
-    per particle-push as the scope table of the hot path counts them: per orbit
+    per particle-push, every term of the method counted on its own: per orbit
     piece n_q [3 s^3 + 3 (2 s^3 + 3 s^2 + 3 s) + s^3] + 3 s^3 FMA (the
     tensor-product sums of grad phi-bar and D A with A^n, A^{n+1}), per particle
     the end-point interpolant 3 s^3 FMA and ~100 flops of breakpoints and push,
@@ -54,7 +54,7 @@ def kernel_flops_per_push(r: int, pieces_per_orbit: float) -> float:
     """FP64 operations the kernel k_gather_push actually performs per
     particle-push (an FMA counts 2): it contracts A^n, A^{n+1} with vbar at each
     node first and sums along z columns first, so it needs fewer than the
-    scope-table count.  Per orbit piece (r = 2, 4-point rule, 3x3x3 nodes):
+    algorithmic count.  Per orbit piece (r = 2, 4-point rule, 3x3x3 nodes):
     quadrature positions and z weights 123; x weights 3 x 24; per z column (9)
     y weights and column products 28 + closing (D A)^T vbar sums 24; per node
     (27) vbar . A^n and vbar . (A^{n+1} - A^n) 11, per quadrature point I,
@@ -149,12 +149,12 @@ def gather_roofline(E, wl, sim, steps, mixed=False):
     g = prof["gather_push"]
     avg_s = g["ms"] / max(g["launches"], 1) * 1e-3
     ppo = prof["pieces"] / max(wl.np * g["launches"], 1)
-    achieved = survey_flops_per_push(wl.r, ppo) * wl.np / avg_s / 1e12
+    achieved = algorithmic_flops_per_push(wl.r, ppo) * wl.np / avg_s / 1e12
     kernel = kernel_flops_per_push(wl.r, ppo) * wl.np / avg_s / 1e12
     hbm = gather_bytes_per_push(mixed) * wl.np / avg_s / 1e9
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "flops_per_push": survey_flops_per_push(wl.r, ppo),
+            "flops_per_push": algorithmic_flops_per_push(wl.r, ppo),
             "kernel_flops_per_push": kernel_flops_per_push(wl.r, ppo),
             "kernel_count_achieved": kernel, "kernel_count_frac": kernel / PEAK_FP64_TFLOPS,
             "avg_launch_ms": avg_s * 1e3, "launches": g["launches"], "steps": steps,
