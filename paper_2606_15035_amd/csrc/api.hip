@@ -1441,6 +1441,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.17"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.18"; }
 
 }  // extern "C"
