@@ -235,6 +235,7 @@ struct ecpic_sim {
   double* realbuf;
   double* Uhalf;
   int* gwork;  // gather work list: [count, indices of blocks whose box missed the LDS tile]
+  int* sboxes;  // node boxes of the scatter's chunks, found in a step's first pass
   double2* tw[3];
   Scratch sc;
   double* host = nullptr;  // pinned read-back
@@ -333,6 +334,7 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   S->Uhalf = w.take<double>(3 * nc);
   for (int a = 0; a < 3; ++a) S->tw[a] = w.take<double2>(S->G.n[a] / 2);
   S->gwork = w.take<int>(particle_blocks(np) + 1);
+  S->sboxes = w.take<int>((size_t)kBoxInts * std::max<int64_t>(scatter_blocks(np, 2048), 1));
   // the plain iteration's next iterate is the gather's output, so the gather
   // (and the step's set-up) can hand the scatter vbar^p directly
   S->vbar = S->cfg.anderson_depth == 0 ? w.take<double>(n3) : nullptr;
@@ -736,7 +738,7 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     on_store(S, [&](auto& st, auto&) {  // J^{n+1/2,p}
       CurrentOut o = cout;
       o.J = J;
-      launch_scatter(s, r, P, st, S->vit, S->vbar, o, S->sc);
+      launch_scatter(s, r, P, st, S->vit, S->vbar, o, S->sc, ChunkBoxes{S->sboxes, p >= 1});
     });
     if (S->mixed()) launch_fixed_current(s, 3 * nc, S->Jfix, J, fix_unit);
     if (prof) HIPCHK(hipEventRecord(S->ev[1], s));
@@ -1441,6 +1443,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.18"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.19"; }
 
 }  // extern "C"

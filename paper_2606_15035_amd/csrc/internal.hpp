@@ -156,11 +156,22 @@ struct CurrentOut {
 template <class PS>
 void launch_extrapolate(hipStream_t s, int64_t np, const PS& st, double* vit,
                         double* vbar = nullptr);
+// Node boxes of the scatter's chunks, kBoxInts ints per chunk (reference
+// cell, box origin and extents, each per axis).  With box non-null and reuse
+// zero the scatter finds each chunk's box from its orbits and stores it; with
+// reuse non-zero it takes the stored box (x^n, and with it the chunk's
+// cells, is the same in every pass of a step; an orbit whose stencil leaves
+// the stored box goes through the scatter's global-memory path).
+constexpr int kBoxInts = 12;
+struct ChunkBoxes {
+  int* box = nullptr;
+  int reuse = 0;
+};
 // Orbit current of iterate vit; with vbar non-null, vbar^p (3 x np) is read
 // from there instead of being formed from v^n and vit
 template <class PS>
 void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
-                    const double* vbar, CurrentOut out, Scratch sc);
+                    const double* vbar, CurrentOut out, Scratch sc, ChunkBoxes bx = {});
 // Iterate and image of the previous Picard pass: with w non-null the gather
 // also writes the block partial sums dF . dF and dF . f_p of Anderson mixing
 // over one difference (dF = f_p - f_{p-1}, f = image - iterate) to site P_AA.

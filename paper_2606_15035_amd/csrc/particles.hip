@@ -570,7 +570,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((
     amdgpu_waves_per_eu(ScatterChunk<R, CH>::kWavesPerSimd))) void k_scatter(StepParams P, PS st,
                                                    const double* __restrict__ vit,
                                                    const double* __restrict__ vbar,
-                                                   CurrentOut out, Scratch sc) {
+                                                   CurrentOut out, Scratch sc,
+                                                   ChunkBoxes bx) {
   constexpr int W = R + 1;
   constexpr bool FIX = PS::kMixed;  // int64 fixed-point deposit
   constexpr int kTileNodes = ScatterChunk<R, CH>::kTileNodes;
@@ -582,35 +583,46 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   double js[1] = {0.0};
   double bad = 0.0;
   late_reduce_init<2>();
-  if (threadIdx.x == 0) {  // the chunk's first particle is the reference cell
-    double x0[3];
-    st.x_of(P.G, P.np, base, x0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-      s_ref[a] = to_int_clamped(floor(x0[a] * P.G.invH[a] + Spline<R>::base_off));
-  }
-  __syncthreads();
-  // pass 1: node box of the chunk's orbits
-  int rmin[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff}, rmax[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
-  for (int k = 0; k < kPerThread; ++k) {
-    const int64_t i = chunk_particle<CH>(base, k);
-    if (i >= P.np) continue;
-    double x0[3], d[3], vb[3];
-    orbit_of(P, st, vit, vbar, i, x0, d, vb);
-    const double vmax = fmax(fabs(vb[0]), fmax(fabs(vb[1]), fabs(vb[2])));
-    js[0] += (MULTI ? species_value(P.aq, st.species(i)) : P.aq[0]) * vmax;
+  // the chunk's node box: reference cell sref (that of the chunk's first
+  // particle), origin tlo relative to it and extents dim, per axis
+  int sref[3], tlo[3], dim[3];
+  if (bx.reuse) {  // found by this chunk in the step's first pass
+    const int* b = bx.box + (int64_t)blockIdx.x * kBoxInts;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const double u0 = x0[a] * P.G.invH[a], u1 = (x0[a] + d[a]) * P.G.invH[a];
-      const int lo = to_int_clamped(floor(fmin(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off - 1;
-      const int hi = to_int_clamped(floor(fmax(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off + W;
-      const int rel = min_image(lo - s_ref[a], P.G.n[a]);
-      rmin[a] = min(rmin[a], rel);
-      rmax[a] = max(rmax[a], rel + (hi - lo));
+      sref[a] = b[a];
+      tlo[a] = b[3 + a];
+      dim[a] = b[6 + a];
     }
-  }
-  int tlo[3], dim[3];
-  {
+  } else {
+    if (threadIdx.x == 0) {
+      double x0[3];
+      st.x_of(P.G, P.np, base, x0);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        s_ref[a] = to_int_clamped(floor(x0[a] * P.G.invH[a] + Spline<R>::base_off));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sref[a] = s_ref[a];
+    // pass 1: the box of the nodes the chunk's orbits touch
+    int rmin[3] = {0x3fffffff, 0x3fffffff, 0x3fffffff};
+    int rmax[3] = {-0x3fffffff, -0x3fffffff, -0x3fffffff};
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t i = chunk_particle<CH>(base, k);
+      if (i >= P.np) continue;
+      double x0[3], d[3], vb[3];
+      orbit_of(P, st, vit, vbar, i, x0, d, vb);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double u0 = x0[a] * P.G.invH[a], u1 = (x0[a] + d[a]) * P.G.invH[a];
+        const int lo = to_int_clamped(floor(fmin(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off - 1;
+        const int hi = to_int_clamped(floor(fmax(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off + W;
+        const int rel = min_image(lo - sref[a], P.G.n[a]);
+        rmin[a] = min(rmin[a], rel);
+        rmax[a] = max(rmax[a], rel + (hi - lo));
+      }
+    }
     int mv[6] = {rmin[0], rmin[1], rmin[2], -rmax[0], -rmax[1], -rmax[2]};
     block_min_ints<6>(mv);
 #pragma unroll
@@ -618,6 +630,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((
       tlo[a] = mv[a];
       dim[a] = -mv[3 + a] - tlo[a] + 1;
     }
+    if (bx.box && threadIdx.x == 0) {
+      int* b = bx.box + (int64_t)blockIdx.x * kBoxInts;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        b[a] = sref[a];
+        b[3 + a] = tlo[a];
+        b[6 + a] = dim[a];
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {  // block-uniform
+    sref[a] = __builtin_amdgcn_readfirstlane(sref[a]);
+    tlo[a] = __builtin_amdgcn_readfirstlane(tlo[a]);
+    dim[a] = __builtin_amdgcn_readfirstlane(dim[a]);
   }
   // block-uniform; each extent is bounded first so that the product cannot overflow
   const bool use_tile = dim[0] > 0 && dim[0] <= kTileNodes && dim[1] <= kTileNodes &&
@@ -639,6 +666,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((
     if (i >= P.np) return false;
     double x0[3], d[3], vb[3], c3[3];
     orbit_of(P, st, vit, vbar, i, x0, d, vb);
+    if (!GLOBAL) {  // J_s: q_i max_a |vbar_a|, once per particle
+      const double vmax = fmax(fabs(vb[0]), fmax(fabs(vb[1]), fabs(vb[2])));
+      js[0] += (MULTI ? species_value(P.aq, st.species(i)) : P.aq[0]) * vmax;
+    }
     // FP64: q_i vbar / dV; fixed point: (q_i / q_0) vbar in units of the quantum
     const double cq = MULTI ? species_value(P.cq, st.species(i)) : P.cq[0];
     int shift[3];
@@ -647,13 +678,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((
       c3[a] = cq * vb[a];
       const double u0 = x0[a] * P.G.invH[a], u1 = (x0[a] + d[a]) * P.G.invH[a];
       const int lo = to_int_clamped(floor(fmin(u0, u1) + Spline<R>::base_off)) + Spline<R>::first_off - 1;
-      const int raw = lo - s_ref[a];
+      const int raw = lo - sref[a];
       shift[a] = min_image(raw, P.G.n[a]) - raw;  // particle frame -> chunk frame
     }
     auto deposit = [&](const double (&Iw)[W][W][W], const int* f) {
-      const int ox = f[0] - s_ref[0] + shift[0] - tlo[0];
-      const int oy = f[1] - s_ref[1] + shift[1] - tlo[1];
-      const int oz = f[2] - s_ref[2] + shift[2] - tlo[2];
+      const int ox = f[0] - sref[0] + shift[0] - tlo[0];
+      const int oy = f[1] - sref[1] + shift[1] - tlo[1];
+      const int oz = f[2] - sref[2] + shift[2] - tlo[2];
       const bool inside = use_tile && ox >= 0 && oy >= 0 && oz >= 0 && ox + W <= dim[0] &&
                           oy + W <= dim[1] && oz + W <= dim[2];
       outside = outside || !inside;
@@ -701,9 +732,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((
                                 const double (&Y)[Quad<R>::NQ][W],
                                 const double (&Z)[Quad<R>::NQ][W], const int* f) {
       constexpr int NQ = Quad<R>::NQ;
-      const int ox = f[0] - s_ref[0] + shift[0] - tlo[0];
-      const int oy = f[1] - s_ref[1] + shift[1] - tlo[1];
-      const int oz = f[2] - s_ref[2] + shift[2] - tlo[2];
+      const int ox = f[0] - sref[0] + shift[0] - tlo[0];
+      const int oy = f[1] - sref[1] + shift[1] - tlo[1];
+      const int oz = f[2] - sref[2] + shift[2] - tlo[2];
       const bool inside = use_tile && ox >= 0 && oy >= 0 && oz >= 0 && ox + W <= dim[0] &&
                           oy + W <= dim[1] && oz + W <= dim[2];
       outside = outside || !inside;
@@ -780,9 +811,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((
         int f[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) f[a] = to_int_clamped(base[a]) + Spline<R>::first_off;
-        const int ox = f[0] - s_ref[0] + shift[0] - tlo[0];
-        const int oy = f[1] - s_ref[1] + shift[1] - tlo[1];
-        const int oz = f[2] - s_ref[2] + shift[2] - tlo[2];
+        const int ox = f[0] - sref[0] + shift[0] - tlo[0];
+        const int oy = f[1] - sref[1] + shift[1] - tlo[1];
+        const int oz = f[2] - sref[2] + shift[2] - tlo[2];
         const bool inside = use_tile && ox >= 0 && oy >= 0 && oz >= 0 && ox + W <= dim[0] &&
                             oy + W <= dim[1] && oz + W <= dim[2];
         outside = outside || !inside;
@@ -858,8 +889,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((
   for (int t = threadIdx.x; t < nt; t += kBlock) {
     const int q = div_small(t, inv_d2), cx = div_small(q, inv_d1);
     const int cz = t - q * dim[2], cy = q - cx * dim[1];
-    const int64_t g = node_index(P.G, s_ref[0] + tlo[0] + cx, s_ref[1] + tlo[1] + cy,
-                                 s_ref[2] + tlo[2] + cz);
+    const int64_t g = node_index(P.G, sref[0] + tlo[0] + cx, sref[1] + tlo[1] + cy,
+                                 sref[2] + tlo[2] + cz);
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       if constexpr (FIX) {
@@ -1418,7 +1449,7 @@ void launch_extrapolate(hipStream_t s, int64_t np, const PS& st, double* vit, do
 
 template <class PS>
 void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
-                    const double* vbar, CurrentOut out, Scratch sc) {
+                    const double* vbar, CurrentOut out, Scratch sc, ChunkBoxes bx) {
   if (P.np <= 0) return;
   const bool multi = P.nsp > 1;
   // degree x (split) x species x chunk length (4096 for r <= 2 only; the
@@ -1427,7 +1458,7 @@ void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, con
     auto launch = [&](auto MULTI, auto CH) {
       const unsigned nblk = (unsigned)scatter_blocks(P.np, CH.value);
       k_scatter<R.value, PS, SPLIT.value, MULTI.value, CH.value>
-          <<<nblk, kBlock, 0, s>>>(P, st, vit, vbar, out, sc);
+          <<<nblk, kBlock, 0, s>>>(P, st, vit, vbar, out, sc, bx);
     };
     auto by_multi = [&](auto CH) {
       if (multi)
@@ -1532,7 +1563,7 @@ void launch_fixed_current(hipStream_t s, int64_t n, unsigned long long* Jfix, do
 #define ECPIC_INSTANTIATE_STORE(PS)                                                              \
   template void launch_extrapolate<PS>(hipStream_t, int64_t, const PS&, double*, double*);                \
   template void launch_scatter<PS>(hipStream_t, int, const StepParams&, const PS&, const double*, \
-                                   const double*, CurrentOut, Scratch);                          \
+                                   const double*, CurrentOut, Scratch, ChunkBoxes);              \
   template void launch_gather_push<PS>(hipStream_t, int, const StepParams&, const PS&,           \
                                        const double*, double*, double*, const double*, int*,     \
                                        Scratch, AndersonPrev);                                   \

@@ -66,6 +66,40 @@ def test_mixed_step_matches_oracle(name, r, chunk):
     check_mixed_step(wl, x, v, sg, so, g.get_current(), o.current(), log, name)
 
 
+def test_mixed_later_passes_outside_the_first_pass_boxes():
+    """The setting of the FP64 parity test of the same name: a three-cell
+    drift along x and v^{n-1} = 4 v^n, so the later Picard passes' orbits
+    leave the node boxes the scatter found in the first pass.  The mixed step
+    matches the oracle; and since the fixed-point current is an exact integer
+    sum, the step is bitwise the same with 2048- and 4096-particle chunks,
+    whose boxes, and the pieces they send through the global-memory path,
+    differ."""
+    wl = W.random_plasma((16, 4, 4), (2.0, 0.5, 0.5), 9000, r=2, dt=0.25, vth=0.06,
+                         drift=(1.5, -0.02, 0.01), seed=29)
+    x, v = to_storage(wl, wl.x, wl.v)
+    vprev = 4.0 * v  # exact in the FP32 storage
+    oargs = wl.cfg_kwargs()
+    oargs.update(tol=0.0, pmax=2)
+    o = O.OracleSim(O.make_cfg(**oargs), wl.np)
+    o.init_particles(x, v, wl.q, wl.m, wl.n0)
+    o.set_state(None, None, vprev, None, None, wl.q, wl.m)
+    assert o.step()["iters"] == 3
+    so = o.get_state()
+    runs = []
+    for chunk in (2048, 4096):
+        g = E.Sim(mixed_cfg(wl, tol=0.0, pmax=2, scatter_chunk=chunk), wl.np)
+        g.init_particles(x, v, wl.q, wl.m, wl.n0)
+        g.set_state(vprev=vprev)
+        assert g.picard_step()["iters"] == 3
+        sg = g.get_state()
+        check_mixed_step(wl, x, v, sg, so, g.get_current(), o.current(), log,
+                         f"boxes of the first pass, chunk {chunk}", pieces=6)
+        runs.append((sg["x"], sg["v"], sg["fields"], g.get_current()))
+        g.close()
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+
+
 def test_mixed_step_is_independent_of_particle_order():
     """The fixed-point current is an exact integer sum, so a mixed step gives
     bitwise the same current, fields and particle state whatever the order in

@@ -341,6 +341,29 @@ def test_step_parity_with_each_scatter_chunk(r, chunk):
         compare_states(wl, g, o, f"r={r} chunk={chunk} step {step}")
 
 
+@pytest.mark.parametrize("r,chunk", [(1, 2048), (2, 2048), (2, 4096), (3, 2048)])
+def test_later_passes_with_orbits_outside_the_first_pass_boxes(r, chunk):
+    """The scatter finds each chunk's node box in the first Picard pass of a
+    step and takes it again in the later passes.  Here every particle drifts
+    three cells per step along x (H / dt = 0.5, drift 1.5, thermal spread
+    0.06) and v^{n-1} = 4 v^n, so the first guess 2 v^n - v^{n-1} is -2 v^n:
+    the first pass's orbits run about 1.5 cells backwards, the later passes'
+    about 3 cells forwards.  Every particle that starts within about two
+    cells of the top of its chunk's box then has pieces outside the box in
+    the later passes (several hundred per chunk, every chunk), which the
+    scatter adds through its global-memory path.  The x axis (16 cells) is
+    longer than any chunk's box, so no box wraps around it.  The step agrees
+    with the oracle at 1e-12."""
+    wl = W.random_plasma((16, 4, 4), (2.0, 0.5, 0.5), 9000, r=r, dt=0.25, vth=0.06,
+                         drift=(1.5, -0.02, 0.01), seed=29)
+    g, o = both(wl, tol=0.0, pmax=2, scatter_chunk=chunk)
+    vprev = 4.0 * wl.v
+    g.set_state(vprev=vprev)
+    o.set_state(None, None, vprev, None, None, wl.q, wl.m)
+    assert g.picard_step()["iters"] == o.step()["iters"] == 3
+    compare_states(wl, g, o, f"boxes of the first pass r={r} chunk={chunk}")
+
+
 @pytest.mark.parametrize("r", [1, 2, 3])
 def test_step_parity_tolerance_mode_and_energy(r):
     wl = small_random(r, seed=9)
