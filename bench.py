@@ -83,8 +83,8 @@ def gather_bytes_per_push(mixed: bool = False) -> float:
 # same counters read for a streaming kernel of known size (k_finalize: fetch
 # 2.00 x, write 1.00 x).  A property of the kernel: valid for the library
 # version it was measured on only (otherwise reported as null).
-MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.19", "workload": "c2",
-                           "bytes": 274.4e6,
+MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.20", "workload": "c2",
+                           "bytes": 275.4e6,
                            "source": "profiles/hbm_traffic_gather_scatter_32cubed_fp64.md"}
 
 

@@ -236,6 +236,7 @@ struct ecpic_sim {
   double* Uhalf;
   int* gwork;  // gather work list: [count, indices of blocks whose box missed the LDS tile]
   int* sboxes;  // node boxes of the scatter's chunks, found in a step's first pass
+  int* gboxes;  // node boxes of the gather's blocks, likewise
   double2* tw[3];
   Scratch sc;
   double* host = nullptr;  // pinned read-back
@@ -335,6 +336,7 @@ void carve(ecpic_sim* S, char* state, char* ws, size_t* state_bytes, size_t* ws_
   for (int a = 0; a < 3; ++a) S->tw[a] = w.take<double2>(S->G.n[a] / 2);
   S->gwork = w.take<int>(particle_blocks(np) + 1);
   S->sboxes = w.take<int>((size_t)kBoxInts * std::max<int64_t>(scatter_blocks(np, 2048), 1));
+  S->gboxes = w.take<int>((size_t)kBoxInts * std::max<int64_t>(particle_blocks(np), 1));
   // the plain iteration's next iterate is the gather's output, so the gather
   // (and the step's set-up) can hand the scatter vbar^p directly
   S->vbar = S->cfg.anderson_depth == 0 ? w.take<double>(n3) : nullptr;
@@ -757,7 +759,8 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     }
     if (prof_g) HIPCHK(hipEventRecord(S->ev[2], s));
     on_store(S, [&](auto& st, auto&) {  // v^{n+1,p+1}
-      launch_gather_push(s, r, P, st, S->vit, S->vnew, S->vbar, S->gbuf, S->gwork, S->sc, prev);
+      launch_gather_push(s, r, P, st, S->vit, S->vnew, S->vbar, S->gbuf, S->gwork, S->sc, prev,
+                         ChunkBoxes{S->gboxes, p >= 1});
     });
     if (prof_g) HIPCHK(hipEventRecord(S->ev[3], s));
     AndersonVecs av{};
@@ -1443,6 +1446,6 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.19"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.20"; }
 
 }  // extern "C"

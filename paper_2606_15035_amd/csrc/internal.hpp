@@ -183,11 +183,14 @@ struct AndersonPrev {
 // kernel lists the blocks whose node box missed the LDS tile, the second
 // kernel runs them from global memory; the per-pass finishing kernel resets
 // work[0].  vbar_out (nullable): (vnew + v^n) / 2, the vbar of a next pass
-// whose iterate is vnew
+// whose iterate is vnew.  bx: node boxes of the blocks of 256 particles, as
+// for the scatter's chunks; with reuse, a block one of whose orbits leaves
+// its stored box finds its box again and stores it.
 template <class PS>
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
                         const double* vit, double* vnew, double* vbar_out, const double* gbuf,
-                        int* work, Scratch sc, AndersonPrev prev = AndersonPrev{});
+                        int* work, Scratch sc, AndersonPrev prev = AndersonPrev{},
+                        ChunkBoxes bx = {});
 template <class PS>
 void launch_sweep(hipStream_t s, int r, const StepParams& P, const PS& st, const double* vit,
                   const double* gbuf, const double* Uhalf, Scratch sc);

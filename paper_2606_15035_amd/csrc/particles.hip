@@ -967,7 +967,10 @@ __device__ __forceinline__ void gather_push_one(const StepParams& P, const Acc& 
 // that box into LDS, and
 // every stencil read of the node loop then comes from LDS; a block whose box
 // does not fit the tile appends its index to a work list (work[0] = count,
-// work[1..] = block indices).  TILED = false: the blocks on that list (all
+// work[1..] = block indices).  After the first Picard pass of a step the
+// block takes the box it stored in an earlier pass and starts copying at
+// once; if one of its orbits has moved out of that box (by the margin test
+// above) it finds and stores the box again, and copies again.  TILED = false: the blocks on that list (all
 // blocks when work is null) read the gather buffer in global memory, a small
 // grid looping over the list.  Two kernels keep each one's register budget.
 constexpr int kGatherTileNodes = 512;
@@ -981,7 +984,8 @@ __device__ __forceinline__ void gather_block(const StepParams& P, const PS& st,
                                              double* __restrict__ vnew,
                                              double* __restrict__ vbar_out, const AosFields& F,
                                              int* __restrict__ work, const Scratch& sc,
-                                             const AndersonPrev& prev, int bid) {
+                                             const AndersonPrev& prev, int bid,
+                                             const ChunkBoxes& bx) {
   constexpr int W = R + 1;
   const int64_t i = (int64_t)bid * kBlock + threadIdx.x;
   const bool active = i < P.np;
@@ -1007,6 +1011,7 @@ __device__ __forceinline__ void gather_block(const StepParams& P, const PS& st,
   if constexpr (TILED) {
     __shared__ double2 tile2[kGatherTileNodes * kGbufStride / 2];
     __shared__ int s_ref[3];
+    __shared__ int s_out[kBlock / kWave];
     int lo[3] = {0, 0, 0}, span[3] = {0, 0, 0};
     if (active) {
 #pragma unroll
@@ -1017,51 +1022,112 @@ __device__ __forceinline__ void gather_block(const StepParams& P, const PS& st,
                   Spline<R>::first_off + W - lo[a];
       }
     }
-    if (threadIdx.x == 0)
+    // the block's node box: reference node sref, origin tlo relative to it and
+    // extents dim, per axis (dim[0] < 0: the box overflows the tile)
+    int sref[3], shift[3], tlo[3], dim[3];
+    auto uniform = [&]() {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) s_ref[a] = lo[a];
-    __syncthreads();
-    int shift[3], tlo[3], dim[3], mv[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int raw = lo[a] - s_ref[a];
-      const int rel = min_image(raw, P.G.n[a]);
-      shift[a] = rel - raw;
-      mv[a] = active ? rel : 0x3fffffff;
-      mv[3 + a] = active ? -(rel + span[a]) : 0x3fffffff;
-    }
-    block_min_ints<6>(mv);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      tlo[a] = mv[a];
-      dim[a] = -mv[3 + a] - tlo[a] + 1;
-    }
-    // block-uniform; each extent is bounded first so that the product cannot overflow
-    const bool fits = dim[0] <= kGatherTileNodes && dim[1] <= kGatherTileNodes &&
-                      dim[2] <= kGatherTileNodes;
-    const int64_t vol = fits ? (int64_t)dim[0] * dim[1] * dim[2] : kGatherTileNodes + 1;
-    if (vol > kGatherTileNodes) {  // leave the block to the global kernel
+      for (int a = 0; a < 3; ++a) {
+        sref[a] = __builtin_amdgcn_readfirstlane(sref[a]);
+        tlo[a] = __builtin_amdgcn_readfirstlane(tlo[a]);
+        dim[a] = __builtin_amdgcn_readfirstlane(dim[a]);
+      }
+    };
+    auto to_global_kernel = [&]() {
       if (threadIdx.x == 0) work[1 + atomicAdd(work, 1)] = bid;
-      return;
+    };
+    auto fill_tile = [&]() {
+      const int nt2 = dim[0] * dim[1] * dim[2] * (kGbufStride / 2);
+      const double2* g2 = reinterpret_cast<const double2*>(F.g);
+      const float inv_d1 = 1.0f / (float)dim[1], inv_d2 = 1.0f / (float)dim[2];
+      for (int t = threadIdx.x; t < nt2; t += kBlock) {
+        const int nd = t / (kGbufStride / 2), part = t % (kGbufStride / 2);
+        const int q = div_small(nd, inv_d2), cx = div_small(q, inv_d1);
+        const int cz = nd - q * dim[2], cy = q - cx * dim[1];
+        const int64_t g = node_index(P.G, sref[0] + tlo[0] + cx, sref[1] + tlo[1] + cy,
+                                     sref[2] + tlo[2] + cz);
+        tile2[t] = g2[g * (kGbufStride / 2) + part];
+      }
+    };
+    bool find_box = true;
+    if (bx.reuse) {  // the box this block found in an earlier pass of the step
+      const int* b = bx.box + (int64_t)bid * kBoxInts;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sref[a] = b[a];
+        tlo[a] = b[3 + a];
+        dim[a] = b[6 + a];
+      }
+      uniform();
+      if (dim[0] < 0) {
+        to_global_kernel();
+        return;
+      }
+      bool outside = false;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int raw = lo[a] - sref[a];
+        const int rel = min_image(raw, P.G.n[a]);
+        shift[a] = rel - raw;
+        outside = outside || (active && (rel < tlo[a] || rel + span[a] > tlo[a] + dim[a] - 1));
+      }
+      fill_tile();  // the loads start before the vote below is known
+      const bool wave_out = __ballot(outside) != 0ull;  // all lanes take part
+      if (threadIdx.x % kWave == 0) s_out[threadIdx.x / kWave] = wave_out;
+      __syncthreads();
+      find_box = false;
+#pragma unroll
+      for (int w = 0; w < kBlock / kWave; ++w) find_box = find_box || s_out[w] != 0;
     }
-    const int nt2 = (int)vol * (kGbufStride / 2);
-    const double2* g2 = reinterpret_cast<const double2*>(F.g);
-    const float inv_d1 = 1.0f / (float)dim[1], inv_d2 = 1.0f / (float)dim[2];
-    for (int t = threadIdx.x; t < nt2; t += kBlock) {
-      const int nd = t / (kGbufStride / 2), part = t % (kGbufStride / 2);
-      const int q = div_small(nd, inv_d2), cx = div_small(q, inv_d1);
-      const int cz = nd - q * dim[2], cy = q - cx * dim[1];
-      const int64_t g = node_index(P.G, s_ref[0] + tlo[0] + cx, s_ref[1] + tlo[1] + cy,
-                                   s_ref[2] + tlo[2] + cz);
-      tile2[t] = g2[g * (kGbufStride / 2) + part];
+    if (find_box) {  // first pass of the step, or an orbit left the stored box
+      if (threadIdx.x == 0)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) s_ref[a] = lo[a];
+      __syncthreads();
+      int mv[6];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        sref[a] = s_ref[a];
+        const int raw = lo[a] - sref[a];
+        const int rel = min_image(raw, P.G.n[a]);
+        shift[a] = rel - raw;
+        mv[a] = active ? rel : 0x3fffffff;
+        mv[3 + a] = active ? -(rel + span[a]) : 0x3fffffff;
+      }
+      block_min_ints<6>(mv);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        tlo[a] = mv[a];
+        dim[a] = -mv[3 + a] - tlo[a] + 1;
+      }
+      // each extent is bounded first so that the product cannot overflow
+      const bool fits = dim[0] <= kGatherTileNodes && dim[1] <= kGatherTileNodes &&
+                        dim[2] <= kGatherTileNodes &&
+                        (int64_t)dim[0] * dim[1] * dim[2] <= kGatherTileNodes;
+      if (!fits) dim[0] = -1;
+      uniform();
+      if (bx.box && threadIdx.x == 0) {
+        int* b = bx.box + (int64_t)bid * kBoxInts;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          b[a] = sref[a];
+          b[3 + a] = tlo[a];
+          b[6 + a] = dim[a];
+        }
+      }
+      if (dim[0] < 0) {
+        to_global_kernel();
+        return;
+      }
+      fill_tile();
+      __syncthreads();
     }
-    __syncthreads();
     if (active) {
       TileGather acc;
       acc.t = (lds_cdouble*)(reinterpret_cast<double*>(tile2));
-      acc.ox = shift[0] - s_ref[0] - tlo[0];
-      acc.oy = shift[1] - s_ref[1] - tlo[1];
-      acc.oz = shift[2] - s_ref[2] - tlo[2];
+      acc.ox = shift[0] - sref[0] - tlo[0];
+      acc.oy = shift[1] - sref[1] - tlo[1];
+      acc.oz = shift[2] - sref[2] - tlo[2];
       acc.dy = dim[1];
       acc.dz = dim[2];
       gather_push_one<R, SPLIT>(P, acc, st, i, x0, d, vb, qi, mi, vn, npieces[0], bad);
@@ -1134,12 +1200,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
                                                        double* __restrict__ vnew,
                                                        double* __restrict__ vbar_out, AosFields F,
                                                        int* __restrict__ work, Scratch sc,
-                                                       AndersonPrev prev) {
+                                                       AndersonPrev prev, ChunkBoxes bx) {
   if (TILED || !work) {
     late_reduce_init<4>();
     late_reduce_init<2>();
     if (!TILED) __syncthreads();  // the tiled path has a barrier before its first use
-    gather_block<R, TILED, PS, SPLIT>(P, st, vit, vnew, vbar_out, F, work, sc, prev, blockIdx.x);
+    gather_block<R, TILED, PS, SPLIT>(P, st, vit, vnew, vbar_out, F, work, sc, prev, blockIdx.x,
+                                      bx);
     return;
   }
   const int count = work[0];  // written by the tiled kernel (previous launch)
@@ -1148,7 +1215,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     late_reduce_init<4>();
     late_reduce_init<2>();
     __syncthreads();
-    gather_block<R, TILED, PS, SPLIT>(P, st, vit, vnew, vbar_out, F, work, sc, prev, work[1 + j]);
+    gather_block<R, TILED, PS, SPLIT>(P, st, vit, vnew, vbar_out, F, work, sc, prev, work[1 + j],
+                                      ChunkBoxes{});
   }
 }
 
@@ -1483,16 +1551,16 @@ void launch_scatter(hipStream_t s, int r, const StepParams& P, const PS& st, con
 template <class PS>
 void launch_gather_push(hipStream_t s, int r, const StepParams& P, const PS& st,
                         const double* vit, double* vnew, double* vbar_out, const double* gbuf,
-                        int* work, Scratch sc, AndersonPrev prev) {
+                        int* work, Scratch sc, AndersonPrev prev, ChunkBoxes bx) {
   if (P.np <= 0) return;
   AosFields F{gbuf};
   const unsigned nb = blocks_for(P.np);
   const unsigned ng = work ? std::min<unsigned>(nb, kGatherListGrid) : nb;
 #define ECPIC_GATHER_PAIR(R_, SPLIT_)                                                          \
   k_gather_push<R_, true, PS, SPLIT_><<<nb, kBlock, 0, s>>>(P, st, vit, vnew, vbar_out, F,    \
-                                                             work, sc, prev);                  \
+                                                             work, sc, prev, bx);              \
   k_gather_push<R_, false, PS, SPLIT_><<<ng, kBlock, 0, s>>>(P, st, vit, vnew, vbar_out, F,   \
-                                                              work, sc, prev)
+                                                              work, sc, prev, ChunkBoxes{})
   if constexpr (!PS::kMixed) {
     if (!P.split) {
       by_degree(r, [&](auto R) { ECPIC_GATHER_PAIR(R.value, false); });
@@ -1566,7 +1634,7 @@ void launch_fixed_current(hipStream_t s, int64_t n, unsigned long long* Jfix, do
                                    const double*, CurrentOut, Scratch, ChunkBoxes);              \
   template void launch_gather_push<PS>(hipStream_t, int, const StepParams&, const PS&,           \
                                        const double*, double*, double*, const double*, int*,     \
-                                       Scratch, AndersonPrev);                                   \
+                                       Scratch, AndersonPrev, ChunkBoxes);                       \
   template void launch_sweep<PS>(hipStream_t, int, const StepParams&, const PS&, const double*,  \
                                  const double*, const double*, Scratch);                         \
   template void launch_finalize<PS>(hipStream_t, const StepParams&, const PS&, const double*,     \
