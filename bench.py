@@ -82,8 +82,10 @@ def gather_bytes_per_push(mixed: bool = False) -> float:
 # FP64 workload: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the
 # same counters read for a streaming kernel of known size (k_finalize: fetch
 # 2.00 x, write 1.00 x).  A property of the kernel: valid for the library
-# version it was measured on only (otherwise reported as null).
-MEASURED_GATHER_TRAFFIC = {"version": "ecpic-gfx950 0.20", "workload": "c2",
+# versions whose particle kernels are those it was measured on (0.21 only
+# added the device microbenchmarks), otherwise reported as null.
+MEASURED_GATHER_TRAFFIC = {"versions": ("ecpic-gfx950 0.20", "ecpic-gfx950 0.21"),
+                           "measured_on": "ecpic-gfx950 0.20", "workload": "c2",
                            "bytes": 275.4e6,
                            "source": "profiles/hbm_traffic_gather_scatter_32cubed_fp64.md"}
 
@@ -324,9 +326,18 @@ def main():
     roofline["kernel"] = "orbit gather + push (k_gather_push<2, true>)"
     roofline["library"] = version
     mt = MEASURED_GATHER_TRAFFIC
-    roofline["traffic"] = (mt["bytes"] if mt["version"] == version and mt["workload"] == args.workload
+    roofline["traffic"] = (mt["bytes"] if version in mt["versions"] and mt["workload"] == args.workload
                            else None)
-    roofline["traffic_source"] = f"{mt['source']} ({mt['version']}; not measured in this run)"
+    roofline["traffic_source"] = f"{mt['source']} ({mt['measured_on']}; not measured in this run)"
+    # the device's own FP64 FMA and streaming rates, beside the published peaks
+    peaks = E.measure_peaks()
+    peaks["source"] = "ecpic_measure_peaks: FMA-chain kernel and streaming copy, best of 5"
+
+    def against_measured(r):
+        r["measured_peak"] = peaks
+        r["frac_of_measured_fp64"] = r["achieved"] / peaks["fp64_tflops"]
+        r["hbm_frac_of_measured"] = r["hbm_algorithmic_GBs"] / peaks["hbm_GBs"]
+    against_measured(roofline)
 
     out = {
         "metric": METRIC,
@@ -370,6 +381,7 @@ def main():
         wl4 = W.two_stream("c4")
         m4, _ = run_workload(E, wl4, E.MIXED, 5, 3, roofline=True)
         m4["roofline"]["kernel"] = "orbit gather + push (k_gather_push<2, true>, mixed store)"
+        against_measured(m4["roofline"])
         m4["workload"] = wl4.description
         m4["particles"] = wl4.np
         mixed["c4"] = m4

@@ -349,6 +349,24 @@ ecpic_status ecpic_adjoint_step_noalloc(ecpic_sim* sim, const double* x, const d
    ecpic_get_state; the psi and rho rows are zero). */
 ecpic_status ecpic_field_energy_grad(ecpic_sim* sim, double* lF);
 
+/* Measured peaks of the current device, the rates that the particle kernels'
+   roofline is stated against beside the published ones (not a step of the
+   method).  No simulation object.
+     buffer, bytes  caller-owned device memory of at least 64 MiB, contents
+                    overwritten (its first half is copied into its second;
+                    give several GiB so that the copy exceeds the caches)
+     repeats        timed launches per figure (>= 1), after one untimed
+     hip_stream     a hipStream_t or NULL; synchronised
+     fp64_tflops    out: FP64 TFLOP/s (2 per FMA) of a kernel whose every lane
+                    runs 8 independent FMA chains on registers, 32 workgroups
+                    of 256 lanes per compute unit; the best launch
+     hbm_gbs        out: bytes read plus bytes written per second (1e9 B/s)
+                    of a 16-byte-per-lane streaming copy; the best launch
+   Errors: ECPIC_EINVAL for a null pointer, bytes below 64 MiB or repeats
+   below 1; ECPIC_EDEVICE on a HIP failure. */
+ecpic_status ecpic_measure_peaks(void* buffer, size_t bytes, int32_t repeats, void* hip_stream,
+                                 double* fp64_tflops, double* hbm_gbs);
+
 /* Message for the last non-OK status of this thread ("" if none). */
 const char* ecpic_last_error(void);
 

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libecpic.so")
-SOURCES = ["api.hip", "particles.hip", "mesh.hip", "sort.hip", "adjoint.hip", "anderson.hip"]
+SOURCES = ["api.hip", "particles.hip", "mesh.hip", "sort.hip", "adjoint.hip", "anderson.hip",
+           "measure.hip"]
 ARCH = os.environ.get("ECPIC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -4,6 +4,7 @@
 // gather + push, then a read-back of the two fixed-point errors).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -1446,6 +1447,78 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.20"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.21"; }
+
+}  // extern "C"
+
+namespace {
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// smallest elapsed time (ms) of `repeats` launches of f on s, after one
+// untimed launch
+template <class F>
+ecpic_status best_launch_ms(hipStream_t s, const EventPair& ev, int repeats, F&& f,
+                            float* best) {
+  f();
+  HIPCHK(hipGetLastError());
+  *best = INFINITY;
+  for (int k = 0; k < repeats; ++k) {
+    HIPCHK(hipEventRecord(ev.a, s));
+    f();
+    HIPCHK(hipEventRecord(ev.b, s));
+    HIPCHK(hipEventSynchronize(ev.b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
+    *best = std::min(*best, ms);
+  }
+  HIPCHK(hipGetLastError());
+  return ECPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ecpic_status ecpic_measure_peaks(void* buffer, size_t bytes, int32_t repeats, void* hip_stream,
+                                 double* fp64_tflops, double* hbm_gbs) {
+  if (!buffer || !fp64_tflops || !hbm_gbs) return fail(ECPIC_EINVAL, "null argument");
+  if (bytes < ((size_t)64 << 20))
+    return fail(ECPIC_EINVAL, "the copy needs a buffer of at least 64 MiB (%zu bytes given)",
+                bytes);
+  if (repeats < 1) return fail(ECPIC_EINVAL, "repeats must be at least 1");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  EventPair ev;
+  HIPCHK(hipEventCreate(&ev.a));
+  HIPCHK(hipEventCreate(&ev.b));
+  // 32 workgroups of 256 lanes per compute unit, several rounds of resident
+  // waves (with one round, 8 per SIMD, uneven placement cost a fifth)
+  const int fma_blocks = 32 * std::max(cus, 1);
+  float ms = 0.f;
+  ecpic_status st = best_launch_ms(
+      s, ev, repeats, [&] { launch_fma_peak(s, fma_blocks, static_cast<double*>(buffer)); }, &ms);
+  if (st != ECPIC_OK) return st;
+  *fp64_tflops = fma_peak_flops(fma_blocks) / (ms * 1e-3) / 1e12;
+  // the first half of the buffer copied into the second, both 256-byte aligned
+  const size_t half = (bytes / 2) & ~(size_t)255;
+  const char* src = static_cast<const char*>(buffer);
+  char* dst = static_cast<char*>(buffer) + half;
+  const int copy_blocks = 256 * std::max(cus, 1);
+  st = best_launch_ms(
+      s, ev, repeats,
+      [&] { launch_stream_copy(s, copy_blocks, src, dst, (int64_t)(half / 16)); }, &ms);
+  if (st != ECPIC_OK) return st;
+  *hbm_gbs = 2.0 * (double)half / (ms * 1e-3) / 1e9;
+  return ECPIC_OK;
+}
 
 }  // extern "C"

@@ -347,4 +347,12 @@ void launch_energy_adjoint(hipStream_t s, const Grid& G, const double2* lEB, dou
 
 constexpr int kGbufStride = 10;  // [gphi x,y,z | A^n x,y,z | A^{n+1} x,y,z | pad]
 
+// ---- device microbenchmarks (measure.hip) ----
+// FP64 flops of one launch of launch_fma_peak with `blocks` workgroups;
+// out: one double per workgroup, never written in practice
+double fma_peak_flops(int blocks);
+void launch_fma_peak(hipStream_t s, int blocks, double* out);
+// copy of n16 16-byte elements from src to dst (16-byte aligned, disjoint)
+void launch_stream_copy(hipStream_t s, int blocks, const void* src, void* dst, int64_t n16);
+
 }  // namespace ecpic

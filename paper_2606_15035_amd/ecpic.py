@@ -111,6 +111,8 @@ def lib():
         L.ecpic_checkpoint_save.argtypes = [P, P]
         L.ecpic_checkpoint_restore.argtypes = [P, P]
         L.ecpic_field_energy_grad.argtypes = [P, D]
+        L.ecpic_measure_peaks.argtypes = [P, C.c_size_t, C.c_int32, P, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
         L.ecpic_last_error.restype = C.c_char_p
         L.ecpic_version.restype = C.c_char_p
         for name in ("ecpic_state_bytes", "ecpic_create", "ecpic_init_particles",
@@ -121,7 +123,8 @@ def lib():
                      "ecpic_get_profile", "ecpic_adjoint_workspace_bytes",
                      "ecpic_adjoint_step", "ecpic_adjoint_step_noalloc",
                      "ecpic_checkpoint_bytes", "ecpic_checkpoint_save",
-                     "ecpic_checkpoint_restore", "ecpic_field_energy_grad"):
+                     "ecpic_checkpoint_restore", "ecpic_field_energy_grad",
+                     "ecpic_measure_peaks"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -393,6 +396,19 @@ def orbit_gather(cfg: Config, x0, d, gphi, U, A0, A1, device="cuda"):
     return {"gphibar": o[:, 0:3], "Ubar": o[:, 3:6], "D": o[:, 6:15].reshape(n, 3, 3),
             "A1_end": o[:, 15:18], "A0_start": o[:, 18:21], "pou": o[:, 21],
             "npieces": o[:, 22].astype(int)}
+
+
+def measure_peaks(nbytes=4 << 30, repeats=5):
+    """Measured FP64 TFLOP/s and HBM GB/s of the current device
+    (ecpic_measure_peaks) over a device buffer of nbytes."""
+    torch = _torch()
+    buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    f, h = C.c_double(), C.c_double()
+    s = torch.cuda.current_stream()
+    _check(lib().ecpic_measure_peaks(C.c_void_p(buf.data_ptr()), int(nbytes), int(repeats),
+                                     C.c_void_p(s.cuda_stream), C.byref(f), C.byref(h)))
+    del buf
+    return {"fp64_tflops": f.value, "hbm_GBs": h.value}
 
 
 def orbit_deposit(cfg: Config, x0, d, qv, device="cuda"):
