@@ -244,7 +244,12 @@ struct ecpic_sim {
   // kernel timing
   int profiling = 0;  // 0 off, 1 every phase, 2 the gather phase only
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_read = nullptr;  // after each pass's read-back of its errors
   ecpic_profile prof{};
+  // Picard passes of the last steps (a ring): the passes every one of them
+  // ran are queued ahead of the previous pass's errors
+  int pass_hist[8] = {};
+  int npass_hist = 0;
   // energy bookkeeping
   double K = 0.0, W = 0.0;
   ecpic_energy en{};
@@ -376,6 +381,33 @@ RealIO soa_io(double* base, int64_t nc, int nb) {
 }
 
 const double2* const* twp(ecpic_sim* S) { return S->tw; }
+
+// the read-back of red[first .. first + count) into the pinned host buffer,
+// queued with an event after it; wait_read() waits for that event only, so
+// work queued behind it keeps the GPU busy while the host looks at the values
+ecpic_status queue_read(ecpic_sim* S, int first, int count) {
+  if (!S->ev_read) HIPCHK(hipEventCreateWithFlags(&S->ev_read, hipEventDisableTiming));
+  HIPCHK(hipMemcpyAsync(S->host, S->sc.red + first, sizeof(double) * count, hipMemcpyDeviceToHost,
+                        S->stream));
+  HIPCHK(hipEventRecord(S->ev_read, S->stream));
+  return ECPIC_OK;
+}
+
+ecpic_status wait_read(ecpic_sim* S) {
+  HIPCHK(hipEventSynchronize(S->ev_read));
+  return ECPIC_OK;
+}
+
+// Number of Picard passes that every one of the last (up to 8) steps ran;
+// 2 without history (a step runs at least passes 0 and 1 unless p_max = 0)
+int sure_passes(const ecpic_sim* S) {
+  int m = 2;
+  if (S->npass_hist > 0) {
+    m = S->pass_hist[0];
+    for (int k = 1; k < std::min(S->npass_hist, 8); ++k) m = std::min(m, S->pass_hist[k]);
+  }
+  return std::max(m, 2);
+}
 
 ecpic_status sync_read(ecpic_sim* S, int first, int count) {
   HIPCHK(hipMemcpyAsync(S->host, S->sc.red + first, sizeof(double) * count, hipMemcpyDeviceToHost,
@@ -560,6 +592,7 @@ void ecpic_destroy(ecpic_sim* S) {
   if (!S) return;
   for (auto& e : S->ev)
     if (e) (void)hipEventDestroy(e);
+  if (S->ev_read) (void)hipEventDestroy(S->ev_read);
   if (S->host) (void)hipHostFree(S->host);
   delete S;
 }
@@ -719,6 +752,23 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   S->jclean = false;
   bool converged = false;
   double err_v = 0.0, err_J = INFINITY;
+  // J^{n+1/2,q} of iterate vit_q into Jq (the mixed form through the
+  // fixed-point sums)
+  auto launch_current = [&](const double* vit_q, double* Jq, int q) {
+    on_store(S, [&](auto& st, auto&) {
+      CurrentOut o = cout;
+      o.J = Jq;
+      launch_scatter(s, r, P, st, vit_q, S->vbar, o, S->sc, ChunkBoxes{S->sboxes, q >= 1});
+    });
+    if (S->mixed()) launch_fixed_current(s, 3 * nc, S->Jfix, Jq, fix_unit);
+  };
+  // In the plain iteration the next pass's iterate is this pass's output and
+  // its vbar has been written by this pass's gather, so the next pass's
+  // scatter can be queued before this pass's errors are read (the GPU then
+  // does not wait for the host's round trip).  Only passes that the step
+  // will run are queued so: those every recent step ran.
+  const int sure = sure_passes(S);
+  bool ahead = false;  // this pass's current was queued by the previous pass
   for (p = 0; p <= S->cfg.picard_max; ++p) {
     S->vit = wl[0];
     S->vnew = pool_free(S, wl, nw, gl, std::min(ng, am));
@@ -738,12 +788,8 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     // fixed-point conversion overwrites it (mixed); the atomic slots of the
     // pass were cleared when the previous pass's finishing kernel folded them
     if (prof) HIPCHK(hipEventRecord(S->ev[0], s));
-    on_store(S, [&](auto& st, auto&) {  // J^{n+1/2,p}
-      CurrentOut o = cout;
-      o.J = J;
-      launch_scatter(s, r, P, st, S->vit, S->vbar, o, S->sc, ChunkBoxes{S->sboxes, p >= 1});
-    });
-    if (S->mixed()) launch_fixed_current(s, 3 * nc, S->Jfix, J, fix_unit);
+    if (!ahead) launch_current(S->vit, J, p);  // J^{n+1/2,p}
+    ahead = false;
     if (prof) HIPCHK(hipEventRecord(S->ev[1], s));
     // transform of J (max|J - J_prev| folded into S_DJMAX; J_prev, the next
     // pass's J, cleared in FP64), continuity + CN, inverse transform of
@@ -784,7 +830,15 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
       launch_finish(s, S->sc, jobs, S->np > 0 ? (mk > 0 ? 7 : 6) : 2, S->gwork);
     }
     HIPCHK(hipGetLastError());
-    ecpic_status st = sync_read(S, S_DVMAX, (S_AA - S_DVMAX) + anderson_sums(mk));
+    ecpic_status st = queue_read(S, S_DVMAX, (S_AA - S_DVMAX) + anderson_sums(mk));
+    if (st != ECPIC_OK) return st;
+    if (am == 0 && !prof && p + 1 <= S->cfg.picard_max && p + 1 < sure) {
+      // w_{p+1} = g_p; Jprev, read by this pass's transform, is the next
+      // pass's J (cleared by that transform in FP64, overwritten in mixed)
+      launch_current(gl[0], Jprev, p + 1);
+      ahead = true;
+    }
+    st = wait_read(S);
     if (st != ECPIC_OK) return st;
     if (prof) {
       float t01 = 0.f, t12 = 0.f;
@@ -831,7 +885,11 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
     push_front(wl, nw, am + 1, wnext);
   }
   if (p > S->cfg.picard_max) p = S->cfg.picard_max;
-  S->jclean = true;
+  // a current queued ahead for a pass the step did not run is left in the
+  // buffer the next step deposits into; that step clears it first
+  S->jclean = !ahead;
+  S->pass_hist[S->npass_hist % 8] = p + 1;
+  S->npass_hist += 1;
 
   // consistency sweep of the accepted iterate (its orbit, current and fields)
   if (prof) HIPCHK(hipEventRecord(S->ev[0], s));
@@ -1447,7 +1505,7 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.21"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.22"; }
 
 }  // extern "C"
 

@@ -386,6 +386,38 @@ def test_step_parity_tolerance_mode_and_energy(r):
         assert eg["gauge_max"] < 1e-12 and eg["gauss_max"] < 1e-10
 
 
+def test_step_that_converges_before_a_queued_pass():
+    """In the plain iteration the scatter of pass q is queued before pass
+    q - 1's errors are read when every recent step ran pass q.  Three steps
+    from a poor first guess (v^{n-1} = v^n + 0.3, so 2 v^n - v^{n-1} is off
+    by 0.3 in every component, more than a cell of orbit) need more passes
+    than the next ones, which start from the usual extrapolation: the first
+    of those that stops earlier than all steps before it queues the current
+    of a pass that is never run, and the step after it must clear that
+    buffer before it deposits (a stale current would put errors of order one
+    into it).  Both sides run the same sequence; states agree at 1e-12
+    wherever the pass counts agree (tolerance mode may stop one pass
+    apart)."""
+    wl = small_random(2, np_=9000, seed=31)
+    g, o = both(wl, tol=1e-11, pmax=30)
+    iters = []
+    for step in range(6):
+        if step < 3:
+            vprev = o.get_state()["v"] + 0.3
+            g.set_state(vprev=vprev)
+            o.set_state(None, None, vprev, None, None, wl.q, wl.m)
+        ig, io = g.picard_step(), o.step()
+        log(f"step {step}: passes gpu {ig['iters']} oracle {io['iters']}")
+        assert abs(ig["iters"] - io["iters"]) <= 1, (ig, io)
+        iters.append(ig["iters"])
+        if ig["iters"] == io["iters"]:
+            compare_states(wl, g, o, f"queued pass step {step}")
+        else:
+            compare_states(wl, g, o, f"queued pass step {step}", rtol=1e-9)
+    # a step with fewer passes than every step before it, followed by another
+    assert any(iters[k] < min(iters[:k]) for k in (3, 4)), iters
+
+
 def test_two_stream_16x4x4_tolerance_run():
     """The 16x4x4 two-stream workload (linear shape, tol 1e-12): 20 steps side by
     side; states agree while the instability is still linear."""
