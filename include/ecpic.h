@@ -25,8 +25,10 @@
  *     read-back.
  *   - All device work is enqueued on the HIP stream given to ecpic_create()
  *     (NULL = default stream).  Calls that return host data synchronise that
- *     stream; ecpic_picard_step() synchronises it once per Picard iteration to
- *     read the two fixed-point errors.
+ *     stream; ecpic_picard_step() waits once per Picard iteration for the
+ *     read-back of the two fixed-point errors (the next iteration's current
+ *     may already be running behind it) and synchronises the stream before it
+ *     returns.
  *   - Host arrays passed in are copied before the call returns; the library
  *     keeps no host pointer.
  *   - Array layouts.  Particle arrays are component-major (SoA): x[a*np + i].
