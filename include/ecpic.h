@@ -22,7 +22,8 @@
  *     frees device memory; the one device array it holds is the fixed
  *     workspace of ecpic_adjoint_step_noalloc(), loaded with its code.  It
  *     allocates a small pinned host buffer for the per-iteration convergence
- *     read-back.
+ *     read-back, and each simulation keeps up to two HIP graph executables
+ *     of its cell sort (runtime objects, released by ecpic_destroy()).
  *   - All device work is enqueued on the HIP stream given to ecpic_create()
  *     (NULL = default stream).  Calls that return host data synchronise that
  *     stream; ecpic_picard_step() waits once per Picard iteration for the

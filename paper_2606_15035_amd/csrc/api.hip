@@ -245,6 +245,14 @@ struct ecpic_sim {
   int profiling = 0;  // 0 off, 1 every phase, 2 the gather phase only
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_read = nullptr;  // after each pass's read-back of its errors
+  // the step's cell sort as a graph, one per arrangement of the two particle
+  // stores and id arrays (they swap at every sort): pointers it was captured
+  // with (cur, alt, id, id2, first guess, its vbar) and the executable
+  struct SortGraph {
+    const void* key[6] = {};
+    hipGraphExec_t exec = nullptr;
+  } sort_graph[2];
+  int next_sort_graph = 0;
   ecpic_profile prof{};
   // Picard passes of the last steps (a ring): the passes every one of them
   // ran are queued ahead of the previous pass's errors
@@ -395,6 +403,51 @@ ecpic_status queue_read(ecpic_sim* S, int first, int count) {
 
 ecpic_status wait_read(ecpic_sim* S) {
   HIPCHK(hipEventSynchronize(S->ev_read));
+  return ECPIC_OK;
+}
+
+const void* store_key(const Fp64Store& s) { return s.x; }
+const void* store_key(const MixedStore& s) { return s.cell; }
+
+// The step's cell sort (six small kernels, which would otherwise each wait
+// for the host's launch on an idle GPU) as one graph launch.  A graph keeps
+// the pointers it was captured with, so it is captured once per arrangement
+// of the stores, id arrays and first-guess buffers (two alternate), on a
+// private stream, and replayed on the simulation's stream; the host then
+// swaps the stores and ids as the sort itself does.
+template <class PS>
+ecpic_status sort_by_graph(ecpic_sim* S, PS& cur, PS& alt) {
+  const void* key[6] = {store_key(cur), store_key(alt), S->id, S->id2, S->vit, S->vbar};
+  ecpic_sim::SortGraph* g = nullptr;
+  for (auto& c : S->sort_graph)
+    if (c.exec && std::equal(key, key + 6, c.key)) g = &c;
+  if (!g) {
+    g = &S->sort_graph[S->next_sort_graph];
+    S->next_sort_graph ^= 1;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    g->exec = nullptr;
+    hipStream_t cs = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    PS c = cur, a = alt;
+    int *i1 = S->id, *i2 = S->id2;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      launch_sort(cs, S->G, S->np, c, a, i1, i2, S->sb, S->vit, S->vbar);
+      e = hipStreamEndCapture(cs, &graph);
+    }
+    (void)hipStreamDestroy(cs);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g->exec = nullptr;
+      return fail(ECPIC_EDEVICE, "capturing the cell sort as a graph: %s", hipGetErrorString(e));
+    }
+    std::copy(key, key + 6, g->key);
+  }
+  HIPCHK(hipGraphLaunch(g->exec, S->stream));
+  std::swap(cur, alt);
+  std::swap(S->id, S->id2);
   return ECPIC_OK;
 }
 
@@ -593,6 +646,8 @@ void ecpic_destroy(ecpic_sim* S) {
   for (auto& e : S->ev)
     if (e) (void)hipEventDestroy(e);
   if (S->ev_read) (void)hipEventDestroy(S->ev_read);
+  for (auto& g : S->sort_graph)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (S->host) (void)hipHostFree(S->host);
   delete S;
 }
@@ -737,11 +792,11 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   // cell order of x^n, and v^{n+1,0} = 2 v^n - v^{n-1} (written by the sort's
   // permutation when the step sorts)
   const int sort_every = S->cfg.sort_interval <= 0 ? 1 : S->cfg.sort_interval;
-  if (S->cfg.sort_interval >= 0 && (S->en.step % sort_every) == 0 && S->np > 0)
-    on_store(S, [&](auto& st, auto& alt) {
-      launch_sort(s, S->G, S->np, st, alt, S->id, S->id2, S->sb, S->vit, S->vbar);
-    });
-  else
+  if (S->cfg.sort_interval >= 0 && (S->en.step % sort_every) == 0 && S->np > 0) {
+    const ecpic_status st_sort =
+        on_store(S, [&](auto& st, auto& alt) { return sort_by_graph(S, st, alt); });
+    if (st_sort != ECPIC_OK) return st_sort;
+  } else
     on_store(S, [&](auto& st, auto&) { launch_extrapolate(s, S->np, st, S->vit, S->vbar); });
   const CurrentOut cout{nullptr, S->Jfix, S->fix_scale};
   const double fix_unit = S->q / S->G.dV / S->fix_scale;
@@ -1505,7 +1560,7 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.22"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.23"; }
 
 }  // extern "C"
 
