@@ -84,10 +84,11 @@ def gather_bytes_per_push(mixed: bool = False) -> float:
 # 2.00 x, write 1.00 x).  A property of the kernel: valid for the library
 # versions whose particle kernels are those it was measured on (0.21 added
 # the device microbenchmarks, 0.22 queues a pass's scatter ahead of the
-# previous pass's read-back, 0.23 launches the cell sort as a graph),
-# otherwise reported as null.
+# previous pass's read-back, 0.23 launches the cell sort as a graph, 0.24
+# changed an adjoint kernel only), otherwise reported as null.
 MEASURED_GATHER_TRAFFIC = {"versions": ("ecpic-gfx950 0.20", "ecpic-gfx950 0.21",
-                                        "ecpic-gfx950 0.22", "ecpic-gfx950 0.23"),
+                                        "ecpic-gfx950 0.22", "ecpic-gfx950 0.23",
+                                        "ecpic-gfx950 0.24"),
                            "measured_on": "ecpic-gfx950 0.20", "workload": "c2",
                            "bytes": 275.4e6,
                            "source": "profiles/hbm_traffic_gather_scatter_32cubed_fp64.md"}

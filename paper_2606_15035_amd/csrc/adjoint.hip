@@ -56,17 +56,21 @@ struct GlobalAdjSink {
 // The block's LDS tile over its chunk's node box (nine doubles per node);
 // o[] takes the particle's frame to the tile's.  A node outside the box
 // (not expected: the box has a node of margin per side) goes to global
-// memory.
+// memory.  The tile pointer carries the LDS address space, so the additions
+// are LDS atomics (through a plain pointer they compiled to flat atomics,
+// the slower path that serves either memory).
+typedef __attribute__((address_space(3))) double lds_double;
 struct TileAdjSink {
   GlobalAdjSink glob;
-  double* tile;
+  lds_double* tile;
   int o[3], dim[3];
   bool use;
   __device__ __forceinline__ void add(int comp, int ix, int iy, int iz, int64_t g,
                                       double v) const {
     const int tx = ix + o[0], ty = iy + o[1], tz = iz + o[2];
     if (use && tx >= 0 && ty >= 0 && tz >= 0 && tx < dim[0] && ty < dim[1] && tz < dim[2])
-      atomicAdd(&tile[9 * ((tx * dim[1] + ty) * dim[2] + tz) + comp], v);
+      __hip_atomic_fetch_add(&tile[9 * ((tx * dim[1] + ty) * dim[2] + tz) + comp], v,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     else
       glob.add(comp, ix, iy, iz, g, v);
   }
@@ -420,7 +424,8 @@ __global__ __launch_bounds__(kBlock) void k_push_adjoint_tiled(AdjParticleArgs P
   for (int k = 0; k < kPerThread; ++k) {
     const int64_t i = adj_chunk_particle(base, k);
     if (i >= P.np) break;
-    TileAdjSink sink{GlobalAdjSink{&P}, tile, {0, 0, 0}, {dim[0], dim[1], dim[2]}, use_tile};
+    TileAdjSink sink{GlobalAdjSink{&P}, (lds_double*)tile, {0, 0, 0}, {dim[0], dim[1], dim[2]},
+                     use_tile};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double x0 = P.x[a * P.np + i], d = P.dt * P.vb[a * P.np + i];

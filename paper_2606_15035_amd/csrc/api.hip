@@ -1560,7 +1560,7 @@ ecpic_status ecpic_field_energy_grad(ecpic_sim* S, double* lF) {
   return ECPIC_OK;
 }
 
-const char* ecpic_version(void) { return "ecpic-gfx950 0.23"; }
+const char* ecpic_version(void) { return "ecpic-gfx950 0.24"; }
 
 }  // extern "C"
 
