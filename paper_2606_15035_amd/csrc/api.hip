@@ -820,8 +820,10 @@ ecpic_status ecpic_picard_step(ecpic_sim* S, ecpic_step_info* info) {
   // In the plain iteration the next pass's iterate is this pass's output and
   // its vbar has been written by this pass's gather, so the next pass's
   // scatter can be queued before this pass's errors are read (the GPU then
-  // does not wait for the host's round trip).  Only passes that the step
-  // will run are queued so: those every recent step ran.
+  // does not wait for the host's round trip).  Only passes the step is
+  // expected to run are queued so: pass 1, which every step runs, and the
+  // passes every one of the last eight steps ran.  If the step stops before
+  // such a pass, its current stays in the buffer that the next step clears.
   const int sure = sure_passes(S);
   bool ahead = false;  // this pass's current was queued by the previous pass
   for (p = 0; p <= S->cfg.picard_max; ++p) {
