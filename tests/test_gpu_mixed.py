@@ -48,7 +48,8 @@ def small_random(r, seed):
                            drift=(0.03, -0.02, 0.01), seed=seed)
 
 
-@pytest.mark.parametrize("name,r,chunk", [("c3", 1, 0), ("random", 2, 0), ("random", 2, 2048)])
+@pytest.mark.parametrize("name,r,chunk", [("c3", 1, 0), ("random", 2, 0), ("random", 2, 2048),
+                                          ("random", 3, 0)])
 def test_mixed_step_matches_oracle(name, r, chunk):
     wl = W.two_stream("c3") if name == "c3" else small_random(r, seed=13)
     x, v = to_storage(wl, wl.x, wl.v)
