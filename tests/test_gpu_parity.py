@@ -423,26 +423,29 @@ def test_sorted_and_unsorted_runs_agree():
     replayed on the simulation's stream between the eagerly launched Picard
     passes (one graph per arrangement of the two particle stores, each
     replayed four times here).  A run that never sorts takes its first guess
-    from the extrapolation kernel instead; its steps agree with the sorted
-    run's to rounding (the particle order changes the order of the FP64
-    atomic additions only)."""
+    from the extrapolation kernel instead, and one that sorts every third
+    step mixes the two; their steps agree with the unsorted run's to
+    rounding (the particle order changes the order of the FP64 atomic
+    additions only)."""
     wl = small_random(2, np_=9000, seed=37)
     runs = {}
-    for si in (1, -1):
+    for si in (1, 3, -1):  # every step, every third step (graph and extrapolation), never
         g = E.Sim(gpu_cfg(wl, tol=0.0, pmax=2, sort_interval=si), wl.np)
         g.init_particles(wl.x, wl.v, wl.q, wl.m, wl.n0)
         runs[si] = g
     for step in range(8):
-        a, b = runs[1], runs[-1]
-        a.picard_step()
-        b.picard_step()
-        sa, sb = a.get_state(), b.get_state()
+        for g in runs.values():
+            g.picard_step()
+        sb = runs[-1].get_state()
         vs = np.abs(sb["v"]).max()
-        dv = np.abs(sa["v"] - sb["v"]).max() / vs
-        dx = np.abs(unwrap_delta(sa["x"], sb["x"], wl.L)).max() / (vs * wl.dt)
-        df = np.abs(sa["fields"] - sb["fields"]).max() / np.abs(sb["fields"]).max()
-        log(f"step {step}: sorted vs unsorted |dv| {dv:.1e} |dx| {dx:.1e} fields {df:.1e}")
-        assert dv < 1e-12 and dx < 1e-12 and df < 1e-12, (step, dv, dx, df)
+        for si in (1, 3):
+            sa = runs[si].get_state()
+            dv = np.abs(sa["v"] - sb["v"]).max() / vs
+            dx = np.abs(unwrap_delta(sa["x"], sb["x"], wl.L)).max() / (vs * wl.dt)
+            df = np.abs(sa["fields"] - sb["fields"]).max() / np.abs(sb["fields"]).max()
+            log(f"step {step}: sort interval {si} vs unsorted |dv| {dv:.1e} |dx| {dx:.1e} "
+                f"fields {df:.1e}")
+            assert dv < 1e-12 and dx < 1e-12 and df < 1e-12, (step, si, dv, dx, df)
 
 
 def test_two_stream_16x4x4_tolerance_run():
